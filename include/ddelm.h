@@ -1,0 +1,191 @@
+/*
+ * ddelm.h -- C ABI of the MI355X (gfx950) DDELM-NN library.
+ *
+ * DDELM-NN: domain decomposition of extreme learning machines with a coarse
+ * space and a theta-mixed Neumann-Neumann acceleration (Lee & Ryoo).  The
+ * calls follow the paper's statement of the problem:
+ *
+ *   ddelm_setup   partition of the domain (sec. 2.1), local networks with
+ *                 preset hidden parameters (sec. 2.2) and the collocation
+ *                 sets x_I, x_B, x_Gamma of every subdomain (sec. 2.2.1);
+ *   ddelm_factor  local feature matrices K_c^i, A_m^i, Kbar^i, Abar^i
+ *                 (sec. 2.2.1, 3.1, 3.2), their Householder QR, and the
+ *                 coarse Schur complement S_Pi with its Cholesky factor
+ *                 (sec. 3, "assemble S_Pi in full");
+ *   ddelm_solve   right-hand side f = [f(x_I); g(x_B); 0] (eq. ddelm),
+ *                 CG on mu_Delta for eq. nn-mixed, then
+ *                 [c; mu_Pi] = K~^+ (f~ - B~ mu_Delta) (eq. coarse_sol_2);
+ *   ddelm_evaluate  u(x) = NN^i(x) = sum_j c_j tanh(w_j . xi + b_j) on the
+ *                 owning subdomain.
+ *
+ * Conventions
+ *   - Two space dimensions.  Subdomain i = iy*nx + ix of a uniform nx x ny
+ *     partition of the box [lo, hi].
+ *   - Hidden weights act on local coordinates xi = (x - centre_i)/(h/2),
+ *     so xi ranges over [-1, 1]^2 on every subdomain.
+ *   - Every edge of every subdomain carries p points at parameters edge_s
+ *     (both ends included).  Edge points on the domain boundary, and the
+ *     extra parameters extra_s on boundary sides, are boundary points.
+ *     Subdomain corners inside the domain form Pi (coarse >= 1); the other
+ *     interface points form Delta.
+ *   - Global orders: Pi point at lattice vertex (jx, jy) has index
+ *     (jy-1)*(nx-1) + (jx-1).  Interior edges are numbered vertical first
+ *     (iy*(nx-1) + jx-1), then horizontal ((nx-1)*ny + (jy-1)*nx + ix);
+ *     Delta point k (1..p-2) of edge e has index e*(p-2) + k-1.  With
+ *     coarse == 0 the interior vertices are Delta points numbered after all
+ *     edge points, in the Pi order.
+ *   - Local row order of K_c^i: interior points (as given), boundary points
+ *     (sides bottom, right, top, left that lie on the domain boundary, each
+ *     by increasing coordinate, a shared corner listed once; then the extra
+ *     boundary points side by side), then Gamma: Pi^i then Delta^i, each by
+ *     global index.
+ *   - All array arguments are DEVICE pointers unless marked "host".  Arrays
+ *     are dense, row-major in the index order written, float64.
+ *   - Inputs are borrowed for the duration of the call; ddelm_setup copies
+ *     what it keeps.  Outputs are written into caller-owned buffers.  The
+ *     context owns its factors and workspaces until ddelm_destroy.
+ *   - Work is ordered on the stream given to ddelm_setup (a hipStream_t
+ *     passed as void*; NULL = the default stream).  Calls that return
+ *     statistics synchronise that stream.  A context is not thread-safe.
+ *   - Errors: a negative status is an error; outputs are then unspecified
+ *     and ddelm_last_error(ctx) describes it.  DDELM_WARN_NOCONV means CG hit
+ *     maxit; the best iterate is still written.
+ */
+#ifndef DDELM_H
+#define DDELM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddelm_ctx_s* ddelm_ctx;
+
+typedef enum {
+  DDELM_OK = 0,
+  DDELM_WARN_NOCONV = 1,
+  DDELM_E_ARG = -1,        /* invalid argument value */
+  DDELM_E_SHAPE = -2,      /* sizes inconsistent or beyond limits */
+  DDELM_E_STATE = -3,      /* call out of order (e.g. solve before factor) */
+  DDELM_E_HIP = -4,        /* HIP runtime error, or a device-side bounded wait expired */
+  DDELM_E_NOMEM = -5,      /* device allocation failed */
+  DDELM_E_CHOLESKY = -6,   /* S_Pi not positive definite */
+  DDELM_E_NONFINITE = -7   /* NaN/Inf met in CG */
+} ddelm_status;
+
+/* Problem description (sec. 2.1 partition, sec. 2.2 networks and points). */
+typedef struct {
+  int nx, ny;               /* subdomains per axis, >= 1 */
+  double lo[2], hi[2];      /* domain box, lo < hi */
+  int p;                    /* points per edge incl. both ends, 3 <= p <= 4096 */
+  const double* edge_s;     /* host [p]: 0 = s_0 < s_1 < ... < s_{p-1} = 1 */
+  int n_extra;              /* extra boundary points per boundary side, >= 0 */
+  const double* extra_s;    /* host [n_extra], each in (0,1); may be NULL if n_extra == 0 */
+  int n_int;                /* interior collocation points per subdomain, >= 1 */
+  const double* x_int;      /* device [N][n_int][2], global coordinates, inside the subdomain */
+  int M;                    /* neurons per subdomain, 1 <= M <= 1024, M <= rows of K_c^i */
+  const double* W;          /* device [N][M][2] hidden weights (local coordinates) */
+  const double* b;          /* device [N][M] hidden biases */
+} ddelm_problem;
+
+typedef struct {
+  double theta;             /* NN mixing weight of eq. nn-mixed, 0 <= theta <= 1 */
+  int coarse;               /* 0: no coarse space, K and A (vanilla DDELM);
+                               1: corners as Pi, K and A;
+                               2: corners as Pi, K_c and A_m (sec. 3.2; default) */
+  int precision;            /* 0: float64 throughout; 1: mixed (float32 local factors
+                               and matvecs, float64 coarse problem, dots and refinement) */
+  double tol;               /* CG stop: ||r_k|| <= tol ||b||, 0 < tol < 1 */
+  int maxit;                /* CG iteration cap (per refinement step), >= 1 */
+  int max_nrhs;             /* largest nrhs a solve may pass, 1..64 */
+  int cg_mode;              /* 0: auto; 1: one launch per CG phase; 2: one persistent
+                               cooperative launch per CG solve */
+  int refine_maxit;         /* mixed precision: outer refinement steps cap (>= 1) */
+  double refine_tol;        /* mixed precision: stop when the correction of mu is
+                               <= refine_tol relative to mu */
+  double inner_tol;         /* mixed precision: CG tolerance of each inner solve */
+} ddelm_options;
+
+typedef struct {
+  int iters;                /* CG iterations (sum over refinement steps, max over RHS) */
+  int refine_steps;         /* refinement steps taken (mixed precision), else 0 */
+  double rel_res;           /* final recurrence residual ||r||/||b||, max over RHS */
+  double ms_rhs;            /* wall time of the right-hand-side assembly */
+  double ms_cg;             /* wall time of the CG loop(s) */
+  double ms_recover;        /* wall time of recovery (and refinement residuals) */
+} ddelm_stats;
+
+typedef struct {
+  int N, M, n_pi, n_dl;     /* subdomains, neurons, #Pi, #Delta */
+  int n_int;                /* interior points per subdomain */
+  int max_m;                /* largest local row count */
+  long long sum_nB;         /* boundary points over all subdomains */
+  long long sum_nG;         /* local interface points over all subdomains */
+} ddelm_sizes;
+
+/* Default options: theta 0.999 (sec. 4.2), coarse 2, fp64, tol 1e-8,
+ * maxit 20000, max_nrhs 1, cg_mode auto, refine_maxit 10, refine_tol 1e-9,
+ * inner_tol 1e-6. */
+void ddelm_default_options(ddelm_options* opt);
+
+/* Validate, build the interface indexing on the host and allocate the
+ * context.  Errors: DDELM_E_ARG, DDELM_E_SHAPE, DDELM_E_NOMEM, DDELM_E_HIP. */
+ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob,
+                         const ddelm_options* opt, void* stream);
+
+/* Assemble local matrices, factor them (Householder QR), build the local
+ * interface operators and the coarse problem.  Errors: DDELM_E_HIP,
+ * DDELM_E_CHOLESKY. */
+ddelm_status ddelm_factor(ddelm_ctx ctx);
+
+/* Solve for nrhs right-hand sides (1 <= nrhs <= max_nrhs).
+ *   f_I   [nrhs][N][n_int]   f at the interior points
+ *   g_B   [nrhs][sum_nB]     g at the boundary points (ddelm_get_boundary_points order)
+ *   coef  [nrhs][N][M]       output: last-layer coefficients c^i
+ *   mu_pi [nrhs][n_pi]       output, may be NULL: mu_Pi
+ *   mu_dl [nrhs][n_dl]       output, may be NULL: mu_Delta
+ *   stats host, may be NULL; when given the call synchronises the stream.
+ * Errors: DDELM_E_STATE (before factor), DDELM_E_ARG, DDELM_E_HIP,
+ * DDELM_E_NONFINITE; DDELM_WARN_NOCONV when maxit was reached. */
+ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B,
+                         double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats);
+
+/* u(x) (and grad u if grad != NULL) on the lowest-index subdomain whose
+ * closed box holds x.  coef [nrhs][N][M], x [npts][2], u [nrhs][npts],
+ * grad [nrhs][npts][2].  Points outside the box are clamped to the nearest
+ * subdomain. */
+ddelm_status ddelm_evaluate(ddelm_ctx ctx, int nrhs, const double* coef, long long npts,
+                            const double* x, double* u, double* grad);
+
+/* Sizes of the problem. */
+ddelm_status ddelm_get_sizes(ddelm_ctx ctx, ddelm_sizes* out);
+
+/* Host arrays [N]: boundary, Pi, Delta and row counts per subdomain. */
+ddelm_status ddelm_get_counts(ddelm_ctx ctx, int* n_B, int* n_P, int* n_D, int* m);
+
+/* Host arrays: global Pi indices of the local Pi points, subdomain by
+ * subdomain ([sum n_P]), and global Delta indices of the local Delta
+ * points ([sum n_D]).  Bit-exact description of the interface split. */
+ddelm_status ddelm_get_indexing(ddelm_ctx ctx, int* pi_glob, int* dl_glob);
+
+/* Device [sum_nB][2]: boundary point coordinates in the g_B order. */
+ddelm_status ddelm_get_boundary_points(ddelm_ctx ctx, double* x_B);
+
+/* Device [n_pi][2] and [n_dl][2]: interface point coordinates. */
+ddelm_status ddelm_get_interface_points(ddelm_ctx ctx, double* x_pi, double* x_dl);
+
+/* Device copy of one local matrix of subdomain `sub`, row-major rows x cols
+ * (host outputs rows, cols; pass out == NULL to query the shape):
+ *   0 K_c^i (m x M)        1 A_m^i (n_G x M)   2 Kbar^i (m x M)   3 Abar^i (n_D x M)
+ *   4 R of K_c^i (M x M)   5 I - Q_G Q_G^T (n_G x n_G)   6 A_m^i K_c^{i+} E_G (n_G x n_G)
+ *   7 Abar^i Kbar^{i+} E_D (n_D x n_D)   8 S_Pi (n_pi x n_pi, sub ignored)
+ * 0-3 are re-assembled on demand; 4-8 need ddelm_factor. */
+ddelm_status ddelm_get_local_matrix(ddelm_ctx ctx, int which, int sub, double* out,
+                                    int* rows, int* cols);
+
+const char* ddelm_last_error(ddelm_ctx ctx);
+void ddelm_destroy(ddelm_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDELM_H */

@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/ddelm.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddelm.so")
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int_p = ctypes.POINTER(ctypes.c_int)
+
+DDELM_OK = 0
+DDELM_WARN_NOCONV = 1
+STATUS_NAMES = {
+    0: "DDELM_OK", 1: "DDELM_WARN_NOCONV", -1: "DDELM_E_ARG", -2: "DDELM_E_SHAPE", -3: "DDELM_E_STATE",
+    -4: "DDELM_E_HIP", -5: "DDELM_E_NOMEM", -6: "DDELM_E_CHOLESKY", -7: "DDELM_E_NONFINITE",
+}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("lo", ctypes.c_double * 2), ("hi", ctypes.c_double * 2),
+        ("p", ctypes.c_int), ("edge_s", c_double_p),
+        ("n_extra", ctypes.c_int), ("extra_s", c_double_p),
+        ("n_int", ctypes.c_int), ("x_int", ctypes.c_void_p),
+        ("M", ctypes.c_int), ("W", ctypes.c_void_p), ("b", ctypes.c_void_p),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("theta", ctypes.c_double), ("coarse", ctypes.c_int), ("precision", ctypes.c_int),
+        ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("max_nrhs", ctypes.c_int),
+        ("cg_mode", ctypes.c_int), ("refine_maxit", ctypes.c_int), ("refine_tol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("refine_steps", ctypes.c_int), ("rel_res", ctypes.c_double),
+        ("ms_rhs", ctypes.c_double), ("ms_cg", ctypes.c_double), ("ms_recover", ctypes.c_double),
+    ]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int), ("M", ctypes.c_int), ("n_pi", ctypes.c_int), ("n_dl", ctypes.c_int),
+        ("n_int", ctypes.c_int), ("max_m", ctypes.c_int), ("sum_nB", ctypes.c_longlong),
+        ("sum_nG", ctypes.c_longlong),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "ddelm_default_options": (None, [ctypes.POINTER(Options)]),
+    "ddelm_setup": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Problem),
+                                   ctypes.POINTER(Options), ctypes.c_void_p]),
+    "ddelm_factor": (ctypes.c_int, [ctypes.c_void_p]),
+    "ddelm_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ddelm_evaluate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ddelm_get_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Sizes)]),
+    "ddelm_get_counts": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_int_p, c_int_p]),
+    "ddelm_get_indexing": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),
+    "ddelm_get_boundary_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "ddelm_get_interface_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ddelm_get_local_matrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                              c_int_p, c_int_p]),
+    "ddelm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "ddelm_destroy": (None, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libddelm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_10032_amd._build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

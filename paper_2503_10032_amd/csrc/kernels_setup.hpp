@@ -1,0 +1,461 @@
+// Setup-time kernels: feature assembly, batched Householder QR, triangular
+// solves, small batched GEMMs, coarse assembly, Cholesky and inverse.
+#pragma once
+#include "geometry.hpp"
+#include "kernels_common.hpp"
+
+namespace ddelm {
+
+// ---------------------------------------------------------------- features
+//
+// Row r of a local matrix of subdomain i is  sum_terms wgt * op(phi_j)(x),
+// phi_j(x) = tanh(w_j . xi + b_j), xi = ((x - cx)/hx, (y - cy)/hy):
+//   value      t
+//   -Laplace   2 t (1 - t^2) (w0^2/hx^2 + w1^2/hy^2)
+//   flux       (1 - t^2) (w0 nx/hx + w1 ny/hy)
+// Output: column-major, element (r, j) at out[off[i] + j*ld[i] + r].
+struct FeatArgs {
+  const int* row0;       // [N+1]
+  const int* ptr;        // [rows+1]
+  const Term* terms;
+  const double* W;       // [N][M][2]
+  const double* bias;    // [N][M]
+  const double* geom;    // [N][4]: cx, cy, hx, hy
+  const long long* off;  // [N]
+  const int* ld;         // [N]
+  int M;
+  int sub0;              // first subdomain of this launch
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__ out) {
+  const int i = a.sub0 + blockIdx.z;
+  const int r = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nrows = a.row0[i + 1] - a.row0[i];
+  if (r >= nrows || j >= a.M) return;
+  const double cx = a.geom[4 * i], cy = a.geom[4 * i + 1], hx = a.geom[4 * i + 2], hy = a.geom[4 * i + 3];
+  const double w0 = a.W[((size_t)i * a.M + j) * 2], w1 = a.W[((size_t)i * a.M + j) * 2 + 1];
+  const double bj = a.bias[(size_t)i * a.M + j];
+  const double gx = w0 / hx, gy = w1 / hy;
+  const double lap = gx * gx + gy * gy;
+  const int row = a.row0[i] + r;
+  double acc = 0.0;
+  for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
+    const Term tm = a.terms[q];
+    const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
+    const double t = tanh(z);
+    const double dt = 1.0 - t * t;
+    double v;
+    if (tm.op == OP_VALUE) v = t;
+    else if (tm.op == OP_NEG_LAPLACE) v = 2.0 * t * dt * lap;
+    else v = dt * (gx * tm.nx + gy * tm.ny);
+    acc += tm.wgt * v;
+  }
+  out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;
+}
+
+// ---------------------------------------------------------------- Householder QR
+//
+// A batch of column-major matrices.  Reflector j of matrix b lives below the
+// diagonal of column j (v_j[j] = 1 implicit), tau[b][j] its scale, so that
+// H_j = I - tau_j v_j v_j^T and K = H_0 H_1 ... H_{M-1} [R; 0].
+struct QRDesc {
+  long long off;   // element offset of the matrix
+  int m;           // rows
+  int ld;          // leading dimension
+  int ncols;       // columns stored (factored columns first)
+  int nrefl;       // reflectors (= factored columns)
+  long long tau;   // offset into tau
+  int pad;
+};
+
+constexpr int kTW = 8;   // columns per register tile
+
+// Factor columns [k, k+kTW) of every matrix (rows k..m-1) with the panel
+// held in registers: row k + tid + q*kBlock, q < RPT.
+template <typename T, int RPT>
+__global__ void __launch_bounds__(kBlock) k_qr_panel(const QRDesc* __restrict__ desc, T* __restrict__ A,
+                                                     T* __restrict__ tau, int k) {
+  const QRDesc d = desc[blockIdx.x];
+  if (k >= d.nrefl) return;
+  __shared__ T red[kWaves * kTW];
+  __shared__ T bc[2];
+  T* Am = A + d.off;
+  const int ncol = min(kTW, d.nrefl - k);
+  T a[RPT][kTW];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kBlock;
+#pragma unroll
+    for (int c = 0; c < kTW; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
+  }
+  for (int jj = 0; jj < ncol; ++jj) {
+    const int j = k + jj;
+    // norm of the part below the diagonal, and the diagonal element
+    T ss = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kBlock;
+      T x = T(0);
+#pragma unroll
+      for (int c = 0; c < kTW; ++c) if (c == jj) x = a[q][c];
+      if (r > j && r < d.m) ss += x * x;
+      if (r == j) bc[0] = x;
+    }
+    ss = block_sum(ss, red);   // contains a barrier after bc[0] was written
+    const T alpha = bc[0];
+    T beta = alpha, tj = 0, scale = 0;
+    if (ss > T(0)) {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tj = (beta - alpha) / beta;
+      scale = T(1) / (alpha - beta);
+    }
+    // form v_j in column jj, R diagonal
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kBlock;
+#pragma unroll
+      for (int c = 0; c < kTW; ++c) {
+        if (c == jj) {
+          if (r == j) a[q][c] = beta;
+          else if (r > j) a[q][c] *= scale;
+        }
+      }
+    }
+    if (threadIdx.x == 0) tau[d.tau + j] = tj;
+    // apply H_j to the panel columns right of jj
+    T part[kTW];
+#pragma unroll
+    for (int c = 0; c < kTW; ++c) part[c] = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kBlock;
+      if (r >= j && r < d.m) {
+        T v = T(1);
+#pragma unroll
+        for (int c = 0; c < kTW; ++c) if (c == jj && r > j) v = a[q][c];
+#pragma unroll
+        for (int c = 0; c < kTW; ++c) if (c > jj) part[c] += v * a[q][c];
+      }
+    }
+    T w[kTW];
+    block_sum_vec<T, kTW>(part, w, red);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kBlock;
+      if (r >= j && r < d.m) {
+        T v = T(1);
+#pragma unroll
+        for (int c = 0; c < kTW; ++c) if (c == jj && r > j) v = a[q][c];
+#pragma unroll
+        for (int c = 0; c < kTW; ++c) if (c > jj) a[q][c] -= tj * w[c] * v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kBlock;
+#pragma unroll
+    for (int c = 0; c < kTW; ++c)
+      if (r < d.m && c < ncol) Am[(long long)(k + c) * d.ld + r] = a[q][c];
+  }
+}
+
+// Apply reflectors [j0, j1) of matrix b (stored in A) to a tile of kTW
+// columns of a target C: rows r0..m-1 with r0 = j0, columns
+// c0 + blockIdx.y*kTW + (0..kTW).  Target column c of matrix b is at
+// C + coff[b] + c*ldc[b].  reverse = 1 applies them from j1-1 down to j0
+// (multiplication by Q instead of Q^T).
+template <typename T, int RPT>
+__global__ void __launch_bounds__(kBlock) k_qr_apply(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                     const T* __restrict__ tau, int j0, int j1, T* __restrict__ C,
+                                                     const long long* __restrict__ coff, const int* __restrict__ ldc,
+                                                     const int* __restrict__ cn, int c0, int reverse) {
+  const QRDesc d = desc[blockIdx.x];
+  j1 = min(j1, d.nrefl);
+  if (j0 >= j1) return;
+  const int cbeg = c0 + blockIdx.y * kTW;
+  const int ctot = cn[blockIdx.x];
+  if (cbeg >= ctot) return;
+  const int ncol = min(kTW, ctot - cbeg);
+  __shared__ T red[kWaves * kTW];
+  const T* Am = A + d.off;
+  T* Cm = C + coff[blockIdx.x];
+  const int L = ldc[blockIdx.x];
+  T a[RPT][kTW];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = j0 + threadIdx.x + q * kBlock;
+#pragma unroll
+    for (int c = 0; c < kTW; ++c) a[q][c] = (r < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + r] : T(0);
+  }
+  for (int s = 0; s < j1 - j0; ++s) {
+    const int j = reverse ? (j1 - 1 - s) : (j0 + s);
+    const T tj = tau[d.tau + j];
+    T v[RPT];
+    T part[kTW];
+#pragma unroll
+    for (int c = 0; c < kTW; ++c) part[c] = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = j0 + threadIdx.x + q * kBlock;
+      v[q] = (r == j) ? T(1) : ((r > j && r < d.m) ? Am[(long long)j * d.ld + r] : T(0));
+#pragma unroll
+      for (int c = 0; c < kTW; ++c) part[c] += v[q] * a[q][c];
+    }
+    T w[kTW];
+    block_sum_vec<T, kTW>(part, w, red);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int c = 0; c < kTW; ++c) a[q][c] -= tj * w[c] * v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = j0 + threadIdx.x + q * kBlock;
+#pragma unroll
+    for (int c = 0; c < kTW; ++c)
+      if (r < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + r] = a[q][c];
+  }
+}
+
+// ---------------------------------------------------------------- triangular solves
+//
+// X <- R^{-1} X (trans = 0) or R^{-T} X (trans = 1) for the n x n upper
+// triangle R of matrix b (R at A + desc.off, leading dimension desc.ld,
+// n = desc.nrefl), X = n x nc columns at X + xoff[b], leading dimension
+// ldx[b].  Up to kTRSMC columns per workgroup, staged in LDS.
+constexpr int kTRSMC = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                 T* __restrict__ X, const long long* __restrict__ xoff,
+                                                 const int* __restrict__ ldx, const int* __restrict__ xn,
+                                                 int trans) {
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);          // [n][kTRSMC]
+  const QRDesc d = desc[blockIdx.x];
+  const int n = d.nrefl;
+  const int cbeg = blockIdx.y * kTRSMC;
+  const int ctot = xn[blockIdx.x];
+  if (cbeg >= ctot) return;
+  const int nc = min(kTRSMC, ctot - cbeg);
+  const T* R = A + d.off;
+  T* Xm = X + xoff[blockIdx.x];
+  const int L = ldx[blockIdx.x];
+  for (int e = threadIdx.x; e < n * kTRSMC; e += kBlock) {
+    const int r = e / kTRSMC, c = e % kTRSMC;
+    xs[e] = c < nc ? Xm[(long long)(cbeg + c) * L + r] : T(0);
+  }
+  __syncthreads();
+  for (int s = 0; s < n; ++s) {
+    const int k = trans ? s : (n - 1 - s);
+    if (threadIdx.x < kTRSMC) xs[k * kTRSMC + threadIdx.x] /= R[(long long)k * d.ld + k];
+    __syncthreads();
+    if (!trans) {
+      for (int e = threadIdx.x; e < k * kTRSMC; e += kBlock) {
+        const int r = e / kTRSMC, c = e % kTRSMC;
+        xs[e] -= R[(long long)k * d.ld + r] * xs[k * kTRSMC + c];
+      }
+    } else {
+      for (int e = (k + 1) * kTRSMC + threadIdx.x; e < n * kTRSMC; e += kBlock) {
+        const int r = e / kTRSMC, c = e % kTRSMC;
+        xs[e] -= R[(long long)r * d.ld + k] * xs[k * kTRSMC + c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * kTRSMC; e += kBlock) {
+    const int r = e / kTRSMC, c = e % kTRSMC;
+    if (c < nc) Xm[(long long)(cbeg + c) * L + r] = xs[e];
+  }
+}
+
+// ---------------------------------------------------------------- batched GEMM
+//
+// C = alpha * op(A) * B + beta * C, all column-major; op(A) = A (m x k) or
+// A^T (A stored k x m).  16 x 16 output tile per workgroup.
+struct GemmDesc {
+  long long a, b, c;     // element offsets
+  int lda, ldb, ldc;
+  int m, n, k;
+};
+
+template <typename TA, typename TC>
+__global__ void __launch_bounds__(kBlock) k_gemm(const GemmDesc* __restrict__ desc, const TA* __restrict__ A,
+                                                 const TA* __restrict__ B, TC* __restrict__ C, int transA,
+                                                 double alpha, double beta) {
+  const GemmDesc g = desc[blockIdx.z];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.x * 16 + tx, col = blockIdx.y * 16 + ty;
+  if (blockIdx.x * 16 >= g.m || blockIdx.y * 16 >= g.n) return;
+  __shared__ double As[16][17], Bs[16][17];
+  double acc = 0.0;
+  for (int k0 = 0; k0 < g.k; k0 += 16) {
+    // As[kk][rr] = op(A)[row0 + rr][k0 + kk]
+    {
+      const int rr = tx, kk = ty;
+      const int r = blockIdx.x * 16 + rr, kx = k0 + kk;
+      double v = 0.0;
+      if (r < g.m && kx < g.k)
+        v = transA ? (double)A[g.a + (long long)r * g.lda + kx] : (double)A[g.a + (long long)kx * g.lda + r];
+      As[kk][rr] = v;
+      const int cc = ty, kb = tx;
+      const int cgl = blockIdx.y * 16 + cc, kbx = k0 + kb;
+      Bs[cc][kb] = (cgl < g.n && kbx < g.k) ? (double)B[g.b + (long long)cgl * g.ldb + kbx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc += As[kk][tx] * Bs[ty][kk];
+    __syncthreads();
+  }
+  if (row < g.m && col < g.n) {
+    TC* cp = C + g.c + (long long)col * g.ldc + row;
+    const double prev = beta != 0.0 ? (double)*cp : 0.0;
+    *cp = (TC)(alpha * acc + beta * prev);
+  }
+}
+
+// ---------------------------------------------------------------- small helpers
+
+// dst[b] (rows x cols, ld_dst) <- src[b] rows [r0, r0+rows), cols [c0, c0+cols)
+// (ld_src); optional transpose.  One launch per batch via blockIdx.z.
+struct CopyDesc {
+  long long src, dst;
+  int lds, ldd;
+  int rows, cols;
+  int trans;
+  int pad;
+};
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(kBlock) k_copy2d(const CopyDesc* __restrict__ desc, const TS* __restrict__ S,
+                                                   TD* __restrict__ D) {
+  const CopyDesc c = desc[blockIdx.y];
+  const long long n = (long long)c.rows * c.cols;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const int r = (int)(e % c.rows), col = (int)(e / c.rows);
+    const TS v = S[c.src + (long long)col * c.lds + r];
+    if (c.trans) D[c.dst + (long long)r * c.ldd + col] = (TD)v;
+    else D[c.dst + (long long)col * c.ldd + r] = (TD)v;
+  }
+}
+
+__global__ void k_fill(double* __restrict__ p, long long n, double v) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
+}
+
+template <typename T>
+__global__ void k_fill_t(T* __restrict__ p, long long n, T v) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
+}
+
+// identity blocks: for each batch entry, add `v` on the diagonal of an n x n
+// block at off (column-major, ld = n)
+__global__ void k_add_diag(const long long* __restrict__ off, const int* __restrict__ n, double* __restrict__ P,
+                           double v) {
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < n[b]; k += kBlock) P[off[b] + (long long)k * n[b] + k] += v;
+}
+
+template <typename T>
+__global__ void k_add_diag_t(const long long* __restrict__ off, const int* __restrict__ n, T* __restrict__ P, T v) {
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < n[b]; k += kBlock) P[off[b] + (long long)k * n[b] + k] += v;
+}
+
+// ---------------------------------------------------------------- coarse problem
+//
+// Sum the local corner blocks into global nP x nP matrices (column-major):
+//   Dpp[p][q] = sum_i L_i[a_p][a_q],  Gs[p][q] = sum_i G_i[a_p][a_q]
+// over subdomains i holding both corners.  One thread per row p; owners in
+// subdomain order, so the sums are deterministic.
+template <typename T>
+__global__ void k_coarse_assemble(int nP, const int* __restrict__ own_ptr, const int* __restrict__ own_slot,
+                                  const int* __restrict__ slot_sub, const int* __restrict__ pi_off,
+                                  const int* __restrict__ pi_l2g, const long long* __restrict__ offG,
+                                  const int* __restrict__ nG, const T* __restrict__ Gm, const T* __restrict__ Lm,
+                                  double* __restrict__ Dpp, double* __restrict__ Gs) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= nP) return;
+  for (int e = own_ptr[p]; e < own_ptr[p + 1]; ++e) {
+    const int slot = own_slot[e];
+    const int i = slot_sub[slot];
+    const int ap = slot - pi_off[i];
+    const int np = pi_off[i + 1] - pi_off[i];
+    const int ng = nG[i];
+    for (int bq = 0; bq < np; ++bq) {
+      const int q = pi_l2g[pi_off[i] + bq];
+      Dpp[(long long)q * nP + p] += (double)Lm[offG[i] + (long long)bq * ng + ap];
+      Gs[(long long)q * nP + p] += (double)Gm[offG[i] + (long long)bq * ng + ap];
+    }
+  }
+}
+
+// In-place lower Cholesky of an n x n column-major SPD matrix (one
+// workgroup).  err[0] |= 2 if a pivot is not positive.
+__global__ void __launch_bounds__(kBlock) k_cholesky(double* __restrict__ S, int n, unsigned* __restrict__ err) {
+  __shared__ double piv;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double dj = S[(long long)j * n + j];
+      if (!(dj > 0.0)) {
+        atomicOr(err, 2u);
+        dj = 1.0;
+      }
+      dj = sqrt(dj);
+      S[(long long)j * n + j] = dj;
+      piv = dj;
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int r = j + 1 + threadIdx.x; r < n; r += kBlock) S[(long long)j * n + r] *= inv;
+    __syncthreads();
+    const int m = n - j - 1;
+    const long long tot = (long long)m * m;
+    for (long long e = threadIdx.x; e < tot; e += kBlock) {
+      const int r = j + 1 + (int)(e % m), c = j + 1 + (int)(e / m);
+      if (r >= c) S[(long long)c * n + r] -= S[(long long)j * n + r] * S[(long long)j * n + c];
+    }
+    __syncthreads();
+  }
+}
+
+// Columns of S^{-1} from the Cholesky factor (lower, column-major):
+// solve L y = e_k then L^T x = y; 4 columns per workgroup, in LDS.
+__global__ void __launch_bounds__(kBlock) k_chol_inverse(const double* __restrict__ Lf, int n,
+                                                         double* __restrict__ Sinv) {
+  extern __shared__ unsigned char smem_raw[];
+  double* x = reinterpret_cast<double*>(smem_raw);   // [n][4]
+  const int c0 = blockIdx.x * 4;
+  for (int e = threadIdx.x; e < n * 4; e += kBlock) {
+    const int r = e / 4, c = e % 4;
+    x[e] = (r == c0 + c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {      // forward: L y = e
+    if (threadIdx.x < 4) x[k * 4 + threadIdx.x] /= Lf[(long long)k * n + k];
+    __syncthreads();
+    for (int e = (k + 1) * 4 + threadIdx.x; e < n * 4; e += kBlock) {
+      const int r = e / 4, c = e % 4;
+      x[e] -= Lf[(long long)k * n + r] * x[k * 4 + c];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {   // backward: L^T x = y
+    if (threadIdx.x < 4) x[k * 4 + threadIdx.x] /= Lf[(long long)k * n + k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * 4; e += kBlock) {
+      const int r = e / 4, c = e % 4;
+      x[e] -= Lf[(long long)r * n + k] * x[k * 4 + c];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * 4; e += kBlock) {
+    const int r = e / 4, c = e % 4;
+    if (c0 + c < n) Sinv[(long long)(c0 + c) * n + r] = x[e];
+  }
+}
+
+}  // namespace ddelm
