@@ -182,6 +182,12 @@ ddelm_status ddelm_get_interface_points(ddelm_ctx ctx, double* x_pi, double* x_d
 ddelm_status ddelm_get_local_matrix(ddelm_ctx ctx, int which, int sub, double* out,
                                     int* rows, int* cols);
 
+/* Host [8]: device-timeline milliseconds (HIP events on the context's
+ * stream) of the phases of the last ddelm_factor and ddelm_solve:
+ *   0 feature assembly   1 Householder QR   2 local interface operators
+ *   3 coarse problem     4 right-hand side  5 CG   6 recovery   7 unused (0) */
+ddelm_status ddelm_get_phase_times(ddelm_ctx ctx, double* ms);
+
 const char* ddelm_last_error(ddelm_ctx ctx);
 void ddelm_destroy(ddelm_ctx ctx);
 

@@ -70,6 +70,7 @@ SIGNATURES = {
     "ddelm_get_interface_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ddelm_get_local_matrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                               c_int_p, c_int_p]),
+    "ddelm_get_phase_times": (ctypes.c_int, [ctypes.c_void_p, c_double_p]),
     "ddelm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "ddelm_destroy": (None, [ctypes.c_void_p]),
 }

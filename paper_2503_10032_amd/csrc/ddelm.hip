@@ -15,6 +15,7 @@
 #include "geometry.hpp"
 #include "kernels_setup.hpp"
 #include "kernels_solve.hpp"
+#include "kernels_cg.hpp"
 
 using namespace ddelm;
 
@@ -128,9 +129,26 @@ struct ddelm_ctx_s {
   DBuf<long long> f_off;               // per subdomain offset into F
   DBuf<int> f_ld, f_cn, f_cnM;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
-  DBuf<double> cg_x, cg_r, cg_p, cg_w, cg_b, cg_part, cg_scal;
+  DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
+  int cg_blocks = 0, cg_slices = 0;
   DBuf<unsigned> bar;
   DBuf<int> sizes_dev;                 // per subdomain M, n_I, n_B, m, n_G
+  // phase timing (HIP events on the stream)
+  hipEvent_t ev[10] = {};
+  double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  void mark(int k) {
+    if (!ev[k]) HIPCHK(hipEventCreate(&ev[k]));
+    HIPCHK(hipEventRecord(ev[k], stream));
+  }
+  double span(int a, int b) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[a], ev[b]));
+    return (double)ms;
+  }
+  ~ddelm_ctx_s() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 
   void fail(ddelm_status st, const std::string& m) { throw StatusError{st, m}; }
 };
@@ -484,136 +502,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
   }
 }
 
-// ---------------------------------------------------------------- persistent CG (one cooperative launch)
-//
-// Runs the whole CG loop: every workgroup walks the same phases, separated
-// by grid barriers; scalar reductions are repeated by every workgroup in the
-// same order, so all workgroups take identical decisions and leave the loop
-// together (at convergence of every RHS or at maxit).
-__global__ void __launch_bounds__(kBlock) k_cg_persistent(OpArgs<double> a, CGState s, unsigned* bar,
-                                                          unsigned* err) {
-  extern __shared__ double sm[];
-  __shared__ double red[kWaves];
-  __shared__ double scal[64 * 4];   // per rhs: rr, bb, done, iters
-  const unsigned nb = gridDim.x;
-  const int nrhs = s.nrhs;
-  const int nloc = a.N * nrhs;
-  const int ncb = ceil_div(2 * a.nP, kBlock) * nrhs;
-  // init: r = p = b (already in r), x = 0, rr
-  {
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < s.n; g += nb * kBlock) {
-        const size_t e = (size_t)r * s.n + g;
-        const double bv = s.r[e];
-        s.x[e] = 0.0;
-        s.p[e] = bv;
-        acc += bv * bv;
-      }
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) s.part[(size_t)r * nb + blockIdx.x] = acc;
-    }
-    grid_barrier(bar, nb, err);
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) acc += s.part[(size_t)r * nb + k];
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) {
-        scal[4 * r] = acc; scal[4 * r + 1] = acc; scal[4 * r + 2] = (acc == 0.0) ? 1.0 : 0.0; scal[4 * r + 3] = 0;
-      }
-    }
-    __syncthreads();
-    grid_barrier(bar, nb, err);   // everyone has read the partials
-  }
-  for (int it = 0; it < s.maxit; ++it) {
-    bool all_done = true;
-    for (int r = 0; r < nrhs; ++r) all_done = all_done && scal[4 * r + 2] != 0.0;
-    if (all_done) break;
-    for (int item = blockIdx.x; item < nloc; item += nb) ph_local_v(a, s.p, item % a.N, item / a.N, sm);
-    grid_barrier(bar, nb, err);
-    for (int item = blockIdx.x; item < ncb; item += nb) {
-      const int nrb = ncb / nrhs;
-      ph_coarse(a.nP, a.pi_own_ptr, a.pi_own_slot, a.X1, a.rho_loc, a.psi_loc, nullptr, a.sumP, item / nrb,
-                item % nrb, a.c1, 1.0, sm);
-    }
-    grid_barrier(bar, nb, err);
-    for (int item = blockIdx.x; item < nloc; item += nb) ph_local_lam(a, item % a.N, item / a.N);
-    grid_barrier(bar, nb, err);
-    if (a.theta != 0.0) {
-      for (int item = blockIdx.x; item < nloc; item += nb) ph_local_P1(a, item % a.N, item / a.N, sm);
-      grid_barrier(bar, nb, err);
-      for (int item = blockIdx.x; item < nloc; item += nb) ph_local_P2(a, item % a.N, item / a.N, sm);
-      grid_barrier(bar, nb, err);
-    }
-    for (int item = blockIdx.x; item < nloc; item += nb) ph_local_eta(a, item % a.N, item / a.N, sm);
-    grid_barrier(bar, nb, err);
-    for (int item = blockIdx.x; item < ncb; item += nb) {
-      const int nrb = ncb / nrhs;
-      ph_coarse(a.nP, a.pi_own_ptr, a.pi_own_slot, a.X1, a.nu_loc, nullptr, nullptr, a.sumP, item / nrb,
-                item % nrb, a.c2, 1.0, sm);
-    }
-    grid_barrier(bar, nb, err);
-    for (int item = blockIdx.x; item < nloc; item += nb) ph_local_w(a, item % a.N, item / a.N);
-    grid_barrier(bar, nb, err);
-    // w and p.w
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < s.n; g += nb * kBlock) {
-        const double wv = dl_sum(a.dl_own_ptr, a.dl_own_slot, a.w_loc + (size_t)r * a.sumD, g);
-        s.w[(size_t)r * s.n + g] = wv;
-        acc += wv * s.p[(size_t)r * s.n + g];
-      }
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) s.part[(size_t)r * nb + blockIdx.x] = acc;
-    }
-    grid_barrier(bar, nb, err);
-    // alpha, x and r updates, partial r.r (into the second half of part)
-    for (int r = 0; r < nrhs; ++r) {
-      double pw = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) pw += s.part[(size_t)r * nb + k];
-      pw = block_sum(pw, red);
-      const double al = (scal[4 * r + 2] != 0.0 || pw == 0.0) ? 0.0 : scal[4 * r] / pw;
-      double acc = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < s.n; g += nb * kBlock) {
-        const size_t e = (size_t)r * s.n + g;
-        s.x[e] += al * s.p[e];
-        const double rv = s.r[e] - al * s.w[e];
-        s.r[e] = rv;
-        acc += rv * rv;
-      }
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) s.part[(size_t)(nrhs + r) * nb + blockIdx.x] = acc;
-    }
-    grid_barrier(bar, nb, err);
-    for (int r = 0; r < nrhs; ++r) {
-      double rr = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) rr += s.part[(size_t)(nrhs + r) * nb + k];
-      rr = block_sum(rr, red);
-      const bool was_done = scal[4 * r + 2] != 0.0;
-      const double be = (was_done || !(scal[4 * r] > 0.0)) ? 0.0 : rr / scal[4 * r];
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < s.n; g += nb * kBlock) {
-        const size_t e = (size_t)r * s.n + g;
-        s.p[e] = s.r[e] + be * s.p[e];
-      }
-      __syncthreads();
-      if (threadIdx.x == 0 && !was_done) {
-        scal[4 * r] = rr;
-        scal[4 * r + 3] += 1.0;
-        if (sqrt(rr) <= s.tol * sqrt(scal[4 * r + 1]) || !(rr == rr)) scal[4 * r + 2] = 1.0;
-      }
-      __syncthreads();
-    }
-    grid_barrier(bar, nb, err);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int r = 0; r < nrhs; ++r) {
-      double* sc = s.scal + (size_t)r * 8;
-      sc[0] = scal[4 * r]; sc[1] = scal[4 * r + 1]; sc[5] = scal[4 * r + 2]; sc[6] = scal[4 * r + 3];
-      sc[7] = (scal[4 * r] == scal[4 * r]) ? 0.0 : 1.0;
-    }
-  }
-}
-
 // ---------------------------------------------------------------- evaluation
 __global__ void k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0, double h1,
                            const double* __restrict__ W, const double* __restrict__ bias,
@@ -664,7 +552,11 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   c->c2.alloc(C);
   c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
   const size_t V = (size_t)nrhs * std::max(c->nD, 1);
-  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_w, &c->cg_b}) b->alloc(V);
+  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b}) b->alloc(V);
+  c->mu_slot.alloc(P);
+  c->e_slot.alloc(P);
+  c->mu_slot.zero(s);
+  c->e_slot.zero(s);
   c->cg_part.alloc((size_t)2 * nrhs * 4096);
   c->cg_scal.alloc((size_t)nrhs * 8);
   // zero everything once so unused Pi/Delta slots never hold garbage
@@ -752,27 +644,55 @@ int cg_multilaunch(ddelm_ctx c, int nrhs) {
   return it;
 }
 
-int coop_grid(ddelm_ctx c, size_t smem) {
+template <int NR>
+void launch_fused(ddelm_ctx c, int nrhs) {
+  hipStream_t s = c->stream;
+  const Geometry& g = c->geo;
+  FusedArgs<double> f;
+  f.a = op_args(c, nrhs);
+  int S = 1;
+  if (const char* env = getenv("DDELM_CG_SLICES")) S = std::max(1, std::min(8, atoi(env)));
+  else if (c->N < 32) S = std::max(1, std::min(4, 64 / std::max(c->N, 1)));
+  f.S = S;
+  f.nrhs = nrhs;
+  f.tol = c->opt.tol;
+  f.maxit = c->opt.maxit;
+  f.x = c->cg_x.p; f.r = c->cg_r.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p; f.w = c->cg_w.p;
+  f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
+  f.err = c->flags.p;
+  const int xs = std::max(g.max_nD, 1) * NR;
+  const int ys = 2 * std::max(g.max_nG, 1) * NR;
+  const int part = kBlock * 2 * NR;
+  const int cu = std::max(2 * c->nP, 1);
+  f.lds_ys = xs;
+  f.lds_part = xs + ys;
+  f.lds_cu = xs + ys + part;
+  const size_t smem = sizeof(double) * (size_t)(xs + ys + part + cu);
+  if (smem > 160 * 1024) c->fail(DDELM_E_SHAPE, "CG workspace exceeds the LDS of one compute unit");
+  const void* fn = (const void*)k_cg_fused<double, NR>;
+  if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   int per_cu = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent, kBlock, smem));
-  per_cu = std::max(1, std::min(per_cu, 2));
-  return std::max(1, c->num_cu * per_cu);
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, smem));
+  if (per_cu < 1) c->fail(DDELM_E_SHAPE, "CG kernel cannot be resident");
+  int nb = std::min(c->num_cu * std::min(per_cu, 2), c->N * S);
+  if (const char* env = getenv("DDELM_CG_BLOCKS")) nb = std::max(1, std::min(nb, atoi(env)));
+  nb = std::max(1, std::min(nb, 4096));
+  f.flags = c->bar.p;
+  HIPCHK(hipMemcpyAsync(f.r, c->cg_b.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(c->bar.p, 0, (size_t)nb * kFlagStride * sizeof(unsigned), s));
+  void* args[] = {(void*)&f};
+  HIPCHK(hipLaunchCooperativeKernel(fn, dim3(nb), dim3(kBlock), args, smem, s));
+  c->cg_blocks = nb;
+  c->cg_slices = S;
 }
 
 void cg_persistent(ddelm_ctx c, int nrhs) {
-  hipStream_t s = c->stream;
-  const size_t sm = local_smem(c);
-  int nb = coop_grid(c, sm);
-  nb = std::min(nb, std::max(c->N * nrhs, 1));
-  nb = std::min(nb, 4096);
-  CGState st = cg_state(c, nrhs, nb);
-  OpArgs<double> a = op_args(c, nrhs);
-  HIPCHK(hipMemcpyAsync(st.r, c->cg_b.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemsetAsync(c->bar.p, 0, 4 * sizeof(unsigned), s));
-  unsigned* bar = c->bar.p;
-  unsigned* err = c->flags.p;
-  void* args[] = {(void*)&a, (void*)&st, (void*)&bar, (void*)&err};
-  HIPCHK(hipLaunchCooperativeKernel((const void*)k_cg_persistent, dim3(nb), dim3(kBlock), args, sm, s));
+  if (nrhs <= 1) launch_fused<1>(c, nrhs);
+  else if (nrhs <= 2) launch_fused<2>(c, nrhs);
+  else if (nrhs <= 4) launch_fused<4>(c, nrhs);
+  else if (nrhs <= 8) launch_fused<8>(c, nrhs);
+  else if (nrhs <= 16) launch_fused<16>(c, nrhs);
+  else c->fail(DDELM_E_ARG, "the persistent CG handles at most 16 right-hand sides");
 }
 
 }  // namespace
@@ -875,7 +795,7 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     c->nG_dev.upload(nGv, s);
     c->flags.alloc(8);
     c->flags.zero(s);
-    c->bar.alloc(4);
+    c->bar.alloc((size_t)4096 * kFlagStride);
     c->bar.zero(s);
     HIPCHK(hipStreamSynchronize(s));
   });
@@ -922,6 +842,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
       for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
       c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
     }
+    c->mark(0);
     // ---- features: K_c (and Kbar) into the first M columns; A_m, Abar separately
     {
       std::vector<long long> o1(N), o2(N);
@@ -967,6 +888,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
         HIPCHK(hipStreamSynchronize(s));
       }
     }
+    c->mark(1);
     // ---- blocked Householder QR of all matrices, panel width kTW
     {
       const int rpt = rows_per_thread(g.max_m);
@@ -980,6 +902,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
       }
       HIPCHK(hipStreamSynchronize(s));
     }
+    c->mark(2);
     // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T in place, Xbar = Rbar^{-1} Qbar_D^T in place
     {
       c->h_offQG.assign(N + 1, 0);
@@ -1084,6 +1007,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
         copy_batch<double>(s, tN, c->Nm.p, c->NTm.p);
       }
     }
+    c->mark(3);
     // ---- coarse problem: D_PiPi, S_Pi = sum G_PiPi + D^T D, Cholesky, inverse, X1
     if (c->nP > 0) {
       const int n = c->nP;
@@ -1121,7 +1045,9 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
     } else {
       c->X1.alloc(1);
     }
+    c->mark(4);
     HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k) c->phase_ms[k] = c->span(k, k + 1);
     c->factored = true;
   });
 }
@@ -1140,6 +1066,7 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
     const int N = c->N, M = c->M;
     alloc_solve_workspace(c, nrhs);
     auto t0 = std::chrono::steady_clock::now();
+    c->mark(5);
     DBuf<long long> offm_d, offB_d;
     offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
     offB_d.upload(std::vector<long long>(c->h_offB.begin(), c->h_offB.end() - 1), s);
@@ -1181,11 +1108,12 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
       k_save_pif<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->c1.p, c->pif.p);
       HIPCHK(hipGetLastError());
     }
+    c->mark(6);
     HIPCHK(hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     // ---- CG
     if (c->nD > 0) {
-      int mode = c->opt.cg_mode == 0 ? 2 : c->opt.cg_mode;
+      int mode = c->opt.cg_mode == 0 ? (nrhs <= 16 ? 2 : 1) : c->opt.cg_mode;
       if (mode == 2) cg_persistent(c, nrhs);
       else cg_multilaunch(c, nrhs);
       std::vector<double> sc((size_t)nrhs * 8);
@@ -1204,6 +1132,7 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
     } else {
       HIPCHK(hipStreamSynchronize(s));
     }
+    c->mark(7);
     auto t2 = std::chrono::steady_clock::now();
     // ---- recovery: mu_Pi = pi_f - [S^-1 (rho + D^T psi)](mu_D); c = c_f0 + E mu
     if (c->nP > 0) {
@@ -1226,8 +1155,12 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
       HIPCHK(hipMemcpyAsync(mu_pi, c->pif.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (mu_dl && c->nD > 0)
       HIPCHK(hipMemcpyAsync(mu_dl, c->cg_x.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
+    c->mark(8);
     HIPCHK(hipStreamSynchronize(s));
     auto t3 = std::chrono::steady_clock::now();
+    c->phase_ms[4] = c->span(5, 6);
+    c->phase_ms[5] = c->span(6, 7);
+    c->phase_ms[6] = c->span(7, 8);
     if (stats) {
       stats->iters = iters;
       stats->refine_steps = 0;
@@ -1363,6 +1296,12 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
     if (which == 8) src = c->Spi.p;
     copy_batch<double>(s, {CopyDesc{soff, 0, R, R, R, C, 1, 0}}, src, out);
   });
+}
+
+ddelm_status ddelm_get_phase_times(ddelm_ctx c, double* ms) {
+  if (!c || !ms) return DDELM_E_ARG;
+  for (int k = 0; k < 8; ++k) ms[k] = c->phase_ms[k];
+  return DDELM_OK;
 }
 
 const char* ddelm_last_error(ddelm_ctx c) { return c ? c->err.c_str() : "null context"; }

@@ -1,0 +1,493 @@
+// Persistent CG on eq. nn-mixed: the whole CG loop in one cooperative launch.
+//
+// Work units are (subdomain i, row slice q): each subdomain's local operator
+// rows are split into S slices so that small problems still spread over
+// many compute units.  Every unit handles all right-hand sides together, so
+// a matrix element read from memory serves nrhs products.
+//
+// Per iteration (theta != 0) the phases are separated by 8 grid-wide
+// synchronisations:
+//   A  p = r + beta p at the unit's Delta points; rows of [G; L](:, Delta) p
+//   B  coarse solve at the subdomain's corners (mu_Pi, e), lam rows
+//   C  y = -N lambda rows               D  z = -N^T (P lambda) rows
+//   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, w rows
+//   G  w = sum of owners, partial p.w   H  alpha, x and r updates, partial r.r
+// The coarse solves are done redundantly by every unit for its own corners
+// (rows of X1 against the full coarse right-hand side), which removes two
+// synchronisations.  Scalar reductions are repeated by every workgroup in
+// the same order, so all take identical decisions.
+//
+// Synchronisation: every workgroup publishes an epoch in its own flag once
+// its memory operations have completed, then waits for all flags to reach
+// that epoch (one thread per flag).  Data exchanged between workgroups moves
+// through coherent loads and stores (see ld_co/st_co).  The waits are bounded.
+#pragma once
+#include "kernels_common.hpp"
+#include "kernels_solve.hpp"
+
+namespace ddelm {
+
+constexpr int kFlagStride = 16;   // one flag per 64-byte line
+
+// Coherent (agent-scope) loads and stores for every value that one workgroup
+// writes and another reads inside the kernel.  They bypass the per-XCD L2
+// copies, so no cache write-back or invalidation fences are needed; the
+// read-only matrices stay cached.
+__device__ __forceinline__ double ld_co(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_co(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide synchronisation: wait until this wave's memory operations have
+// completed, publish the epoch in this workgroup's flag, then wait (bounded)
+// until every workgroup's flag has reached it.  Together with ld_co/st_co for
+// the exchanged data this orders all cross-workgroup traffic.
+__device__ __forceinline__ void flag_sync(unsigned* flags, unsigned nb, unsigned epoch, unsigned* err) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&flags[blockIdx.x * kFlagStride], epoch, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+  for (unsigned t = threadIdx.x; t < nb; t += kBlock) {
+    unsigned long long spins = 0;
+    while (__hip_atomic_load(&flags[t * kFlagStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1ull << 27)) {
+        __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+struct FusedArgs {
+  OpArgs<T> a;
+  int S;                 // row slices per subdomain
+  int nrhs;
+  double tol;
+  int maxit;
+  double* x;             // [nrhs][nD]
+  double* r;             // [nrhs][nD], holds b on entry
+  double* p0;            // [nrhs][nD] p buffers (alternate by iteration)
+  double* p1;
+  double* w;             // [nrhs][nD]
+  double* part;          // [2][nrhs][nb]
+  double* mu_slot;       // [nrhs][sumP]  mu_Pi at the corner slots
+  double* e_slot;        // [nrhs][sumP]
+  double* scal;          // [nrhs][8] out: rr, bb, -, -, -, done, iters, nonfinite
+  unsigned* flags;       // [nb * kFlagStride]
+  unsigned* err;
+  int lds_ys, lds_part, lds_cu;   // LDS offsets (doubles) of the output, partial-sum and coarse areas
+};
+
+__device__ __forceinline__ void slice_rows(int n, int S, int q, int& r0, int& r1) {
+  const int len = (n + S - 1) / S;
+  r0 = min(n, q * len);
+  r1 = min(n, r0 + len);
+}
+
+// y_m[t][r] = sum_{k<K} A_m[(c0 + k) * lda + r0 + t] * x[k*NR + r] for rows t < R and
+// matrices m < NM; results in out[(m*R + t)*NR + r] (LDS).  The 256 threads
+// are split into nsplit groups over k; partial sums meet in `part` (LDS,
+// kBlock * NM * NR doubles).
+template <typename T, int NR, int NM>
+__device__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K, const double* x, int nrhs,
+                        double* out, double* part) {
+  if (R <= 0) {
+    __syncthreads();
+    return;
+  }
+  int Rp = ((R + 63) / 64) * 64;
+  if (Rp > kBlock) Rp = kBlock;     // R > 256: rows handled in passes
+  const int nsplit = kBlock / Rp;
+  for (int rb = 0; rb < R; rb += Rp) {
+    const int t = threadIdx.x % Rp, j = threadIdx.x / Rp;
+    const int row = rb + t;
+    double acc[NM][NR];
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[m][r] = 0.0;
+    if (row < R && j < nsplit) {
+      const T* a0 = A0 + (long long)c0 * lda + r0 + row;
+      const T* a1 = NM > 1 ? A1 + (long long)c0 * lda + r0 + row : nullptr;
+      int k = j;
+      for (; k + 3 * nsplit < K; k += 4 * nsplit) {
+        double v0[4], v1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v0[u] = (double)a0[(long long)(k + u * nsplit) * lda];
+          if (NM > 1) v1[u] = (double)a1[(long long)(k + u * nsplit) * lda];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double xv = x[(k + u * nsplit) * NR + r];
+            acc[0][r] += v0[u] * xv;
+            if (NM > 1) acc[NM - 1][r] += v1[u] * xv;
+          }
+      }
+      for (; k < K; k += nsplit) {
+        const double v0 = (double)a0[(long long)k * lda];
+        const double v1 = NM > 1 ? (double)a1[(long long)k * lda] : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double xv = x[k * NR + r];
+          acc[0][r] += v0 * xv;
+          if (NM > 1) acc[NM - 1][r] += v1 * xv;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) part[((m * nsplit + j) * Rp + t) * NR + r] = acc[m][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NM * Rp * NR; e += kBlock) {
+      const int m = e / (Rp * NR), rem = e % (Rp * NR), tt = rem / NR, r = rem % NR;
+      if (rb + tt < R && r < nrhs) {
+        double s = 0.0;
+        for (int jj = 0; jj < nsplit; ++jj) s += part[((m * nsplit + jj) * Rp + tt) * NR + r];
+        out[(m * R + rb + tt) * NR + r] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// sum over owners of a local Delta vector, for all Delta points of subdomain i
+// into xs[k*NR + r] (LDS); optionally mixes two vectors (theta*A + (1-theta)*B)
+template <int NR>
+__device__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2g, int d0,
+                          int nd, const double* A, const double* B, double ca, double cb, int sumD, int nrhs,
+                          double* xs) {
+  for (int e = threadIdx.x; e < nd * NR; e += kBlock) {
+    const int k = e / NR, r = e % NR;
+    double v = 0.0;
+    if (r < nrhs) {
+      const int g = l2g[d0 + k];
+      double sa = 0.0, sb = 0.0;
+      for (int o = own_ptr[g]; o < own_ptr[g + 1]; ++o) {
+        const int sl = own_slot[o];
+        sa += ld_co(&A[(size_t)r * sumD + sl]);
+        if (B) sb += ld_co(&B[(size_t)r * sumD + sl]);
+      }
+      v = B ? ca * sa + cb * sb : sa;
+    }
+    xs[e] = v;
+  }
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
+  extern __shared__ double lds[];
+  __shared__ double red[kWaves];
+  __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR];
+  __shared__ double cor[2][4][NR];          // per corner: (mu, e) or (nu, -D nu)
+  const OpArgs<T>& a = f.a;
+  const unsigned nb = gridDim.x;
+  const int nrhs = f.nrhs;
+  const int nunits = a.N * f.S;
+  // LDS layout: inputs [max n_D][NR], outputs [2][max n_G][NR], partial sums
+  // [kBlock][2][NR], coarse right-hand side [2 nP] (one rhs at a time)
+  double* xs = lds;
+  double* ys = lds + f.lds_ys;
+  double* part = lds + f.lds_part;
+  double* cu = lds + f.lds_cu;
+  unsigned epoch = 0;                        // flags are zeroed before every launch
+  double* pb[2] = {f.p0, f.p1};
+
+  // ---- prologue: x = 0, partial r.r
+  for (int r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
+      const size_t e = (size_t)r * a.nD + g;
+      const double rv = ld_co(&f.r[e]);
+      f.x[e] = 0.0;
+      st_co(&f.p1[e], 0.0);
+      acc += rv * rv;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], acc);
+  }
+  flag_sync(f.flags, nb, ++epoch, f.err);
+
+  int it = 0;
+  for (;; ++it) {
+    // ---- reduce r.r, convergence test, beta (identical in every workgroup)
+    for (int r = 0; r < nrhs; ++r) {
+      double rr = 0.0;
+      for (int k = threadIdx.x; k < (int)nb; k += kBlock) rr += ld_co(&f.part[(size_t)(nrhs + r) * nb + k]);
+      rr = block_sum(rr, red);
+      if (threadIdx.x == 0) {
+        if (it == 0) {
+          sc_bb[r] = rr; sc_rr[r] = rr; sc_done[r] = (rr == 0.0) ? 1.0 : 0.0; sc_it[r] = 0; sc_beta[r] = 0.0;
+        } else if (sc_done[r] == 0.0) {
+          sc_beta[r] = sc_rr[r] > 0.0 ? rr / sc_rr[r] : 0.0;
+          sc_rr[r] = rr;
+          sc_it[r] += 1.0;
+        } else {
+          sc_beta[r] = 0.0;
+        }
+        if (sc_done[r] == 0.0 && (sqrt(sc_rr[r]) <= f.tol * sqrt(sc_bb[r]) || !(sc_rr[r] == sc_rr[r])))
+          sc_done[r] = 1.0;
+      }
+    }
+    __syncthreads();
+    bool all_done = true;
+    for (int r = 0; r < nrhs; ++r) all_done = all_done && sc_done[r] != 0.0;
+    if (all_done || it >= f.maxit) break;
+    double* pc = pb[it & 1];          // p of this iteration
+    const double* pp = pb[(it + 1) & 1];
+
+    // ---- A: p at the unit's Delta points, rows of [G; L](:, Delta) p
+    for (int u = blockIdx.x; u < nunits; u += nb) {
+      const int i = u / f.S, q = u % f.S;
+      const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
+      const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+      const int ng = np + nd;
+      for (int e = threadIdx.x; e < nd * NR; e += kBlock) {
+        const int k = e / NR, r = e % NR;
+        double v = 0.0;
+        if (r < nrhs) {
+          const int g = a.dl_l2g[d0 + k];
+          const size_t ge = (size_t)r * a.nD + g;
+          v = ld_co(&f.r[ge]) + sc_beta[r] * ld_co(&pp[ge]);
+          if (q == 0 && a.dl_own_slot[a.dl_own_ptr[g]] == d0 + k) st_co(&pc[ge], v);
+        }
+        xs[e] = v;
+      }
+      __syncthreads();
+      int r0, r1;
+      slice_rows(ng, f.S, q, r0, r1);
+      mv_rows<T, NR, 2>(a.Gm + a.offG[i], a.Lm + a.offG[i], ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
+      for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
+        const int tt = e / NR, r = e % NR;
+        if (r >= nrhs) continue;
+        const int row = r0 + tt;
+        const double sg = ys[(0 * (r1 - r0) + tt) * NR + r], sl = ys[(1 * (r1 - r0) + tt) * NR + r];
+        if (row < np) {
+          st_co(&a.rho_loc[(size_t)r * a.sumP + p0 + row], sg);
+          st_co(&a.psi_loc[(size_t)r * a.sumP + p0 + row], sl);
+        } else {
+          st_co(&a.s_loc[(size_t)r * a.sumD + d0 + row - np], sg);
+          st_co(&a.l_loc[(size_t)r * a.sumD + d0 + row - np], sl);
+        }
+      }
+      __syncthreads();
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+
+    // ---- B: coarse solve at the corners, lam rows
+    for (int u = blockIdx.x; u < nunits; u += nb) {
+      const int i = u / f.S, q = u % f.S;
+      const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
+      const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+      const int ng = np + nd;
+      if (np > 0) {
+        for (int r = 0; r < nrhs; ++r) {
+          for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o) {
+              const int sl = a.pi_own_slot[o];
+              s1 += ld_co(&a.rho_loc[(size_t)r * a.sumP + sl]);
+              s2 += ld_co(&a.psi_loc[(size_t)r * a.sumP + sl]);
+            }
+            cu[pq] = s1;
+            cu[a.nP + pq] = s2;
+          }
+          __syncthreads();
+          // 2*np dot products of length 2 nP, one wave each (round robin)
+          const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+          for (int dd = wid; dd < 2 * np; dd += kWaves) {
+            const int b = dd >> 1, kind = dd & 1;
+            const int row = (kind ? a.nP : 0) + a.pi_l2g[p0 + b];
+            double s = 0.0;
+            for (int c = lane; c < 2 * a.nP; c += 64) s += a.X1[(long long)c * 2 * a.nP + row] * cu[c];
+            s = wave_sum(s);
+            if (lane == 0) cor[kind][b][r] = s;
+          }
+          __syncthreads();
+        }
+        if (q == 0) {
+          for (int e = threadIdx.x; e < np * nrhs; e += kBlock) {
+            const int b = e / nrhs, r = e % nrhs;
+            st_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r]);
+            st_co(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r]);
+          }
+        }
+      }
+      int r0, r1;
+      slice_rows(nd, f.S, q, r0, r1);
+      const T* L = a.Lm + a.offG[i];
+      for (int e = threadIdx.x; e < (r1 - r0) * nrhs; e += kBlock) {
+        const int tt = e / nrhs, r = e % nrhs;
+        const int row = r0 + tt;
+        double acc = ld_co(&a.l_loc[(size_t)r * a.sumD + d0 + row]);
+        for (int b = 0; b < np; ++b) acc -= (double)L[(long long)b * ng + np + row] * cor[0][b][r];
+        st_co(&a.lam_loc[(size_t)r * a.sumD + d0 + row], acc);
+      }
+      __syncthreads();
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+
+    if (a.theta != 0.0) {
+      // ---- C: y = -N lambda rows
+      for (int u = blockIdx.x; u < nunits; u += nb) {
+        const int i = u / f.S, q = u % f.S;
+        const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD,
+                      nrhs, xs);
+        __syncthreads();
+        int r0, r1;
+        slice_rows(nd, f.S, q, r0, r1);
+        mv_rows<T, NR, 1>(a.Nm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
+        for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
+          const int tt = e / NR, r = e % NR;
+          if (r < nrhs) st_co(&a.y_loc[(size_t)r * a.sumD + d0 + r0 + tt], -ys[tt * NR + r]);
+        }
+        __syncthreads();
+      }
+      flag_sync(f.flags, nb, ++epoch, f.err);
+      // ---- D: z = -N^T (P lambda) rows
+      for (int u = blockIdx.x; u < nunits; u += nb) {
+        const int i = u / f.S, q = u % f.S;
+        const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.y_loc, nullptr, 1.0, 0.0, a.sumD,
+                      nrhs, xs);
+        __syncthreads();
+        int r0, r1;
+        slice_rows(nd, f.S, q, r0, r1);
+        mv_rows<T, NR, 1>(a.NTm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
+        for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
+          const int tt = e / NR, r = e % NR;
+          if (r < nrhs) st_co(&a.z_loc[(size_t)r * a.sumD + d0 + r0 + tt], -ys[tt * NR + r]);
+        }
+        __syncthreads();
+      }
+      flag_sync(f.flags, nb, ++epoch, f.err);
+    }
+
+    // ---- E: eta, rows of L^T(:, Delta) eta
+    for (int u = blockIdx.x; u < nunits; u += nb) {
+      const int i = u / f.S, q = u % f.S;
+      const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
+      const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+      const int ng = np + nd;
+      if (a.theta != 0.0)
+        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.z_loc, a.lam_loc, a.theta,
+                      1.0 - a.theta, a.sumD, nrhs, xs);
+      else
+        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD,
+                      nrhs, xs);
+      __syncthreads();
+      int r0, r1;
+      slice_rows(ng, f.S, q, r0, r1);
+      mv_rows<T, NR, 1>(a.LTm + a.offG[i], nullptr, ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
+      for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
+        const int tt = e / NR, r = e % NR;
+        if (r >= nrhs) continue;
+        const int row = r0 + tt;
+        if (row < np) st_co(&a.nu_loc[(size_t)r * a.sumP + p0 + row], ys[tt * NR + r]);
+        else st_co(&a.t_loc[(size_t)r * a.sumD + d0 + row - np], ys[tt * NR + r]);
+      }
+      __syncthreads();
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+
+    // ---- F: coarse nu at the corners, w rows
+    for (int u = blockIdx.x; u < nunits; u += nb) {
+      const int i = u / f.S, q = u % f.S;
+      const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
+      const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+      const int ng = np + nd;
+      if (np > 0) {
+        for (int r = 0; r < nrhs; ++r) {
+          for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
+            double s1 = 0.0;
+            for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o)
+              s1 += ld_co(&a.nu_loc[(size_t)r * a.sumP + a.pi_own_slot[o]]);
+            cu[pq] = s1;
+          }
+          __syncthreads();
+          const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+          for (int dd = wid; dd < 2 * np; dd += kWaves) {
+            const int b = dd >> 1, kind = dd & 1;
+            const int row = (kind ? a.nP : 0) + a.pi_l2g[p0 + b];
+            double s = 0.0;
+            for (int c = lane; c < a.nP; c += 64) s += a.X1[(long long)c * 2 * a.nP + row] * cu[c];
+            s = wave_sum(s);
+            if (lane == 0) cor[kind][b][r] = s;
+          }
+          __syncthreads();
+        }
+      }
+      int r0, r1;
+      slice_rows(nd, f.S, q, r0, r1);
+      const T* G = a.Gm + a.offG[i];
+      const T* LT = a.LTm + a.offG[i];
+      for (int e = threadIdx.x; e < (r1 - r0) * nrhs; e += kBlock) {
+        const int tt = e / nrhs, r = e % nrhs;
+        const int row = r0 + tt;
+        double acc = ld_co(&a.s_loc[(size_t)r * a.sumD + d0 + row]) + ld_co(&a.t_loc[(size_t)r * a.sumD + d0 + row]);
+        for (int b = 0; b < np; ++b) {
+          const double mu = ld_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b]);
+          const double ee = ld_co(&f.e_slot[(size_t)r * a.sumP + p0 + b]);
+          acc -= (double)G[(long long)b * ng + np + row] * (mu + cor[0][b][r]);
+          acc += (double)LT[(long long)b * ng + np + row] * (ee + cor[1][b][r]);
+        }
+        st_co(&a.w_loc[(size_t)r * a.sumD + d0 + row], acc);
+      }
+      __syncthreads();
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+
+    // ---- G: w = sum of owners, partial p.w
+    for (int r = 0; r < nrhs; ++r) {
+      double acc = 0.0;
+      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
+        double wv = 0.0;
+        for (int o = a.dl_own_ptr[g]; o < a.dl_own_ptr[g + 1]; ++o)
+          wv += ld_co(&a.w_loc[(size_t)r * a.sumD + a.dl_own_slot[o]]);
+        f.w[(size_t)r * a.nD + g] = wv;
+        acc += wv * ld_co(&pc[(size_t)r * a.nD + g]);
+      }
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], acc);
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+
+    // ---- H: alpha, x and r updates, partial r.r
+    for (int r = 0; r < nrhs; ++r) {
+      double pw = 0.0;
+      for (int k = threadIdx.x; k < (int)nb; k += kBlock) pw += ld_co(&f.part[(size_t)r * nb + k]);
+      pw = block_sum(pw, red);
+      const double al = (sc_done[r] != 0.0 || pw == 0.0) ? 0.0 : sc_rr[r] / pw;
+      double acc = 0.0;
+      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
+        const size_t e = (size_t)r * a.nD + g;
+        f.x[e] += al * ld_co(&pc[e]);
+        const double rv = ld_co(&f.r[e]) - al * f.w[e];
+        st_co(&f.r[e], rv);
+        acc += rv * rv;
+      }
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], acc);
+    }
+    flag_sync(f.flags, nb, ++epoch, f.err);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int r = 0; r < nrhs; ++r) {
+      double* sc = f.scal + (size_t)r * 8;
+      sc[0] = sc_rr[r]; sc[1] = sc_bb[r]; sc[5] = sc_done[r]; sc[6] = sc_it[r];
+      sc[7] = (sc_rr[r] == sc_rr[r]) ? 0.0 : 1.0;
+      sc[2] = (double)epoch;
+    }
+  }
+}
+
+}  // namespace ddelm

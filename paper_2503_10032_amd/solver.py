@@ -137,6 +137,13 @@ class DDELMSolver:
         self._check(self.lib.ddelm_get_interface_points(self.ctx, xp.data_ptr(), xd.data_ptr()), "get_interface_points")
         return xp[: self.n_pi], xd[: self.n_dl]
 
+    def phase_times(self):
+        """Device-timeline ms of the last factor/solve phases (see ddelm_get_phase_times)."""
+        ms = np.zeros(8)
+        self._check(self.lib.ddelm_get_phase_times(self.ctx, ms.ctypes.data_as(L.c_double_p)), "get_phase_times")
+        keys = ("assemble", "qr", "local_ops", "coarse", "rhs", "cg", "recover")
+        return {k: float(ms[i]) for i, k in enumerate(keys)}
+
     def local_matrix(self, which: int, sub: int = 0) -> torch.Tensor:
         r, c = ctypes.c_int(), ctypes.c_int()
         self._check(self.lib.ddelm_get_local_matrix(self.ctx, which, sub, None, ctypes.byref(r), ctypes.byref(c)),
