@@ -16,6 +16,7 @@
 #include "kernels_setup.hpp"
 #include "kernels_solve.hpp"
 #include "kernels_cg.hpp"
+#include "kernels_qr.hpp"
 
 using namespace ddelm;
 
@@ -78,6 +79,44 @@ struct RowSetDev {
   }
 };
 
+// Device copies of small per-call descriptor arrays: one device buffer and one
+// pinned host staging buffer, filled by a bump pointer and reset at the start
+// of every API call (the previous call has drained the stream).
+struct Arena {
+  char* dev = nullptr;
+  char* host = nullptr;
+  size_t cap = 0, used = 0;
+  void ensure(size_t c) {
+    if (c <= cap) return;
+    release();
+    HIPCHK(hipMalloc((void**)&dev, c));
+    HIPCHK(hipHostMalloc((void**)&host, c, hipHostMallocDefault));
+    cap = c;
+  }
+  void release() {
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    dev = host = nullptr;
+    cap = used = 0;
+  }
+  void reset() { used = 0; }
+  template <typename T>
+  T* put(const T* data, size_t n, hipStream_t s) {
+    const size_t bytes = n * sizeof(T);
+    const size_t off = (used + 255) & ~size_t(255);
+    if (off + bytes > cap) throw StatusError{DDELM_E_NOMEM, "descriptor arena exhausted"};
+    if (bytes) {
+      std::memcpy(host + off, data, bytes);
+      HIPCHK(hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, s));
+    }
+    used = off + bytes;
+    return reinterpret_cast<T*>(dev + off);
+  }
+  template <typename T>
+  T* put(const std::vector<T>& v, hipStream_t s) { return put(v.data(), v.size(), s); }
+  ~Arena() { release(); }
+};
+
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
@@ -103,7 +142,8 @@ struct ddelm_ctx_s {
   std::vector<long long> h_offm;     // offsets into packed row space (sum m)
   long long summ = 0;
   // QR: 2N matrices (K_c then Kbar), fp64
-  DBuf<double> qrA, tau;
+  DBuf<double> qrA, tau, Tbuf;
+  int npanel = 0;
   DBuf<QRDesc> qrdesc;
   std::vector<QRDesc> h_qrdesc;
   int max_ncols = 0;
@@ -133,6 +173,8 @@ struct ddelm_ctx_s {
   int cg_blocks = 0, cg_slices = 0;
   DBuf<unsigned> bar;
   DBuf<int> sizes_dev;                 // per subdomain M, n_I, n_B, m, n_G
+  Arena arena;
+  DBuf<long long> offm_d, offB_d, offQG_d, offAm_d;
   // phase timing (HIP events on the stream)
   hipEvent_t ev[10] = {};
   double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -187,6 +229,18 @@ void launch_qr_panel(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T
 }
 
 template <typename T>
+void launch_qr_panel16(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
+                       int npanel) {
+  switch (rpt) {
+#define CASE(R) case R: k_qr_panel16<T, R><<<grid, kPanelThreads, 0, s>>>(d, A, tau, Tb, k, panel, npanel); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+    default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
 void launch_qr_apply(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, const T* A, const T* tau, int j0, int j1,
                      T* C, const long long* coff, const int* ldc, const int* cn, int c0, int reverse) {
   switch (rpt) {
@@ -199,32 +253,28 @@ void launch_qr_apply(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, const T
 }
 
 template <typename T>
-void gemm_batch(hipStream_t s, const std::vector<GemmDesc>& h, const T* A, const T* B, T* C, int transA, double alpha,
+void gemm_batch(ddelm_ctx c, const std::vector<GemmDesc>& h, const T* A, const T* B, T* C, int transA, double alpha,
                 double beta) {
   if (h.empty()) return;
   int mm = 0, nn = 0;
   for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
   if (mm == 0 || nn == 0) return;
-  DBuf<GemmDesc> d;
-  d.upload(h, s);
+  const GemmDesc* d = c->arena.put(h, c->stream);
   dim3 grid(ceil_div(mm, 16), ceil_div(nn, 16), (unsigned)h.size());
-  k_gemm<T, T><<<grid, kBlock, 0, s>>>(d.p, A, B, C, transA, alpha, beta);
+  k_gemm<T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));   // descriptor buffer is freed on return
 }
 
 template <typename T>
-void copy_batch(hipStream_t s, const std::vector<CopyDesc>& h, const T* S, T* D) {
+void copy_batch(ddelm_ctx c, const std::vector<CopyDesc>& h, const T* S, T* D) {
   if (h.empty()) return;
   long long mx = 0;
-  for (auto& c : h) mx = std::max(mx, (long long)c.rows * c.cols);
+  for (auto& cd : h) mx = std::max(mx, (long long)cd.rows * cd.cols);
   if (mx == 0) return;
-  DBuf<CopyDesc> d;
-  d.upload(h, s);
+  const CopyDesc* d = c->arena.put(h, c->stream);
   dim3 grid(std::min(ceil_div(mx, kBlock), 1024), (unsigned)h.size());
-  k_copy2d<T, T><<<grid, kBlock, 0, s>>>(d.p, S, D);
+  k_copy2d<T, T><<<grid, kBlock, 0, c->stream>>>(d, S, D);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(s));
 }
 
 void fill(hipStream_t s, double* p, long long n, double v) {
@@ -239,18 +289,13 @@ int rows_per_thread(int m) { return ceil_div(m, kBlock); }
 void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, double* out, const std::vector<long long>& off,
                        const std::vector<int>& ld, int sub0, int nsub) {
   if (max_rows == 0 || nsub == 0) return;
-  DBuf<long long> d_off;
-  DBuf<int> d_ld;
-  d_off.upload(off, c->stream);
-  d_ld.upload(ld, c->stream);
   FeatArgs a;
   a.row0 = rs.row0.p; a.ptr = rs.ptr.p; a.terms = rs.terms.p;
   a.W = c->W.p; a.bias = c->b.p; a.geom = c->geom.p;
-  a.off = d_off.p; a.ld = d_ld.p; a.M = c->M; a.sub0 = sub0;
+  a.off = c->arena.put(off, c->stream); a.ld = c->arena.put(ld, c->stream); a.M = c->M; a.sub0 = sub0;
   dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
   k_features<double><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->stream));
 }
 
 OpArgs<double> op_args(ddelm_ctx c, int nrhs) {
@@ -652,7 +697,7 @@ void launch_fused(ddelm_ctx c, int nrhs) {
   f.a = op_args(c, nrhs);
   int S = 1;
   if (const char* env = getenv("DDELM_CG_SLICES")) S = std::max(1, std::min(8, atoi(env)));
-  else if (c->N < 32) S = std::max(1, std::min(4, 64 / std::max(c->N, 1)));
+  else S = std::max(1, std::min(4, 128 / std::max(c->N, 1)));
   f.S = S;
   f.nrhs = nrhs;
   f.tol = c->opt.tol;
@@ -793,6 +838,11 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     c->pi_slot_sub.upload(slot_sub, s);
     std::vector<int> nGv(c->h_nG);
     c->nG_dev.upload(nGv, s);
+    {
+      long long units = 0;
+      for (int i = 0; i < N; ++i) units += c->h_nG[i] + c->h_nD[i];
+      c->arena.ensure((size_t)(1 << 20) + (size_t)N * 1024 + (size_t)units * 16);
+    }
     c->flags.alloc(8);
     c->flags.zero(s);
     c->bar.alloc((size_t)4096 * kFlagStride);
@@ -816,6 +866,8 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
     const int N = c->N, M = c->M;
     const Geometry& g = c->geo;
     const bool nn = c->use_nn;
+    HIPCHK(hipStreamSynchronize(s));
+    c->arena.reset();
     const int nmat = nn ? 2 * N : N;
     // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
     c->h_qrdesc.assign(nmat, QRDesc());
@@ -881,26 +933,28 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
         for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
       }
       if (!pos.empty()) {
-        DBuf<long long> dp;
-        dp.upload(pos, s);
-        k_set_units<<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp.p, (long long)pos.size(), c->qrA.p);
+        const long long* dp = c->arena.put(pos, s);
+        k_set_units<<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), c->qrA.p);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s));
       }
     }
     c->mark(1);
-    // ---- blocked Householder QR of all matrices, panel width kTW
+    // ---- blocked Householder QR of all matrices: 16-column panels, WY updates on MFMA
     {
       const int rpt = rows_per_thread(g.max_m);
-      for (int k = 0; k < M; k += kTW) {
-        launch_qr_panel<double>(rpt, dim3(nmat), s, c->qrdesc.p, c->qrA.p, c->tau.p, k);
-        const int c0 = k + kTW;
-        const int ntile = ceil_div(c->max_ncols - c0, kTW);
-        if (ntile > 0)
-          launch_qr_apply<double>(rpt, dim3(nmat, ntile), s, c->qrdesc.p, c->qrA.p, c->tau.p, k, k + kTW, c->qrA.p,
-                                  c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 0);
+      c->npanel = ceil_div(M, kNB);
+      c->Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
+      for (int p = 0; p < c->npanel; ++p) {
+        const int k = p * kNB;
+        launch_qr_panel16<double>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, c->qrA.p, c->tau.p, c->Tbuf.p, k, p, c->npanel);
+        const int c0 = k + std::min(kNB, M - k);
+        const int ntile = ceil_div(c->max_ncols - c0, kUC);
+        if (ntile > 0) {
+          k_qr_wy<double><<<dim3(nmat, ntile), kBlock, 0, s>>>(c->qrdesc.p, c->qrA.p, c->Tbuf.p, k, p, c->npanel,
+                                                               c->qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
+          HIPCHK(hipGetLastError());
+        }
       }
-      HIPCHK(hipStreamSynchronize(s));
     }
     c->mark(2);
     // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T in place, Xbar = Rbar^{-1} Qbar_D^T in place
@@ -914,7 +968,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
         if (c->h_nG[i] == 0) continue;
         cp.push_back(CopyDesc{d.off + (long long)M * d.ld, c->h_offQG[i], d.ld, M, M, c->h_nG[i], 0, 0});
       }
-      copy_batch<double>(s, cp, c->qrA.p, c->QG.p);
+      copy_batch<double>(c, cp, c->qrA.p, c->QG.p);
       // triangular solves on the appended columns
       std::vector<long long> xoff(nmat);
       std::vector<int> ldx(nmat), xn(nmat);
@@ -927,15 +981,14 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
         maxx = std::max(maxx, xn[b]);
       }
       if (maxx > 0) {
-        DBuf<long long> dxo;
-        DBuf<int> dld, dxn;
-        dxo.upload(xoff, s); dld.upload(ldx, s); dxn.upload(xn, s);
+        const long long* dxo = c->arena.put(xoff, s);
+        const int* dld = c->arena.put(ldx, s);
+        const int* dxn = c->arena.put(xn, s);
         const size_t smt = (size_t)M * kTRSMC * sizeof(double);
         if (smt > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_trsm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smt));
-        k_trsm<double><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, c->qrA.p, c->qrA.p, dxo.p,
-                                                                               dld.p, dxn.p, 0);
+        k_trsm<double><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, c->qrA.p, c->qrA.p, dxo,
+                                                                               dld, dxn, 0);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s));
       }
     }
     // ---- local interface operators
@@ -969,42 +1022,36 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
           tN.push_back(CopyDesc{c->h_offN[i], c->h_offN[i], nd, nd, nd, nd, 1, 0});
         }
       }
-      gemm_batch<double>(s, gG, c->QG.p, c->QG.p, c->Gm.p, 1, -1.0, 0.0);
+      gemm_batch<double>(c, gG, c->QG.p, c->QG.p, c->Gm.p, 1, -1.0, 0.0);
       {
         std::vector<long long> o;
         std::vector<int> n;
         for (int i = 0; i < N; ++i) if (c->h_nG[i]) { o.push_back(c->h_offG[i]); n.push_back(c->h_nG[i]); }
         if (!o.empty()) {
-          DBuf<long long> dO; DBuf<int> dn;
-          dO.upload(o, s); dn.upload(n, s);
-          k_add_diag<<<(unsigned)o.size(), kBlock, 0, s>>>(dO.p, dn.p, c->Gm.p, 1.0);
+          const long long* dO = c->arena.put(o, s);
+          const int* dn = c->arena.put(n, s);
+          k_add_diag<<<(unsigned)o.size(), kBlock, 0, s>>>(dO, dn, c->Gm.p, 1.0);
           HIPCHK(hipGetLastError());
-          HIPCHK(hipStreamSynchronize(s));
         }
       }
       // A_m and E live in different buffers: run the GEMM with A = Am, B = qrA
       if (!gL.empty()) {
         int mm = 0, nn2 = 0;
         for (auto& q : gL) { mm = std::max(mm, q.m); nn2 = std::max(nn2, q.n); }
-        DBuf<GemmDesc> dd;
-        dd.upload(gL, s);
-        // k_gemm takes A and B from separate pointers through the descriptor offsets
+        const GemmDesc* dd = c->arena.put(gL, s);
         k_gemm<double, double><<<dim3(ceil_div(mm, 16), ceil_div(nn2, 16), (unsigned)gL.size()), kBlock, 0, s>>>(
-            dd.p, c->Am.p, c->qrA.p, c->Lm.p, 0, 1.0, 0.0);
+            dd, c->Am.p, c->qrA.p, c->Lm.p, 0, 1.0, 0.0);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s));
       }
-      copy_batch<double>(s, tL, c->Lm.p, c->LTm.p);
+      copy_batch<double>(c, tL, c->Lm.p, c->LTm.p);
       if (!gN.empty()) {
         int mm = 0, nn2 = 0;
         for (auto& q : gN) { mm = std::max(mm, q.m); nn2 = std::max(nn2, q.n); }
-        DBuf<GemmDesc> dd;
-        dd.upload(gN, s);
+        const GemmDesc* dd = c->arena.put(gN, s);
         k_gemm<double, double><<<dim3(ceil_div(mm, 16), ceil_div(nn2, 16), (unsigned)gN.size()), kBlock, 0, s>>>(
-            dd.p, c->CD.p, c->qrA.p, c->Nm.p, 0, 1.0, 0.0);
+            dd, c->CD.p, c->qrA.p, c->Nm.p, 0, 1.0, 0.0);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s));
-        copy_batch<double>(s, tN, c->Nm.p, c->NTm.p);
+        copy_batch<double>(c, tN, c->Nm.p, c->NTm.p);
       }
     }
     c->mark(3);
@@ -1021,24 +1068,20 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
                                                                        c->Dpp.p, c->Gs.p);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(c->Spi.p, c->Gs.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      gemm_batch<double>(s, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Dpp.p, c->Spi.p, 1, 1.0, 1.0);
+      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Dpp.p, c->Spi.p, 1, 1.0, 1.0);
       HIPCHK(hipMemcpyAsync(c->Sfac.p, c->Spi.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemsetAsync(c->flags.p, 0, 8 * sizeof(unsigned), s));
       k_cholesky<<<1, kBlock, 0, s>>>(c->Sfac.p, n, c->flags.p);
       HIPCHK(hipGetLastError());
-      unsigned fl[8];
-      HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (fl[0] & 2u) c->fail(DDELM_E_CHOLESKY, "S_Pi is not positive definite");
       const size_t smi = (size_t)n * 4 * sizeof(double);
       if (smi > 160 * 1024) c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
       if (smi > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smi));
       k_chol_inverse<<<ceil_div(n, 4), kBlock, smi, s>>>(c->Sfac.p, n, c->Sinv.p);
       HIPCHK(hipGetLastError());
       // Z = D Sinv, Zt = Z^T, W = D Zt, X1
-      gemm_batch<double>(s, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Sinv.p, c->Zm.p, 0, 1.0, 0.0);
-      copy_batch<double>(s, {CopyDesc{0, 0, n, n, n, n, 1, 0}}, c->Zm.p, c->Ztm.p);
-      gemm_batch<double>(s, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Ztm.p, c->Wm.p, 0, 1.0, 0.0);
+      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Sinv.p, c->Zm.p, 0, 1.0, 0.0);
+      copy_batch<double>(c, {CopyDesc{0, 0, n, n, n, n, 1, 0}}, c->Zm.p, c->Ztm.p);
+      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Ztm.p, c->Wm.p, 0, 1.0, 0.0);
       k_assemble_X1<<<std::min(ceil_div(4ll * nn2, kBlock), 4096), kBlock, 0, s>>>(n, c->Sinv.p, c->Zm.p, c->Wm.p,
                                                                                    c->X1.p);
       HIPCHK(hipGetLastError());
@@ -1046,7 +1089,15 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
       c->X1.alloc(1);
     }
     c->mark(4);
+    // offsets used by every solve
+    c->offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
+    c->offB_d.upload(std::vector<long long>(c->h_offB.begin(), c->h_offB.end() - 1), s);
+    c->offQG_d.upload(std::vector<long long>(c->h_offQG.begin(), c->h_offQG.end() - 1), s);
+    c->offAm_d.upload(std::vector<long long>(c->h_offAm.begin(), c->h_offAm.end() - 1), s);
+    unsigned fl[8];
+    HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (fl[0] & 2u) c->fail(DDELM_E_CHOLESKY, "S_Pi is not positive definite");
     for (int k = 0; k < 4; ++k) c->phase_ms[k] = c->span(k, k + 1);
     c->factored = true;
   });
@@ -1066,36 +1117,38 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
     const int N = c->N, M = c->M;
     alloc_solve_workspace(c, nrhs);
     auto t0 = std::chrono::steady_clock::now();
+    c->arena.reset();
     c->mark(5);
-    DBuf<long long> offm_d, offB_d;
-    offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
-    offB_d.upload(std::vector<long long>(c->h_offB.begin(), c->h_offB.end() - 1), s);
+    const DBuf<long long>& offm_d = c->offm_d;
+    const DBuf<long long>& offB_d = c->offB_d;
     // ---- f, Q^T f, projections, K^+ f, fluxes
     k_rhs_assemble<<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, offm_d.p, offB_d.p, c->summ,
                                                      c->geo.sum_nB, f_I, g_B, c->F.p);
     HIPCHK(hipGetLastError());
     const int rpt = rows_per_thread(c->geo.max_m);
-    launch_qr_apply<double>(rpt, dim3(N, ceil_div(nrhs, kTW)), s, c->qrdesc.p, c->qrA.p, c->tau.p, 0, M, c->F.p,
-                            c->f_off.p, c->f_ld.p, c->f_cn.p, 0, 0);
-    DBuf<long long> offQG_d, offAm_d;
-    offQG_d.upload(std::vector<long long>(c->h_offQG.begin(), c->h_offQG.end() - 1), s);
-    offAm_d.upload(std::vector<long long>(c->h_offAm.begin(), c->h_offAm.end() - 1), s);
+    for (int p = 0; p < c->npanel; ++p) {
+      k_qr_wy<double><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, c->qrA.p, c->Tbuf.p, p * kNB, p,
+                                                                      c->npanel, c->F.p, c->f_off.p, c->f_ld.p,
+                                                                      c->f_cn.p, 0, 1);
+      HIPCHK(hipGetLastError());
+    }
+    (void)rpt;
+    const DBuf<long long>& offQG_d = c->offQG_d;
+    const DBuf<long long>& offAm_d = c->offAm_d;
     k_rhs_proj<<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
                                                                   offQG_d.p, c->QG.p, offm_d.p, c->summ, c->F.p,
                                                                   c->sumP, c->sumD, c->rho_loc.p, c->s_loc.p);
     HIPCHK(hipGetLastError());
     {
       const size_t smt = (size_t)M * kTRSMC * sizeof(double);
-      DBuf<int> cnM;
-      cnM.upload(std::vector<int>(N, nrhs), s);
+      const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
       k_trsm<double><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, c->qrA.p, c->F.p, c->f_off.p,
-                                                                          c->f_ld.p, cnM.p, 0);
+                                                                          c->f_ld.p, cnM, 0);
       HIPCHK(hipGetLastError());
       k_rhs_flux<<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
                                                                     offAm_d.p, c->Am.p, offm_d.p, c->summ, c->F.p,
                                                                     c->sumP, c->sumD, c->psi_loc.p, c->l_loc.p);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(s));
     }
     // ---- b of eq. nn-mixed
     OpArgs<double> a = op_args(c, nrhs);
@@ -1264,6 +1317,8 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
     *rows = R; *cols = C;
     if (!out || R == 0 || C == 0) return;
     hipStream_t s = c->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    c->arena.reset();
     DBuf<double> tmp;
     tmp.alloc((size_t)R * C);
     tmp.zero(s);
@@ -1277,14 +1332,15 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
       assemble_features(c, rs, R, tmp.p, o, l, sub, 1);
       src = tmp.p; soff = 0; ld = R;
       // column-major R x C -> row-major output
-      copy_batch<double>(s, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, src, out);
+      copy_batch<double>(c, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, src, out);
+      HIPCHK(hipStreamSynchronize(s));
       return;
     }
     if (!c->factored) c->fail(DDELM_E_STATE, "matrix needs ddelm_factor");
     if (which == 4) {
       const QRDesc& d = c->h_qrdesc[sub];
-      copy_batch<double>(s, {CopyDesc{d.off, 0, d.ld, C, R, C, 1, 0}}, c->qrA.p, out);
-      // zero the strictly lower part on the host side is left to the caller
+      copy_batch<double>(c, {CopyDesc{d.off, 0, d.ld, C, R, C, 1, 0}}, c->qrA.p, out);
+      HIPCHK(hipStreamSynchronize(s));
       return;
     }
     if (which == 5) { src = c->Gm.p; soff = c->h_offG[sub]; }
@@ -1294,7 +1350,8 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
       src = c->Nm.p; soff = c->h_offN[sub];
     }
     if (which == 8) src = c->Spi.p;
-    copy_batch<double>(s, {CopyDesc{soff, 0, R, R, R, C, 1, 0}}, src, out);
+    copy_batch<double>(c, {CopyDesc{soff, 0, R, R, R, C, 1, 0}}, src, out);
+    HIPCHK(hipStreamSynchronize(s));
   });
 }
 

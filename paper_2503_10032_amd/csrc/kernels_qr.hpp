@@ -1,0 +1,281 @@
+// Blocked Householder QR with compact-WY updates on the matrix cores.
+//
+// Panels are 16 columns wide.  The panel kernel factors 16 columns held in
+// registers and builds the upper-triangular T of the block reflector
+//   H_k H_{k+1} ... H_{k+15} = I - V T V^T            (forward, columnwise)
+// The update kernel then applies the block reflector to any set of columns,
+//   C <- (I - V T^T V^T) C  (Q^T C)   or   C <- (I - V T V^T) C  (Q C),
+// as W = V^T C, W <- T^T W (or T W), C <- C - V W, with both products on
+// 16x16x4 MFMA (f64 or f32).  V^T C contracts over rows, which are
+// contiguous in the column-major storage, so the operands of that product
+// are staged through LDS; C - V W is computed transposed (rows along the
+// lanes) straight from global memory.
+#pragma once
+#include "kernels_common.hpp"
+#include "kernels_setup.hpp"
+
+namespace ddelm {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element v of lane l holds D[drow(l, v)][l & 15]
+  __device__ static __forceinline__ int drow(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int drow(int l, int v) { return 4 * (l >> 4) + v; }
+};
+// Operands: lane l supplies A[l & 15][l >> 4] and B[l >> 4][l & 15].
+
+constexpr int kNB = 16;   // panel width
+
+// element (row, j) of the block reflector V of panel k of matrix Am (rows
+// relative to the matrix): 0 above the diagonal, 1 on it, stored below it
+template <typename T>
+__device__ __forceinline__ T v_elem(const T* Am, int ld, int m, int k, int row, int j) {
+  const int rr = row - k;
+  if (row >= m || rr < j) return T(0);
+  if (rr == j) return T(1);
+  return Am[(long long)(k + j) * ld + row];
+}
+
+// ---------------------------------------------------------------- panel
+// One workgroup of kPanelThreads threads per matrix; rows k + tid + q*kPanelThreads.
+constexpr int kPanelThreads = 512;
+constexpr int kPanelWaves = kPanelThreads / 64;
+
+template <typename T, int RPT>
+__global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __restrict__ desc, T* __restrict__ A,
+                                                              T* __restrict__ tau, T* __restrict__ Tbuf, int k,
+                                                              int panel, int npanel) {
+  const QRDesc d = desc[blockIdx.x];
+  if (k >= d.nrefl) return;
+  __shared__ T red[kPanelWaves * kNB + kNB];
+  __shared__ T rowj[kNB];
+  __shared__ T Ts[kNB][kNB];
+  T* Am = A + d.off;
+  const int ncol = min(kNB, d.nrefl - k);
+  for (int e = threadIdx.x; e < kNB * kNB; e += kPanelThreads) Ts[e / kNB][e % kNB] = T(0);
+  T a[RPT][kNB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kPanelThreads;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
+  }
+  // One reduction per column.  With x the current column below the diagonal
+  // (rows r > j), alpha = x_j and s = 1/(alpha - beta), v_j = [1; s x] and
+  //   v_j . a_c = a_c[j] + s sum_{r>j} x_r a_c[r]        (c > jj, applies H_j)
+  //   v_c . v_j = v_c[j] + s sum_{r>j} x_r v_c[r]        (c < jj, builds T)
+  // so the squared norm of x (slot jj) and the 15 sums share one reduction.
+  for (int jj = 0; jj < ncol; ++jj) {
+    const int j = k + jj;
+    T part[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) part[c] = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kPanelThreads;
+      T x = T(0);
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) if (c == jj) x = a[q][c];
+      if (r > j && r < d.m) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) part[c] += x * a[q][c];   // slot jj: x . x
+      }
+      if (r == j) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) rowj[c] = a[q][c];
+      }
+    }
+    T w[kNB];
+    block_sum_vec_w<T, kNB, kPanelWaves>(part, w, red);
+    T ss = 0;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) if (c == jj) ss = w[c];
+    T alpha = 0;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) if (c == jj) alpha = rowj[c];
+    T beta = alpha, tj = 0, scale = 0;
+    if (ss > T(0)) {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tj = (beta - alpha) / beta;
+      scale = T(1) / (alpha - beta);
+    }
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) w[c] = rowj[c] + scale * w[c];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = k + threadIdx.x + q * kPanelThreads;
+      if (r >= j && r < d.m) {
+        T x = T(0);
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) if (c == jj) x = a[q][c];
+        const T vj = (r == j) ? T(1) : x * scale;
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) {
+          if (c == jj) a[q][c] = (r == j) ? beta : vj;
+          else if (c > jj) a[q][c] -= tj * w[c] * vj;
+        }
+      }
+    }
+    // T(0:jj, jj) = -tau_j T(0:jj, 0:jj) z, z_c = v_c . v_j = w_c (c < jj); T(jj, jj) = tau_j
+    if (threadIdx.x < jj) {      // thread i forms T(i, jj)
+      const int i = threadIdx.x;
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < kNB; ++c)
+        if (c >= i && c < jj) s += Ts[i][c] * w[c];
+      Ts[i][jj] = -tj * s;
+    }
+    if (threadIdx.x == 0) {
+      Ts[jj][jj] = tj;
+      tau[d.tau + j] = tj;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kPanelThreads;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+      if (r < d.m && c < ncol) Am[(long long)(k + c) * d.ld + r] = a[q][c];
+  }
+  T* Tout = Tbuf + ((long long)blockIdx.x * npanel + panel) * kNB * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += kPanelThreads) Tout[e] = Ts[e / kNB][e % kNB];
+}
+
+// ---------------------------------------------------------------- block reflector application
+//
+// Target of matrix b: columns c0 + blockIdx.y*32 + (0..32) of C + coff[b]
+// (leading dimension ldc[b], cn[b] columns in total); rows k..m-1 change.
+// transT = 1 applies Q^T (I - V T^T V^T); transT = 0 applies Q (I - V T V^T).
+constexpr int kUC = 32;   // columns per workgroup
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                  const T* __restrict__ Tbuf, int k, int panel, int npanel,
+                                                  T* __restrict__ C, const long long* __restrict__ coff,
+                                                  const int* __restrict__ ldc, const int* __restrict__ cn, int c0,
+                                                  int transT) {
+  typedef typename Mfma<T>::v4 v4;
+  const QRDesc d = desc[blockIdx.x];
+  if (k >= d.nrefl) return;
+  const int cbeg = c0 + blockIdx.y * kUC;
+  const int ctot = cn[blockIdx.x];
+  if (cbeg >= ctot) return;
+  const int ncol = min(kUC, ctot - cbeg);
+  const int L = ldc[blockIdx.x];
+  const T* Am = A + d.off;
+  T* Cm = C + coff[blockIdx.x];
+  __shared__ T Vs[64][kNB + 1];
+  __shared__ T Cs[64][kUC + 1];
+  __shared__ T Wp[kWaves][kNB][kUC + 1];
+  __shared__ T Ts[kNB][kNB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const T* Tin = Tbuf + ((long long)blockIdx.x * npanel + panel) * kNB * kNB;
+  for (int e = threadIdx.x; e < kNB * kNB; e += kBlock) Ts[e / kNB][e % kNB] = Tin[e];
+  // ---- W = V^T C over rows k..m-1, 64-row chunks staged in LDS
+  v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int r0 = k; r0 < d.m; r0 += 64) {
+    // all loads of the chunk first (4 V and 8 C elements per thread), then the LDS stores
+    T vv[4], cc[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      vv[u] = v_elem(Am, d.ld, d.m, k, r0 + e % 64, e / 64);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int c = e / 64, row = r0 + e % 64;
+      cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      Vs[e % 64][e / 64] = vv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      Cs[e % 64][e / 64] = cc[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int rr = wv * 16 + ks * 4 + (lane >> 4);
+      const T av = Vs[rr][lane & 15];
+      acc0 = Mfma<T>::mma(av, Cs[rr][lane & 15], acc0);
+      acc1 = Mfma<T>::mma(av, Cs[rr][16 + (lane & 15)], acc1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = Mfma<T>::drow(lane, v);
+    Wp[wv][i][lane & 15] = acc0[v];
+    Wp[wv][i][16 + (lane & 15)] = acc1[v];
+  }
+  __syncthreads();
+  // W summed over waves into Wp[0]; then Wn = -T^T W (Q^T) or -T W (Q) into Wp[1]
+  for (int e = threadIdx.x; e < kNB * kUC; e += kBlock) {
+    const int i = e / kUC, c = e % kUC;
+    Wp[0][i][c] = Wp[0][i][c] + Wp[1][i][c] + Wp[2][i][c] + Wp[3][i][c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNB * kUC; e += kBlock) {
+    const int i = e / kUC, c = e % kUC;
+    T s = 0;
+    if (transT) {
+      for (int ip = 0; ip <= i; ++ip) s += Ts[ip][i] * Wp[0][ip][c];
+    } else {
+      for (int ip = i; ip < kNB; ++ip) s += Ts[i][ip] * Wp[0][ip][c];
+    }
+    Wp[1][i][c] = -s;
+  }
+  __syncthreads();
+  // ---- C^T <- C^T + Wn^T V^T for 16-row blocks (rows along the lanes)
+  for (int rb = k + wv * 16; rb < d.m; rb += kWaves * 16) {
+    const int row = rb + (lane & 15);
+    v4 acc[2];
+    T bv[4];
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = cg * 16 + Mfma<T>::drow(lane, v);
+        acc[cg][v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+      }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) bv[ks] = v_elem(Am, d.ld, d.m, k, row, ks * 4 + (lane >> 4));
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const T av = Wp[1][ks * 4 + (lane >> 4)][cg * 16 + (lane & 15)];
+        acc[cg] = Mfma<T>::mma(av, bv[ks], acc[cg]);
+      }
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = cg * 16 + Mfma<T>::drow(lane, v);
+        if (row < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + row] = acc[cg][v];
+      }
+  }
+}
+
+}  // namespace ddelm
