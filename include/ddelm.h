@@ -149,6 +149,21 @@ ddelm_status ddelm_factor(ddelm_ctx ctx);
 ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B,
                          double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats);
 
+/* Solve the coupled system of eq. ddelm with a general right-hand side
+ * [f; h]: f given on every local row (interior, boundary and interface rows,
+ * the interface rows in the K_c^i row space) and h on the flux rows of the
+ * interface points (Pi block then Delta block).  The result is the DDELM-NN
+ * solution for that right-hand side (d_Pi = h_Pi - A_Pi K^+ f and
+ * d~ = h_Delta - A~ K~^+ f~ in sec. 3).  Used by iterative refinement and by
+ * the adjoint.
+ *   f_loc [nrhs][sum m]            local right-hand sides, subdomain after subdomain
+ *   h     [nrhs][n_pi + n_dl]      may be NULL (zero)
+ *   coef, mu_pi, mu_dl, stats      as in ddelm_solve
+ * In mixed precision this call runs the float32 solve with the same
+ * refinement as ddelm_solve. */
+ddelm_status ddelm_solve_general(ddelm_ctx ctx, int nrhs, const double* f_loc, const double* h, double* coef,
+                                 double* mu_pi, double* mu_dl, ddelm_stats* stats);
+
 /* u(x) (and grad u if grad != NULL) on the lowest-index subdomain whose
  * closed box holds x.  coef [nrhs][N][M], x [npts][2], u [nrhs][npts],
  * grad [nrhs][npts][2].  Points outside the box are clamped to the nearest
@@ -159,7 +174,8 @@ ddelm_status ddelm_evaluate(ddelm_ctx ctx, int nrhs, const double* coef, long lo
 /* Sizes of the problem. */
 ddelm_status ddelm_get_sizes(ddelm_ctx ctx, ddelm_sizes* out);
 
-/* Host arrays [N]: boundary, Pi, Delta and row counts per subdomain. */
+/* Host arrays [N]: boundary, Pi, Delta and row counts per subdomain
+ * (m = rows of K_c^i; the local rows of f_loc in ddelm_solve_general). */
 ddelm_status ddelm_get_counts(ddelm_ctx ctx, int* n_B, int* n_P, int* n_D, int* m);
 
 /* Host arrays: global Pi indices of the local Pi points, subdomain by

@@ -61,6 +61,8 @@ SIGNATURES = {
     "ddelm_factor": (ctypes.c_int, [ctypes.c_void_p]),
     "ddelm_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ddelm_solve_general": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ddelm_evaluate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ddelm_get_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Sizes)]),

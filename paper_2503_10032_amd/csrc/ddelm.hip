@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ddelm.h"
@@ -17,6 +18,7 @@
 #include "kernels_solve.hpp"
 #include "kernels_cg.hpp"
 #include "kernels_qr.hpp"
+#include "kernels_rhs.hpp"
 
 using namespace ddelm;
 
@@ -69,16 +71,6 @@ struct DBuf {
   ~DBuf() { free(); }
 };
 
-struct RowSetDev {
-  DBuf<int> row0, ptr;
-  DBuf<Term> terms;
-  void upload(const RowSet& r, hipStream_t s) {
-    row0.upload(r.row0, s);
-    ptr.upload(r.ptr, s);
-    terms.upload(r.terms, s);
-  }
-};
-
 // Device copies of small per-call descriptor arrays: one device buffer and one
 // pinned host staging buffer, filled by a bump pointer and reset at the start
 // of every API call (the previous call has drained the stream).
@@ -119,6 +111,26 @@ struct Arena {
 
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+struct RowSetDev {
+  DBuf<int> row0, ptr;
+  DBuf<Term> terms;
+  void upload(const RowSet& r, hipStream_t s) {
+    row0.upload(r.row0, s);
+    ptr.upload(r.ptr, s);
+    terms.upload(r.terms, s);
+  }
+};
+
+// Local factors and operators in the storage type T of the local solves.
+template <typename T>
+struct LocalBufs {
+  DBuf<T> qrA, tau, Tbuf;              // QR matrices (K_c^i | E_G, Kbar^i | E_flux), tau, block-reflector T
+  DBuf<T> Am, CD;                      // A_m^i (n_G x M), Abar^i (n_D x M)
+  DBuf<T> QG;                          // Q_G^T (M x n_G) per subdomain
+  DBuf<T> Gm, Lm, LTm, Nm, NTm;        // local interface operators
+  DBuf<T> F;                           // [nrhs][sum m] local right-hand sides
+};
+
 }  // namespace
 
 struct ddelm_ctx_s {
@@ -129,6 +141,7 @@ struct ddelm_ctx_s {
   int nP = 0, nD = 0, sumP = 0, sumD = 0;
   bool factored = false;
   bool use_nn = true;     // theta != 0: Kbar factored and P applied
+  bool mixed = false;     // float32 local factors + float64 refinement
   std::string err;
   int device = 0;
   int num_cu = 0;
@@ -141,36 +154,38 @@ struct ddelm_ctx_s {
   std::vector<long long> h_offB;     // offsets into g_B
   std::vector<long long> h_offm;     // offsets into packed row space (sum m)
   long long summ = 0;
-  // QR: 2N matrices (K_c then Kbar), fp64
-  DBuf<double> qrA, tau, Tbuf;
-  int npanel = 0;
+  // QR layout: 2N matrices (K_c then Kbar)
   DBuf<QRDesc> qrdesc;
   std::vector<QRDesc> h_qrdesc;
   int max_ncols = 0;
+  int npanel = 0;
   DBuf<long long> qr_coff;
   DBuf<int> qr_ldc, qr_cn;
-  // local matrices
-  DBuf<double> Am, CD;                 // n_G x M, n_D x M per subdomain
-  std::vector<long long> h_offAm, h_offCD;
-  DBuf<double> QG;                     // M x n_G per subdomain (Q_G^T)
-  std::vector<long long> h_offQG;
-  DBuf<double> Gm, Lm, LTm, Nm, NTm;
-  std::vector<long long> h_offG, h_offN;
+  std::vector<long long> h_offAm, h_offCD, h_offQG, h_offG, h_offN, h_offK;
   DBuf<long long> offG, offN;
-  // coarse
+  LocalBufs<double> l64;
+  LocalBufs<float> l32;
+  template <typename T>
+  LocalBufs<T>& lb();
+  // float64 features kept for refinement residuals (mixed precision)
+  DBuf<double> K64, A64, CD64;
+  DBuf<long long> offK_d;
+  // coarse (always float64)
   DBuf<double> Spi, Sfac, Sinv, Dpp, Gs, Zm, Ztm, Wm, X1;
-  DBuf<unsigned> flags;                // [0] barrier err, [1] cholesky err, [2..3] barrier
+  DBuf<unsigned> flags;                // [0] barrier expired (1) / Cholesky (2)
   // indexing on device
   DBuf<int> pi_off, dl_off, pi_l2g, dl_l2g, pi_own_ptr, pi_own_slot, dl_own_ptr, dl_own_slot, pi_slot_sub;
   DBuf<int> nG_dev;
   // solve workspaces
   int cap_nrhs = 0;
-  DBuf<double> F;                      // [nrhs][summ]
   DBuf<long long> f_off;               // per subdomain offset into F
-  DBuf<int> f_ld, f_cn, f_cnM;
+  DBuf<int> f_ld, f_cn;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
   int cg_blocks = 0, cg_slices = 0;
+  // refinement workspaces (mixed precision)
+  DBuf<double> F64, R64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
+  DBuf<double> fGP0, fGD0, hP0, hD0;   // interface rows and flux rows of a general right-hand side
   DBuf<unsigned> bar;
   DBuf<int> sizes_dev;                 // per subdomain M, n_I, n_B, m, n_G
   Arena arena;
@@ -195,6 +210,11 @@ struct ddelm_ctx_s {
   void fail(ddelm_status st, const std::string& m) { throw StatusError{st, m}; }
 };
 
+template <>
+LocalBufs<double>& ddelm_ctx_s::lb<double>() { return l64; }
+template <>
+LocalBufs<float>& ddelm_ctx_s::lb<float>() { return l32; }
+
 namespace {
 
 template <typename F>
@@ -218,34 +238,11 @@ ddelm_status run_guarded(ddelm_ctx c, F&& fn) {
 // --------------------------------------------------------------- launch helpers
 
 template <typename T>
-void launch_qr_panel(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, int k) {
-  switch (rpt) {
-#define CASE(R) case R: k_qr_panel<T, R><<<grid, kBlock, 0, s>>>(d, A, tau, k); break;
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
-#undef CASE
-    default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
-  }
-  HIPCHK(hipGetLastError());
-}
-
-template <typename T>
 void launch_qr_panel16(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
                        int npanel) {
   switch (rpt) {
 #define CASE(R) case R: k_qr_panel16<T, R><<<grid, kPanelThreads, 0, s>>>(d, A, tau, Tb, k, panel, npanel); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
-#undef CASE
-    default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
-  }
-  HIPCHK(hipGetLastError());
-}
-
-template <typename T>
-void launch_qr_apply(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, const T* A, const T* tau, int j0, int j1,
-                     T* C, const long long* coff, const int* ldc, const int* cn, int c0, int reverse) {
-  switch (rpt) {
-#define CASE(R) case R: k_qr_apply<T, R><<<grid, kBlock, 0, s>>>(d, A, tau, j0, j1, C, coff, ldc, cn, c0, reverse); break;
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
 #undef CASE
     default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
   }
@@ -261,19 +258,33 @@ void gemm_batch(ddelm_ctx c, const std::vector<GemmDesc>& h, const T* A, const T
   if (mm == 0 || nn == 0) return;
   const GemmDesc* d = c->arena.put(h, c->stream);
   dim3 grid(ceil_div(mm, 16), ceil_div(nn, 16), (unsigned)h.size());
-  k_gemm<T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  k_gemm<T, T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
   HIPCHK(hipGetLastError());
 }
 
-template <typename T>
-void copy_batch(ddelm_ctx c, const std::vector<CopyDesc>& h, const T* S, T* D) {
+// C (TC) = alpha op(A) B + beta C with A and B of different storage types
+template <typename TA, typename TB, typename TC>
+void gemm_batch_mixed(ddelm_ctx c, const std::vector<GemmDesc>& h, const TA* A, const TB* B, TC* C, int transA,
+                      double alpha, double beta) {
+  if (h.empty()) return;
+  int mm = 0, nn = 0;
+  for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
+  if (mm == 0 || nn == 0) return;
+  const GemmDesc* d = c->arena.put(h, c->stream);
+  dim3 grid(ceil_div(mm, 16), ceil_div(nn, 16), (unsigned)h.size());
+  k_gemm<TA, TB, TC><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename TS, typename TD>
+void copy_batch(ddelm_ctx c, const std::vector<CopyDesc>& h, const TS* S, TD* D) {
   if (h.empty()) return;
   long long mx = 0;
   for (auto& cd : h) mx = std::max(mx, (long long)cd.rows * cd.cols);
   if (mx == 0) return;
   const CopyDesc* d = c->arena.put(h, c->stream);
   dim3 grid(std::min(ceil_div(mx, kBlock), 1024), (unsigned)h.size());
-  k_copy2d<T, T><<<grid, kBlock, 0, c->stream>>>(d, S, D);
+  k_copy2d<TS, TD><<<grid, kBlock, 0, c->stream>>>(d, S, D);
   HIPCHK(hipGetLastError());
 }
 
@@ -283,10 +294,16 @@ void fill(hipStream_t s, double* p, long long n, double v) {
   HIPCHK(hipGetLastError());
 }
 
-int rows_per_thread(int m) { return ceil_div(m, kBlock); }
+template <typename TS, typename TD>
+void convert(hipStream_t s, const TS* src, TD* dst, long long n) {
+  if (n <= 0) return;
+  k_convert<TS, TD><<<std::min(ceil_div(n, kBlock), 4096), kBlock, 0, s>>>(src, dst, n);
+  HIPCHK(hipGetLastError());
+}
 
-// --------------------------------------------------------------- feature assembly into column-major blocks
-void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, double* out, const std::vector<long long>& off,
+// feature assembly into column-major blocks
+template <typename T>
+void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, const std::vector<long long>& off,
                        const std::vector<int>& ld, int sub0, int nsub) {
   if (max_rows == 0 || nsub == 0) return;
   FeatArgs a;
@@ -294,19 +311,21 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, double* o
   a.W = c->W.p; a.bias = c->b.p; a.geom = c->geom.p;
   a.off = c->arena.put(off, c->stream); a.ld = c->arena.put(ld, c->stream); a.M = c->M; a.sub0 = sub0;
   dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
-  k_features<double><<<grid, kBlock, 0, c->stream>>>(a, out);
+  k_features<T><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
 }
 
-OpArgs<double> op_args(ddelm_ctx c, int nrhs) {
-  OpArgs<double> a;
+template <typename T>
+OpArgs<T> op_args(ddelm_ctx c, int nrhs) {
+  OpArgs<T> a;
+  LocalBufs<T>& L = c->lb<T>();
   a.N = c->N; a.nP = c->nP; a.nD = c->nD; a.nrhs = nrhs;
   a.sumP = c->sumP; a.sumD = c->sumD; a.theta = c->use_nn ? c->opt.theta : 0.0;
   a.pi_off = c->pi_off.p; a.dl_off = c->dl_off.p; a.pi_l2g = c->pi_l2g.p; a.dl_l2g = c->dl_l2g.p;
   a.pi_own_ptr = c->pi_own_ptr.p; a.pi_own_slot = c->pi_own_slot.p;
   a.dl_own_ptr = c->dl_own_ptr.p; a.dl_own_slot = c->dl_own_slot.p;
   a.offG = c->offG.p; a.offN = c->offN.p;
-  a.Gm = c->Gm.p; a.Lm = c->Lm.p; a.LTm = c->LTm.p; a.Nm = c->Nm.p; a.NTm = c->NTm.p;
+  a.Gm = L.Gm.p; a.Lm = L.Lm.p; a.LTm = L.LTm.p; a.Nm = L.Nm.p; a.NTm = L.NTm.p;
   a.X1 = c->X1.p;
   a.s_loc = c->s_loc.p; a.l_loc = c->l_loc.p; a.rho_loc = c->rho_loc.p; a.psi_loc = c->psi_loc.p;
   a.lam_loc = c->lam_loc.p; a.y_loc = c->y_loc.p; a.z_loc = c->z_loc.p; a.t_loc = c->t_loc.p;
@@ -319,276 +338,13 @@ size_t local_smem(ddelm_ctx c) {
   return sizeof(double) * (size_t)std::max({c->geo.max_nG, 2 * c->nP, 1});
 }
 
-}  // namespace
-
-// =============================================================== kernels that need the context layout
-
-namespace {
-
-// f^i = [f_I; g_B; 0] into F[r][off_m[i] + row]
-__global__ void k_rhs_assemble(int N, int n_int, const int* __restrict__ sizes, const long long* __restrict__ offm,
-                               const long long* __restrict__ offB, long long summ, long long sumB,
-                               const double* __restrict__ fI, const double* __restrict__ gB, double* __restrict__ F) {
-  const int i = blockIdx.x, r = blockIdx.y;
-  const int nB = sizes[5 * i + 2], m = sizes[5 * i + 3];
-  double* Fi = F + (size_t)r * summ + offm[i];
-  for (int row = threadIdx.x; row < m; row += kBlock) {
-    double v = 0.0;
-    if (row < n_int) v = fI[((size_t)r * N + i) * n_int + row];
-    else if (row < n_int + nB) v = gB[(size_t)r * sumB + offB[i] + row - n_int];
-    Fi[row] = v;
-  }
-}
-
-// p_G = Q_G (Q^T f)[:M]; rho_loc = p_P (Pi slots), s_loc = p_D (Delta slots)
-// (interface rows of f are zero in a standard solve)
-__global__ void k_rhs_proj(int M, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                           const int* __restrict__ dl_off, const long long* __restrict__ offQG,
-                           const double* __restrict__ QG, const long long* __restrict__ offm, long long summ,
-                           const double* __restrict__ F, int sumP, int sumD, double* __restrict__ rho_loc,
-                           double* __restrict__ s_loc) {
-  const int i = blockIdx.x, r = blockIdx.y;
-  const int ng = sizes[5 * i + 4];
-  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
-  extern __shared__ double al[];
-  const double* Fi = F + (size_t)r * summ + offm[i];
-  for (int k = threadIdx.x; k < M; k += kBlock) al[k] = Fi[k];
-  __syncthreads();
-  const double* Q = QG + offQG[i];
-  for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += Q[(long long)t * M + k] * al[k];
-    if (t < np) rho_loc[(size_t)r * sumP + p0 + t] = acc;
-    else s_loc[(size_t)r * sumD + d0 + t - np] = acc;
-  }
-}
-
-// ad = A_m c_f0; psi_loc = -ad_P, l_loc = -ad_D
-__global__ void k_rhs_flux(int M, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                           const int* __restrict__ dl_off, const long long* __restrict__ offAm,
-                           const double* __restrict__ Am, const long long* __restrict__ offm, long long summ,
-                           const double* __restrict__ F, int sumP, int sumD, double* __restrict__ psi_loc,
-                           double* __restrict__ l_loc) {
-  const int i = blockIdx.x, r = blockIdx.y;
-  const int ng = sizes[5 * i + 4];
-  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
-  extern __shared__ double cf[];
-  const double* Fi = F + (size_t)r * summ + offm[i];
-  for (int k = threadIdx.x; k < M; k += kBlock) cf[k] = Fi[k];
-  __syncthreads();
-  const double* A = Am + offAm[i];
-  for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += A[(long long)k * ng + t] * cf[k];
-    if (t < np) psi_loc[(size_t)r * sumP + p0 + t] = -acc;
-    else l_loc[(size_t)r * sumD + d0 + t - np] = -acc;
-  }
-}
-
-// c^i = c_f0 + E [mu_P(Pi^i); mu_D(Delta^i)]  with E = R^{-1} Q_G^T stored in
-// the K_c matrix (rows 0..M-1 of columns M.., leading dimension m)
-__global__ void k_recover(int M, int nP, int nD, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                          const int* __restrict__ dl_off, const int* __restrict__ pi_l2g,
-                          const int* __restrict__ dl_l2g, const QRDesc* __restrict__ desc,
-                          const double* __restrict__ qrA, const long long* __restrict__ offm, long long summ,
-                          const double* __restrict__ F, const double* __restrict__ mu_pi,
-                          const double* __restrict__ mu_dl, int N, double* __restrict__ coef) {
-  const int i = blockIdx.x, r = blockIdx.y;
-  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i], nd = dl_off[i + 1] - d0;
-  extern __shared__ double mus[];
-  for (int a = threadIdx.x; a < np + nd; a += kBlock)
-    mus[a] = a < np ? mu_pi[(size_t)r * nP + pi_l2g[p0 + a]] : mu_dl[(size_t)r * nD + dl_l2g[d0 + a - np]];
-  __syncthreads();
-  const QRDesc d = desc[i];
-  const double* E = qrA + d.off + (long long)M * d.ld;
-  const double* Fi = F + (size_t)r * summ + offm[i];
-  for (int k = threadIdx.x; k < M; k += kBlock) {
-    double acc = Fi[k];
-    for (int a = 0; a < np + nd; ++a) acc += E[(long long)a * d.ld + k] * mus[a];
-    coef[((size_t)r * N + i) * M + k] = acc;
-  }
-}
-
-// mu_Pi = pi_f - mu_Pi(v)
-__global__ void k_mu_pi(int nP, int nrhs, const double* __restrict__ pif, const double* __restrict__ c1,
-                        double* __restrict__ out) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= nP * nrhs) return;
-  const int r = e / nP, p = e % nP;
-  out[e] = pif[e] - c1[(size_t)r * 2 * nP + p];
-}
-
-__global__ void k_save_pif(int nP, int nrhs, const double* __restrict__ c1, double* __restrict__ pif) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= nP * nrhs) return;
-  const int r = e / nP, p = e % nP;
-  pif[e] = c1[(size_t)r * 2 * nP + p];
-}
-
-// set the unit entries of the appended identity columns
-__global__ void k_set_units(const long long* __restrict__ pos, long long n, double* __restrict__ A) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e < n) A[pos[e]] = 1.0;
-}
-
-// X1 = [[Sinv, Z^T], [-Z, I - W]] (column-major, 2n x 2n) with Z = D Sinv, W = D Z^T
-__global__ void k_assemble_X1(int n, const double* __restrict__ Sinv, const double* __restrict__ Z,
-                              const double* __restrict__ W, double* __restrict__ X1) {
-  const long long tot = 4ll * n * n;
-  const int ld = 2 * n;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < tot; e += (long long)gridDim.x * kBlock) {
-    const int r = (int)(e % ld), c = (int)(e / ld);
-    double v;
-    if (r < n && c < n) v = Sinv[(long long)c * n + r];
-    else if (r < n) v = Z[(long long)r * n + (c - n)];               // Z^T[r][c-n] = Z[c-n][r]
-    else if (c < n) v = -Z[(long long)c * n + (r - n)];
-    else v = (r == c ? 1.0 : 0.0) - W[(long long)(c - n) * n + (r - n)];
-    X1[e] = v;
-  }
-}
-
-// ---------------------------------------------------------------- CG kernels (one launch per phase)
-
-// w = sum of owners, partial p.w
-__global__ void __launch_bounds__(kBlock) k_cg_wdot(OpArgs<double> a, CGState s) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.y, blk = blockIdx.x;
-  double acc = 0.0;
-  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
-    const double wv = dl_sum(a.dl_own_ptr, a.dl_own_slot, a.w_loc + (size_t)r * a.sumD, g);
-    s.w[(size_t)r * s.n + g] = wv;
-    acc += wv * s.p[(size_t)r * s.n + g];
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
-}
-
-// alpha = rr / p.w (one block per rhs)
-__global__ void __launch_bounds__(kBlock) k_cg_alpha(CGState s) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.x;
-  const double pw = cg_reduce_parts(s.part, s.nblk, r, red);
-  if (threadIdx.x == 0) {
-    double* sc = s.scal + (size_t)r * 8;
-    sc[2] = pw;
-    sc[3] = (sc[5] != 0.0 || pw == 0.0) ? 0.0 : sc[0] / pw;
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_cg_axpy(CGState s) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.y, blk = blockIdx.x;
-  const double al = s.scal[(size_t)r * 8 + 3];
-  double acc = 0.0;
-  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
-    const size_t e = (size_t)r * s.n + g;
-    s.x[e] += al * s.p[e];
-    const double rv = s.r[e] - al * s.w[e];
-    s.r[e] = rv;
-    acc += rv * rv;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
-}
-
-__global__ void __launch_bounds__(kBlock) k_cg_beta(CGState s) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.x;
-  const double rr = cg_reduce_parts(s.part, s.nblk, r, red);
-  if (threadIdx.x == 0) {
-    double* sc = s.scal + (size_t)r * 8;
-    if (sc[5] != 0.0) {
-      sc[4] = 0.0;
-    } else {
-      sc[4] = sc[0] > 0.0 ? rr / sc[0] : 0.0;
-      sc[0] = rr;
-      sc[6] += 1.0;
-      if (!(rr == rr) || isinf(rr)) sc[7] = 1.0;
-      if (sqrt(rr) <= s.tol * sqrt(sc[1]) || !(rr == rr)) sc[5] = 1.0;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_cg_pupd(CGState s) {
-  const int r = blockIdx.y, blk = blockIdx.x;
-  const double be = s.scal[(size_t)r * 8 + 4];
-  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
-    const size_t e = (size_t)r * s.n + g;
-    s.p[e] = s.r[e] + be * s.p[e];
-  }
-}
-
-// r = p = b, x = 0; partial b.b
-__global__ void __launch_bounds__(kBlock) k_cg_init(CGState s, const double* __restrict__ b) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.y, blk = blockIdx.x;
-  double acc = 0.0;
-  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
-    const size_t e = (size_t)r * s.n + g;
-    const double bv = b[e];
-    s.x[e] = 0.0;
-    s.r[e] = bv;
-    s.p[e] = bv;
-    acc += bv * bv;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
-}
-
-__global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
-  __shared__ double red[kWaves];
-  const int r = blockIdx.x;
-  const double bb = cg_reduce_parts(s.part, s.nblk, r, red);
-  if (threadIdx.x == 0) {
-    double* sc = s.scal + (size_t)r * 8;
-    sc[0] = bb; sc[1] = bb; sc[2] = 0; sc[3] = 0; sc[4] = 0;
-    sc[5] = (bb == 0.0) ? 1.0 : 0.0;
-    sc[6] = 0; sc[7] = 0;
-  }
-}
-
-// ---------------------------------------------------------------- evaluation
-__global__ void k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0, double h1,
-                           const double* __restrict__ W, const double* __restrict__ bias,
-                           const double* __restrict__ coef, long long npts, const double* __restrict__ x,
-                           double* __restrict__ u, double* __restrict__ grad, int r) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= npts) return;
-  const double px = x[2 * e], py = x[2 * e + 1];
-  int ix = (int)ceil((px - lo0) / h0) - 1, iy = (int)ceil((py - lo1) / h1) - 1;
-  ix = ix < 0 ? 0 : (ix > nx - 1 ? nx - 1 : ix);
-  iy = iy < 0 ? 0 : (iy > ny - 1 ? ny - 1 : iy);
-  const int i = iy * nx + ix;
-  const double hx = 0.5 * h0, hy = 0.5 * h1;
-  const double cx = lo0 + (ix + 0.5) * h0, cy = lo1 + (iy + 0.5) * h1;
-  const double xi0 = (px - cx) / hx, xi1 = (py - cy) / hy;
-  const double* c = coef + ((size_t)r * N + i) * M;
-  double acc = 0.0, g0 = 0.0, g1 = 0.0;
-  for (int j = 0; j < M; ++j) {
-    const double w0 = W[((size_t)i * M + j) * 2], w1 = W[((size_t)i * M + j) * 2 + 1];
-    const double t = tanh(w0 * xi0 + w1 * xi1 + bias[(size_t)i * M + j]);
-    acc += c[j] * t;
-    const double dt = c[j] * (1.0 - t * t);
-    g0 += dt * w0;
-    g1 += dt * w1;
-  }
-  u[(size_t)r * npts + e] = acc;
-  if (grad) {
-    grad[((size_t)r * npts + e) * 2] = g0 / hx;
-    grad[((size_t)r * npts + e) * 2 + 1] = g1 / hy;
-  }
-}
-
-}  // namespace
-
-// =============================================================== host implementation
-
-namespace {
+// --------------------------------------------------------------- solve workspaces
 
 void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   if (nrhs <= c->cap_nrhs) return;
   hipStream_t s = c->stream;
-  c->F.alloc((size_t)nrhs * c->summ);
+  if (c->mixed) c->l32.F.alloc((size_t)nrhs * c->summ);
+  else c->l64.F.alloc((size_t)nrhs * c->summ);
   const size_t D = (size_t)nrhs * std::max(c->sumD, 1), P = (size_t)nrhs * std::max(c->sumP, 1);
   for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc}) b->alloc(D);
   for (DBuf<double>* b : {&c->rho_loc, &c->psi_loc, &c->nu_loc}) b->alloc(P);
@@ -600,14 +356,29 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b}) b->alloc(V);
   c->mu_slot.alloc(P);
   c->e_slot.alloc(P);
-  c->mu_slot.zero(s);
-  c->e_slot.zero(s);
   c->cg_part.alloc((size_t)2 * nrhs * 4096);
   c->cg_scal.alloc((size_t)nrhs * 8);
-  // zero everything once so unused Pi/Delta slots never hold garbage
   for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc, &c->rho_loc,
-                          &c->psi_loc, &c->nu_loc, &c->c1, &c->c2, &c->pif})
+                          &c->psi_loc, &c->nu_loc, &c->c1, &c->c2, &c->pif, &c->mu_slot, &c->e_slot})
     b->zero(s);
+  c->fGP.alloc(P); c->fGD.alloc(D);
+  c->fGP0.alloc(P); c->fGD0.alloc(D);
+  c->hP0.alloc((size_t)nrhs * std::max(c->nP, 1));
+  c->hD0.alloc(V);
+  for (DBuf<double>* b : {&c->fGP, &c->fGD, &c->fGP0, &c->fGD0, &c->hP0, &c->hD0}) b->zero(s);
+  if (c->mixed) {
+    c->F64.alloc((size_t)nrhs * c->summ);
+    c->R64.alloc((size_t)nrhs * c->summ);
+    c->aP.alloc(P);
+    c->aD.alloc(D);
+    c->hPb.alloc((size_t)nrhs * std::max(c->nP, 1));
+    c->hDb.alloc(V);
+    c->dcoef.alloc((size_t)nrhs * c->N * c->M);
+    c->dmup.alloc((size_t)nrhs * std::max(c->nP, 1));
+    c->dmud.alloc(V);
+    c->nrm_part.alloc((size_t)nrhs * 2 * 256);
+    for (DBuf<double>* b : {&c->fGP, &c->aP, &c->fGD, &c->aD, &c->hPb, &c->hDb, &c->dmup, &c->dmud}) b->zero(s);
+  }
   std::vector<long long> foff(c->N);
   std::vector<int> fld(c->N, (int)c->summ), fcn(c->N, nrhs);
   for (int i = 0; i < c->N; ++i) foff[i] = c->h_offm[i];
@@ -618,48 +389,50 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
-// one application of the operator phases after the first stage
-void run_phases_after_stage1(ddelm_ctx c, OpArgs<double>& a, int nrhs, const double* hP) {
+// --------------------------------------------------------------- operator phases after the first stage
+template <typename T>
+void run_phases_after_stage1(ddelm_ctx c, OpArgs<T>& a, int nrhs, const double* hP) {
   hipStream_t s = c->stream;
   const size_t sm = local_smem(c);
   const dim3 gl(c->N, nrhs);
   if (c->nP > 0) {
-    OpArgs<double> ah = a;
+    OpArgs<T> ah = a;
     ah.hP = hP;
-    k_ph_coarse1<double><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(ah);
+    k_ph_coarse1<T><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(ah);
     HIPCHK(hipGetLastError());
   }
-  k_ph_lam<double><<<gl, kBlock, 0, s>>>(a);
+  k_ph_lam<T><<<gl, kBlock, 0, s>>>(a);
   HIPCHK(hipGetLastError());
   if (a.theta != 0.0) {
-    k_ph_P1<double><<<gl, kBlock, sm, s>>>(a);
-    k_ph_P2<double><<<gl, kBlock, sm, s>>>(a);
+    k_ph_P1<T><<<gl, kBlock, sm, s>>>(a);
+    k_ph_P2<T><<<gl, kBlock, sm, s>>>(a);
     HIPCHK(hipGetLastError());
   }
-  k_ph_eta<double><<<gl, kBlock, sm, s>>>(a);
+  k_ph_eta<T><<<gl, kBlock, sm, s>>>(a);
   HIPCHK(hipGetLastError());
   if (c->nP > 0) {
-    k_ph_coarse2<double><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
+    k_ph_coarse2<T><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
     HIPCHK(hipGetLastError());
   }
-  k_ph_w<double><<<gl, kBlock, 0, s>>>(a);
+  k_ph_w<T><<<gl, kBlock, 0, s>>>(a);
   HIPCHK(hipGetLastError());
 }
 
-CGState cg_state(ddelm_ctx c, int nrhs, int nblk) {
+CGState cg_state(ddelm_ctx c, int nrhs, int nblk, double tol) {
   CGState s;
   s.x = c->cg_x.p; s.r = c->cg_r.p; s.p = c->cg_p.p; s.w = c->cg_w.p;
   s.part = c->cg_part.p; s.scal = c->cg_scal.p;
   s.n = c->nD; s.nrhs = nrhs; s.nblk = nblk;
-  s.tol = c->opt.tol; s.maxit = c->opt.maxit;
+  s.tol = tol; s.maxit = c->opt.maxit;
   return s;
 }
 
-int cg_multilaunch(ddelm_ctx c, int nrhs) {
+template <typename T>
+void cg_multilaunch(ddelm_ctx c, int nrhs, double tol) {
   hipStream_t s = c->stream;
   const int nblk = std::max(1, std::min(256, ceil_div(c->nD, kBlock)));
-  CGState st = cg_state(c, nrhs, nblk);
-  OpArgs<double> a = op_args(c, nrhs);
+  CGState st = cg_state(c, nrhs, nblk, tol);
+  OpArgs<T> a = op_args<T>(c, nrhs);
   const size_t sm = local_smem(c);
   k_cg_init<<<dim3(nblk, nrhs), kBlock, 0, s>>>(st, c->cg_b.p);
   k_cg_init2<<<nrhs, kBlock, 0, s>>>(st);
@@ -670,9 +443,9 @@ int cg_multilaunch(ddelm_ctx c, int nrhs) {
   while (it < c->opt.maxit) {
     const int nstep = std::min(check_every, c->opt.maxit - it);
     for (int k = 0; k < nstep; ++k) {
-      k_ph_local_v<double><<<dim3(c->N, nrhs), kBlock, sm, s>>>(a, st.p);
-      run_phases_after_stage1(c, a, nrhs, nullptr);
-      k_cg_wdot<<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, st);
+      k_ph_local_v<T><<<dim3(c->N, nrhs), kBlock, sm, s>>>(a, st.p);
+      run_phases_after_stage1<T>(c, a, nrhs, nullptr);
+      k_cg_wdot<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, st);
       k_cg_alpha<<<nrhs, kBlock, 0, s>>>(st);
       k_cg_axpy<<<dim3(nblk, nrhs), kBlock, 0, s>>>(st);
       k_cg_beta<<<nrhs, kBlock, 0, s>>>(st);
@@ -686,21 +459,20 @@ int cg_multilaunch(ddelm_ctx c, int nrhs) {
     for (int r = 0; r < nrhs; ++r) all = all && sc[8 * r + 5] != 0.0;
     if (all) break;
   }
-  return it;
 }
 
-template <int NR>
-void launch_fused(ddelm_ctx c, int nrhs) {
+template <typename T, int NR>
+void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   hipStream_t s = c->stream;
   const Geometry& g = c->geo;
-  FusedArgs<double> f;
-  f.a = op_args(c, nrhs);
+  FusedArgs<T> f;
+  f.a = op_args<T>(c, nrhs);
   int S = 1;
   if (const char* env = getenv("DDELM_CG_SLICES")) S = std::max(1, std::min(8, atoi(env)));
   else S = std::max(1, std::min(4, 128 / std::max(c->N, 1)));
   f.S = S;
   f.nrhs = nrhs;
-  f.tol = c->opt.tol;
+  f.tol = tol;
   f.maxit = c->opt.maxit;
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p; f.w = c->cg_w.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
@@ -714,7 +486,7 @@ void launch_fused(ddelm_ctx c, int nrhs) {
   f.lds_cu = xs + ys + part;
   const size_t smem = sizeof(double) * (size_t)(xs + ys + part + cu);
   if (smem > 160 * 1024) c->fail(DDELM_E_SHAPE, "CG workspace exceeds the LDS of one compute unit");
-  const void* fn = (const void*)k_cg_fused<double, NR>;
+  const void* fn = (const void*)k_cg_fused<T, NR>;
   if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   int per_cu = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, smem));
@@ -731,13 +503,394 @@ void launch_fused(ddelm_ctx c, int nrhs) {
   c->cg_slices = S;
 }
 
-void cg_persistent(ddelm_ctx c, int nrhs) {
-  if (nrhs <= 1) launch_fused<1>(c, nrhs);
-  else if (nrhs <= 2) launch_fused<2>(c, nrhs);
-  else if (nrhs <= 4) launch_fused<4>(c, nrhs);
-  else if (nrhs <= 8) launch_fused<8>(c, nrhs);
-  else if (nrhs <= 16) launch_fused<16>(c, nrhs);
+template <typename T>
+void cg_persistent(ddelm_ctx c, int nrhs, double tol) {
+  if (nrhs <= 1) launch_fused<T, 1>(c, nrhs, tol);
+  else if (nrhs <= 2) launch_fused<T, 2>(c, nrhs, tol);
+  else if (nrhs <= 4) launch_fused<T, 4>(c, nrhs, tol);
+  else if (nrhs <= 8) launch_fused<T, 8>(c, nrhs, tol);
+  else if (nrhs <= 16) launch_fused<T, 16>(c, nrhs, tol);
   else c->fail(DDELM_E_ARG, "the persistent CG handles at most 16 right-hand sides");
+}
+
+// --------------------------------------------------------------- factorisation
+template <typename T>
+void factor_impl(ddelm_ctx c) {
+  hipStream_t s = c->stream;
+  const int N = c->N, M = c->M;
+  const Geometry& g = c->geo;
+  const bool nn = c->use_nn;
+  const int nmat = nn ? 2 * N : N;
+  LocalBufs<T>& L = c->lb<T>();
+  // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
+  c->h_qrdesc.assign(nmat, QRDesc());
+  long long off = 0, toff = 0;
+  c->max_ncols = 0;
+  for (int b = 0; b < nmat; ++b) {
+    const int i = b % N;
+    QRDesc d;
+    d.off = off; d.m = c->h_m[i]; d.ld = c->h_m[i];
+    d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
+    d.nrefl = M; d.tau = toff; d.pad = 0;
+    c->h_qrdesc[b] = d;
+    off += (long long)d.ld * d.ncols;
+    toff += M;
+    c->max_ncols = std::max(c->max_ncols, d.ncols);
+  }
+  L.qrA.alloc(off);
+  L.tau.alloc(toff);
+  L.qrA.zero(s);
+  c->qrdesc.upload(c->h_qrdesc, s);
+  {
+    std::vector<long long> coff(nmat);
+    std::vector<int> ldc(nmat), cn(nmat);
+    for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
+    c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
+  }
+  c->mark(0);
+  // ---- features
+  {
+    std::vector<long long> o1(N), o2(N);
+    std::vector<int> l1(N);
+    for (int i = 0; i < N; ++i) { o1[i] = c->h_qrdesc[i].off; l1[i] = c->h_m[i]; }
+    c->h_offAm.assign(N + 1, 0);
+    c->h_offCD.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      c->h_offAm[i + 1] = c->h_offAm[i] + (long long)c->h_nG[i] * M;
+      c->h_offCD[i + 1] = c->h_offCD[i] + (long long)c->h_nD[i] * M;
+    }
+    const std::vector<long long> oAm(c->h_offAm.begin(), c->h_offAm.end() - 1);
+    const std::vector<int> ldA(c->h_nG.begin(), c->h_nG.end());
+    L.Am.alloc(std::max(c->h_offAm[N], 1ll));
+    if (std::is_same<T, double>::value) {
+      assemble_features<T>(c, c->rsK, g.max_m, L.qrA.p, o1, l1, 0, N);
+      assemble_features<T>(c, c->rsA, g.max_nG, L.Am.p, oAm, ldA, 0, N);
+    } else {
+      // float64 copies of K_c and A_m stay for the refinement residuals
+      c->h_offK.assign(N + 1, 0);
+      for (int i = 0; i < N; ++i) c->h_offK[i + 1] = c->h_offK[i] + (long long)c->h_m[i] * M;
+      c->K64.alloc(c->h_offK[N]);
+      c->A64.alloc(std::max(c->h_offAm[N], 1ll));
+      const std::vector<long long> oK(c->h_offK.begin(), c->h_offK.end() - 1);
+      assemble_features<double>(c, c->rsK, g.max_m, c->K64.p, oK, l1, 0, N);
+      assemble_features<double>(c, c->rsA, g.max_nG, c->A64.p, oAm, ldA, 0, N);
+      std::vector<CopyDesc> cp;
+      for (int i = 0; i < N; ++i) cp.push_back(CopyDesc{c->h_offK[i], o1[i], c->h_m[i], c->h_m[i], c->h_m[i], M, 0, 0});
+      copy_batch<double, T>(c, cp, c->K64.p, L.qrA.p);
+      convert<double, T>(s, c->A64.p, L.Am.p, c->h_offAm[N]);
+      c->offK_d.upload(oK, s);
+    }
+    if (nn) {
+      for (int i = 0; i < N; ++i) o2[i] = c->h_qrdesc[N + i].off;
+      assemble_features<T>(c, c->rsKb, g.max_m, L.qrA.p, o2, l1, 0, N);
+      std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
+      const std::vector<long long> oCD(c->h_offCD.begin(), c->h_offCD.end() - 1);
+      if (std::is_same<T, double>::value) {
+        L.CD.alloc(std::max(c->h_offCD[N], 1ll));
+        assemble_features<T>(c, c->rsAb, g.max_nD, L.CD.p, oCD, ldC, 0, N);
+      } else {
+        c->CD64.alloc(std::max(c->h_offCD[N], 1ll));
+        assemble_features<double>(c, c->rsAb, g.max_nD, c->CD64.p, oCD, ldC, 0, N);
+      }
+    }
+    // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
+    // M+t has a 1 at flux row n_I+n_B+n_P+t
+    std::vector<long long> pos;
+    for (int b = 0; b < nmat; ++b) {
+      const int i = b % N;
+      const QRDesc& d = c->h_qrdesc[b];
+      const SubInfo& sb = g.subs[i];
+      const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
+      const int cnt = b < N ? sb.n_G() : sb.n_D;
+      for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
+    }
+    if (!pos.empty()) {
+      const long long* dp = c->arena.put(pos, s);
+      k_set_units<T><<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), L.qrA.p);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  c->mark(1);
+  // ---- blocked Householder QR of all matrices: 16-column panels, WY updates on MFMA
+  {
+    c->npanel = ceil_div(M, kNB);
+    L.Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
+    for (int p = 0; p < c->npanel; ++p) {
+      const int k = p * kNB;
+      launch_qr_panel16<T>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, L.qrA.p, L.tau.p, L.Tbuf.p, k,
+                           p, c->npanel);
+      const int c0 = k + std::min(kNB, M - k);
+      const int ntile = ceil_div(c->max_ncols - c0, kUC);
+      if (ntile > 0) {
+        k_qr_wy<T><<<dim3(nmat, ntile), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, k, p, c->npanel, L.qrA.p,
+                                                        c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
+        HIPCHK(hipGetLastError());
+      }
+    }
+  }
+  c->mark(2);
+  // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T and Xbar = Rbar^{-1} Qbar_D^T in place
+  {
+    c->h_offQG.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) c->h_offQG[i + 1] = c->h_offQG[i] + (long long)M * c->h_nG[i];
+    L.QG.alloc(std::max(c->h_offQG[N], 1ll));
+    std::vector<CopyDesc> cp;
+    for (int i = 0; i < N; ++i) {
+      const QRDesc& d = c->h_qrdesc[i];
+      if (c->h_nG[i] == 0) continue;
+      cp.push_back(CopyDesc{d.off + (long long)M * d.ld, c->h_offQG[i], d.ld, M, M, c->h_nG[i], 0, 0});
+    }
+    copy_batch<T, T>(c, cp, L.qrA.p, L.QG.p);
+    std::vector<long long> xoff(nmat);
+    std::vector<int> ldx(nmat), xn(nmat);
+    int maxx = 0;
+    for (int b = 0; b < nmat; ++b) {
+      const QRDesc& d = c->h_qrdesc[b];
+      xoff[b] = d.off + (long long)M * d.ld;
+      ldx[b] = d.ld;
+      xn[b] = d.ncols - M;
+      maxx = std::max(maxx, xn[b]);
+    }
+    if (maxx > 0) {
+      const long long* dxo = c->arena.put(xoff, s);
+      const int* dld = c->arena.put(ldx, s);
+      const int* dxn = c->arena.put(xn, s);
+      const size_t smt = (size_t)M * kTRSMC * sizeof(T);
+      if (smt > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_trsm<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smt));
+      k_trsm<T><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.qrA.p, dxo, dld, dxn, 0);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  // ---- local interface operators
+  {
+    c->h_offG.assign(N + 1, 0);
+    c->h_offN.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      c->h_offG[i + 1] = c->h_offG[i] + (long long)c->h_nG[i] * c->h_nG[i];
+      c->h_offN[i + 1] = c->h_offN[i] + (long long)c->h_nD[i] * c->h_nD[i];
+    }
+    const size_t nGt = std::max(c->h_offG[N], 1ll), nNt = std::max(c->h_offN[N], 1ll);
+    L.Gm.alloc(nGt); L.Lm.alloc(nGt); L.LTm.alloc(nGt);
+    L.Nm.alloc(nNt); L.NTm.alloc(nNt);
+    L.Gm.zero(s); L.Lm.zero(s); L.LTm.zero(s); L.Nm.zero(s); L.NTm.zero(s);
+    c->offG.upload(std::vector<long long>(c->h_offG.begin(), c->h_offG.end() - 1), s);
+    c->offN.upload(std::vector<long long>(c->h_offN.begin(), c->h_offN.end() - 1), s);
+    std::vector<GemmDesc> gG, gL, gN;
+    std::vector<CopyDesc> tL, tN;
+    for (int i = 0; i < N; ++i) {
+      const int ng = c->h_nG[i], nd = c->h_nD[i];
+      const QRDesc& d = c->h_qrdesc[i];
+      if (ng == 0) continue;
+      gG.push_back(GemmDesc{c->h_offQG[i], c->h_offQG[i], c->h_offG[i], M, M, ng, ng, ng, M});
+      gL.push_back(GemmDesc{c->h_offAm[i], d.off + (long long)M * d.ld, c->h_offG[i], ng, d.ld, ng, ng, ng, M});
+      tL.push_back(CopyDesc{c->h_offG[i], c->h_offG[i], ng, ng, ng, ng, 1, 0});
+      if (nn && nd > 0) {
+        const QRDesc& db = c->h_qrdesc[N + i];
+        gN.push_back(GemmDesc{c->h_offCD[i], db.off + (long long)M * db.ld, c->h_offN[i], nd, db.ld, nd, nd, nd, M});
+        tN.push_back(CopyDesc{c->h_offN[i], c->h_offN[i], nd, nd, nd, nd, 1, 0});
+      }
+    }
+    gemm_batch<T>(c, gG, L.QG.p, L.QG.p, L.Gm.p, 1, -1.0, 0.0);
+    {
+      std::vector<long long> o;
+      std::vector<int> n;
+      for (int i = 0; i < N; ++i) if (c->h_nG[i]) { o.push_back(c->h_offG[i]); n.push_back(c->h_nG[i]); }
+      if (!o.empty()) {
+        const long long* dO = c->arena.put(o, s);
+        const int* dn = c->arena.put(n, s);
+        k_add_diag_t<T><<<(unsigned)o.size(), kBlock, 0, s>>>(dO, dn, L.Gm.p, T(1));
+        HIPCHK(hipGetLastError());
+      }
+    }
+    // feature rows times coefficient-space blocks: with float32 factors the
+    // feature matrices stay float64 (the coefficients can be large and cancel)
+    if (std::is_same<T, double>::value) gemm_batch<T>(c, gL, L.Am.p, L.qrA.p, L.Lm.p, 0, 1.0, 0.0);
+    else gemm_batch_mixed<double, T, T>(c, gL, c->A64.p, L.qrA.p, L.Lm.p, 0, 1.0, 0.0);
+    copy_batch<T, T>(c, tL, L.Lm.p, L.LTm.p);
+    if (!gN.empty()) {
+      if (std::is_same<T, double>::value) gemm_batch<T>(c, gN, L.CD.p, L.qrA.p, L.Nm.p, 0, 1.0, 0.0);
+      else gemm_batch_mixed<double, T, T>(c, gN, c->CD64.p, L.qrA.p, L.Nm.p, 0, 1.0, 0.0);
+      copy_batch<T, T>(c, tN, L.Nm.p, L.NTm.p);
+    }
+  }
+  c->mark(3);
+  // ---- coarse problem (float64): D_PiPi, S_Pi = sum G_PiPi + D^T D, Cholesky, inverse, X1
+  if (c->nP > 0) {
+    const int n = c->nP;
+    const size_t nn2 = (size_t)n * n;
+    c->Dpp.alloc(nn2); c->Gs.alloc(nn2); c->Spi.alloc(nn2); c->Sfac.alloc(nn2); c->Sinv.alloc(nn2);
+    c->Zm.alloc(nn2); c->Ztm.alloc(nn2); c->Wm.alloc(nn2); c->X1.alloc(4 * nn2);
+    c->Dpp.zero(s); c->Gs.zero(s);
+    k_coarse_assemble<T><<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, c->pi_own_ptr.p, c->pi_own_slot.p, c->pi_slot_sub.p,
+                                                                c->pi_off.p, c->pi_l2g.p, c->offG.p, c->nG_dev.p,
+                                                                L.Gm.p, L.Lm.p, c->Dpp.p, c->Gs.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->Spi.p, c->Gs.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Dpp.p, c->Spi.p, 1, 1.0, 1.0);
+    HIPCHK(hipMemcpyAsync(c->Sfac.p, c->Spi.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(c->flags.p, 0, 8 * sizeof(unsigned), s));
+    k_cholesky<<<1, kBlock, 0, s>>>(c->Sfac.p, n, c->flags.p);
+    HIPCHK(hipGetLastError());
+    const size_t smi = (size_t)n * 4 * sizeof(double);
+    if (smi > 160 * 1024) c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
+    if (smi > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smi));
+    k_chol_inverse<<<ceil_div(n, 4), kBlock, smi, s>>>(c->Sfac.p, n, c->Sinv.p);
+    HIPCHK(hipGetLastError());
+    gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Sinv.p, c->Zm.p, 0, 1.0, 0.0);
+    copy_batch<double, double>(c, {CopyDesc{0, 0, n, n, n, n, 1, 0}}, c->Zm.p, c->Ztm.p);
+    gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Ztm.p, c->Wm.p, 0, 1.0, 0.0);
+    k_assemble_X1<<<std::min(ceil_div(4ll * nn2, kBlock), 4096), kBlock, 0, s>>>(n, c->Sinv.p, c->Zm.p, c->Wm.p,
+                                                                                 c->X1.p);
+    HIPCHK(hipGetLastError());
+  } else {
+    c->X1.alloc(1);
+  }
+  c->mark(4);
+  c->offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
+  c->offB_d.upload(std::vector<long long>(c->h_offB.begin(), c->h_offB.end() - 1), s);
+  c->offQG_d.upload(std::vector<long long>(c->h_offQG.begin(), c->h_offQG.end() - 1), s);
+  c->offAm_d.upload(std::vector<long long>(c->h_offAm.begin(), c->h_offAm.end() - 1), s);
+  unsigned fl[8];
+  HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl[0] & 2u) c->fail(DDELM_E_CHOLESKY, "S_Pi is not positive definite");
+  for (int k = 0; k < 4; ++k) c->phase_ms[k] = c->span(k, k + 1);
+}
+
+// --------------------------------------------------------------- one DDELM-NN solve on prepared local RHS
+//
+// F (type T, [nrhs][sum m]) holds f^i for every subdomain; fGP/fGD are its
+// interface rows in slot order (null when zero); hP/hD the flux right-hand
+// side (null when zero).  Writes coef (overwrite or accumulate), mu_pi, mu_dl.
+struct CoreOut {
+  int iters = 0;
+  double relres = 0.0;
+  bool noconv = false;
+  double ms_rhs = 0, ms_cg = 0, ms_rec = 0;
+};
+
+template <typename T>
+CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, const double* hP, const double* hD,
+                   double tol, double* coef, int accumulate, double* mu_pi_out, double* mu_dl_out) {
+  CoreOut res;
+  hipStream_t s = c->stream;
+  const int N = c->N, M = c->M;
+  LocalBufs<T>& L = c->lb<T>();
+  auto t0 = std::chrono::steady_clock::now();
+  c->mark(5);
+  // ---- Q^T f (block reflectors), projections, K^+ f, fluxes
+  for (int p = 0; p < c->npanel; ++p) {
+    k_qr_wy<T><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, p * kNB, p, c->npanel,
+                                                               L.F.p, c->f_off.p, c->f_ld.p, c->f_cn.p, 0, 1);
+    HIPCHK(hipGetLastError());
+  }
+  k_rhs_proj<T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
+                                                                   c->offQG_d.p, L.QG.p, c->offm_d.p, c->summ, L.F.p,
+                                                                   c->sumP, c->sumD, fGP, fGD, c->rho_loc.p,
+                                                                   c->s_loc.p);
+  HIPCHK(hipGetLastError());
+  {
+    const size_t smt = (size_t)M * kTRSMC * sizeof(T);
+    const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
+    k_trsm<T><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p,
+                                                                   cnM, 0);
+    HIPCHK(hipGetLastError());
+
+    if (c->mixed)
+      k_rhs_flux<T, double><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
+          M, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
+          c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, L.F.p, c->sumP, c->sumD, hD, c->psi_loc.p, c->l_loc.p);
+    else
+      k_rhs_flux<T, T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
+          M, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
+          c->offAm_d.p, L.Am.p, c->offm_d.p, c->summ, L.F.p, c->sumP, c->sumD, hD, c->psi_loc.p, c->l_loc.p);
+    HIPCHK(hipGetLastError());
+  }
+  // ---- b of eq. nn-mixed
+  OpArgs<T> a = op_args<T>(c, nrhs);
+  run_phases_after_stage1<T>(c, a, nrhs, hP);
+  if (c->nD > 0) {
+    k_ph_sum_w<T><<<dim3(ceil_div(c->nD, kBlock), nrhs), kBlock, 0, s>>>(a, c->cg_b.p);
+    HIPCHK(hipGetLastError());
+  }
+  if (c->nP > 0) {
+    k_save_pif<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->c1.p, c->pif.p);
+    HIPCHK(hipGetLastError());
+  }
+  c->mark(6);
+  HIPCHK(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  // ---- CG
+  if (c->nD > 0) {
+    const int mode = c->opt.cg_mode == 0 ? (nrhs <= 16 ? 2 : 1) : c->opt.cg_mode;
+    if (mode == 2) cg_persistent<T>(c, nrhs, tol);
+    else cg_multilaunch<T>(c, nrhs, tol);
+    std::vector<double> sc((size_t)nrhs * 8);
+    unsigned fl[8];
+    HIPCHK(hipMemcpyAsync(sc.data(), c->cg_scal.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (fl[0] & 1u) c->fail(DDELM_E_HIP, "device grid barrier wait expired");
+    for (int r = 0; r < nrhs; ++r) {
+      res.iters = std::max(res.iters, (int)sc[8 * r + 6]);
+      const double rr = sc[8 * r], bb = sc[8 * r + 1];
+      if (!(rr == rr)) c->fail(DDELM_E_NONFINITE, "NaN in CG");
+      res.relres = std::max(res.relres, bb > 0 ? std::sqrt(rr / bb) : 0.0);
+      if (sc[8 * r + 5] == 0.0) res.noconv = true;
+    }
+  }
+  c->mark(7);
+  auto t2 = std::chrono::steady_clock::now();
+  // ---- recovery: mu_Pi = pi_f - [S^-1 (rho + D^T psi)](mu_D); c = c_f0 + E mu
+  if (c->nP > 0) {
+    if (c->nD > 0) {
+      const size_t sm = local_smem(c);
+      k_ph_local_v<T><<<dim3(N, nrhs), kBlock, sm, s>>>(a, c->cg_x.p);
+      k_ph_coarse1<T><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
+      HIPCHK(hipGetLastError());
+    } else {
+      fill(s, c->c1.p, (long long)nrhs * 2 * c->nP, 0.0);
+    }
+    k_mu_pi<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->pif.p, c->c1.p, c->pif.p);
+    HIPCHK(hipGetLastError());
+  }
+  k_recover<T><<<dim3(N, nrhs), kBlock, (size_t)std::max(c->geo.max_nG, 1) * sizeof(double), s>>>(
+      M, c->nP, c->nD, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->qrdesc.p, L.qrA.p, c->offm_d.p, c->summ,
+      L.F.p, c->pif.p, c->cg_x.p, N, coef, accumulate);
+  HIPCHK(hipGetLastError());
+  if (mu_pi_out && c->nP > 0)
+    HIPCHK(hipMemcpyAsync(mu_pi_out, c->pif.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (mu_dl_out && c->nD > 0)
+    HIPCHK(hipMemcpyAsync(mu_dl_out, c->cg_x.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
+  c->mark(8);
+  HIPCHK(hipStreamSynchronize(s));
+  auto t3 = std::chrono::steady_clock::now();
+  c->phase_ms[4] += c->span(5, 6);
+  c->phase_ms[5] += c->span(6, 7);
+  c->phase_ms[6] += c->span(7, 8);
+  res.ms_rhs = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  res.ms_cg = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  res.ms_rec = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  return res;
+}
+
+// sums over rhs of |dx|^2 and |x|^2 after x += dx (host result per rhs)
+void axpy_norms(ddelm_ctx c, const double* dx, double* x, int n, int nrhs, std::vector<double>& dn,
+                std::vector<double>& xn) {
+  dn.assign(nrhs, 0.0);
+  xn.assign(nrhs, 0.0);
+  if (n <= 0) return;
+  const int nblk = std::max(1, std::min(256, ceil_div(n, kBlock)));
+  k_axpy_norms<<<dim3(nblk, nrhs), kBlock, 0, c->stream>>>(dx, x, n, nblk, c->nrm_part.p);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h((size_t)nrhs * nblk * 2);
+  HIPCHK(hipMemcpyAsync(h.data(), c->nrm_part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int r = 0; r < nrhs; ++r)
+    for (int b = 0; b < nblk; ++b) {
+      dn[r] += h[((size_t)r * nblk + b) * 2];
+      xn[r] += h[((size_t)r * nblk + b) * 2 + 1];
+    }
 }
 
 }  // namespace
@@ -773,7 +926,10 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     if (o.coarse < 0 || o.coarse > 2) c->fail(DDELM_E_ARG, "coarse must be 0, 1 or 2");
     if (o.coarse == 0 && o.theta != 0.0)
       c->fail(DDELM_E_ARG, "theta must be 0 without a coarse space (Kbar needs Dirichlet corner rows)");
-    if (o.precision != 0) c->fail(DDELM_E_ARG, "precision 1 (mixed) is not available in this build");
+    if (o.precision != 0 && o.precision != 1) c->fail(DDELM_E_ARG, "precision must be 0 or 1");
+    if (o.precision == 1 && !(o.refine_maxit >= 1 && o.refine_tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0))
+      c->fail(DDELM_E_ARG, "refinement options out of range");
+    c->mixed = o.precision == 1;
     if (!(o.tol > 0.0 && o.tol < 1.0)) c->fail(DDELM_E_ARG, "tol must lie in (0, 1)");
     if (o.maxit < 1) c->fail(DDELM_E_ARG, "maxit must be >= 1");
     if (o.max_nrhs < 1 || o.max_nrhs > 64) c->fail(DDELM_E_ARG, "max_nrhs must lie in [1, 64]");
@@ -862,369 +1018,148 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
   if (!c) return DDELM_E_ARG;
   return run_guarded(c, [&]() {
     if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
-    hipStream_t s = c->stream;
-    const int N = c->N, M = c->M;
-    const Geometry& g = c->geo;
-    const bool nn = c->use_nn;
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipStreamSynchronize(c->stream));
     c->arena.reset();
-    const int nmat = nn ? 2 * N : N;
-    // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
-    c->h_qrdesc.assign(nmat, QRDesc());
-    long long off = 0, toff = 0;
-    c->max_ncols = 0;
-    for (int b = 0; b < nmat; ++b) {
-      const int i = b % N;
-      QRDesc d;
-      d.off = off; d.m = c->h_m[i]; d.ld = c->h_m[i];
-      d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
-      d.nrefl = M; d.tau = toff; d.pad = 0;
-      c->h_qrdesc[b] = d;
-      off += (long long)d.ld * d.ncols;
-      toff += M;
-      c->max_ncols = std::max(c->max_ncols, d.ncols);
-    }
-    c->qrA.alloc(off);
-    c->tau.alloc(toff);
-    c->qrA.zero(s);
-    c->qrdesc.upload(c->h_qrdesc, s);
-    {
-      std::vector<long long> coff(nmat);
-      std::vector<int> ldc(nmat), cn(nmat);
-      for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
-      c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
-    }
-    c->mark(0);
-    // ---- features: K_c (and Kbar) into the first M columns; A_m, Abar separately
-    {
-      std::vector<long long> o1(N), o2(N);
-      std::vector<int> l1(N);
-      for (int i = 0; i < N; ++i) { o1[i] = c->h_qrdesc[i].off; l1[i] = c->h_m[i]; }
-      assemble_features(c, c->rsK, g.max_m, c->qrA.p, o1, l1, 0, N);
-      if (nn) {
-        for (int i = 0; i < N; ++i) o2[i] = c->h_qrdesc[N + i].off;
-        assemble_features(c, c->rsKb, g.max_m, c->qrA.p, o2, l1, 0, N);
-      }
-      c->h_offAm.assign(N + 1, 0);
-      c->h_offCD.assign(N + 1, 0);
-      for (int i = 0; i < N; ++i) {
-        c->h_offAm[i + 1] = c->h_offAm[i] + (long long)c->h_nG[i] * M;
-        c->h_offCD[i + 1] = c->h_offCD[i] + (long long)c->h_nD[i] * M;
-      }
-      c->Am.alloc(std::max(c->h_offAm[N], 1ll));
-      std::vector<int> ldA(c->h_nG.begin(), c->h_nG.end());
-      assemble_features(c, c->rsA, g.max_nG, c->Am.p, std::vector<long long>(c->h_offAm.begin(), c->h_offAm.end() - 1),
-                        ldA, 0, N);
-      if (nn) {
-        c->CD.alloc(std::max(c->h_offCD[N], 1ll));
-        std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
-        assemble_features(c, c->rsAb, g.max_nD, c->CD.p,
-                          std::vector<long long>(c->h_offCD.begin(), c->h_offCD.end() - 1), ldC, 0, N);
-      }
-      // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
-      // M+t has a 1 at flux row n_I+n_B+n_P+t
-      std::vector<long long> pos;
-      for (int b = 0; b < nmat; ++b) {
-        const int i = b % N;
-        const QRDesc& d = c->h_qrdesc[b];
-        const SubInfo& sb = g.subs[i];
-        const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
-        const int cnt = b < N ? sb.n_G() : sb.n_D;
-        for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
-      }
-      if (!pos.empty()) {
-        const long long* dp = c->arena.put(pos, s);
-        k_set_units<<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), c->qrA.p);
-        HIPCHK(hipGetLastError());
-      }
-    }
-    c->mark(1);
-    // ---- blocked Householder QR of all matrices: 16-column panels, WY updates on MFMA
-    {
-      const int rpt = rows_per_thread(g.max_m);
-      c->npanel = ceil_div(M, kNB);
-      c->Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
-      for (int p = 0; p < c->npanel; ++p) {
-        const int k = p * kNB;
-        launch_qr_panel16<double>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, c->qrA.p, c->tau.p, c->Tbuf.p, k, p, c->npanel);
-        const int c0 = k + std::min(kNB, M - k);
-        const int ntile = ceil_div(c->max_ncols - c0, kUC);
-        if (ntile > 0) {
-          k_qr_wy<double><<<dim3(nmat, ntile), kBlock, 0, s>>>(c->qrdesc.p, c->qrA.p, c->Tbuf.p, k, p, c->npanel,
-                                                               c->qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
-          HIPCHK(hipGetLastError());
-        }
-      }
-    }
-    c->mark(2);
-    // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T in place, Xbar = Rbar^{-1} Qbar_D^T in place
-    {
-      c->h_offQG.assign(N + 1, 0);
-      for (int i = 0; i < N; ++i) c->h_offQG[i + 1] = c->h_offQG[i] + (long long)M * c->h_nG[i];
-      c->QG.alloc(std::max(c->h_offQG[N], 1ll));
-      std::vector<CopyDesc> cp;
-      for (int i = 0; i < N; ++i) {
-        const QRDesc& d = c->h_qrdesc[i];
-        if (c->h_nG[i] == 0) continue;
-        cp.push_back(CopyDesc{d.off + (long long)M * d.ld, c->h_offQG[i], d.ld, M, M, c->h_nG[i], 0, 0});
-      }
-      copy_batch<double>(c, cp, c->qrA.p, c->QG.p);
-      // triangular solves on the appended columns
-      std::vector<long long> xoff(nmat);
-      std::vector<int> ldx(nmat), xn(nmat);
-      int maxx = 0;
-      for (int b = 0; b < nmat; ++b) {
-        const QRDesc& d = c->h_qrdesc[b];
-        xoff[b] = d.off + (long long)M * d.ld;
-        ldx[b] = d.ld;
-        xn[b] = d.ncols - M;
-        maxx = std::max(maxx, xn[b]);
-      }
-      if (maxx > 0) {
-        const long long* dxo = c->arena.put(xoff, s);
-        const int* dld = c->arena.put(ldx, s);
-        const int* dxn = c->arena.put(xn, s);
-        const size_t smt = (size_t)M * kTRSMC * sizeof(double);
-        if (smt > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_trsm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smt));
-        k_trsm<double><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, c->qrA.p, c->qrA.p, dxo,
-                                                                               dld, dxn, 0);
-        HIPCHK(hipGetLastError());
-      }
-    }
-    // ---- local interface operators
-    {
-      c->h_offG.assign(N + 1, 0);
-      c->h_offN.assign(N + 1, 0);
-      for (int i = 0; i < N; ++i) {
-        c->h_offG[i + 1] = c->h_offG[i] + (long long)c->h_nG[i] * c->h_nG[i];
-        c->h_offN[i + 1] = c->h_offN[i] + (long long)c->h_nD[i] * c->h_nD[i];
-      }
-      const size_t nGt = std::max(c->h_offG[N], 1ll), nNt = std::max(c->h_offN[N], 1ll);
-      c->Gm.alloc(nGt); c->Lm.alloc(nGt); c->LTm.alloc(nGt);
-      c->Nm.alloc(nNt); c->NTm.alloc(nNt);
-      c->Gm.zero(s); c->Lm.zero(s); c->LTm.zero(s); c->Nm.zero(s); c->NTm.zero(s);
-      c->offG.upload(std::vector<long long>(c->h_offG.begin(), c->h_offG.end() - 1), s);
-      c->offN.upload(std::vector<long long>(c->h_offN.begin(), c->h_offN.end() - 1), s);
-      std::vector<GemmDesc> gG, gL, gN;
-      std::vector<CopyDesc> tL, tN;
-      for (int i = 0; i < N; ++i) {
-        const int ng = c->h_nG[i], nd = c->h_nD[i];
-        const QRDesc& d = c->h_qrdesc[i];
-        if (ng == 0) continue;
-        // G = -(Q_G^T)^T (Q_G^T) (+ I below)
-        gG.push_back(GemmDesc{c->h_offQG[i], c->h_offQG[i], c->h_offG[i], M, M, ng, ng, ng, M});
-        // L = A_m E
-        gL.push_back(GemmDesc{c->h_offAm[i], d.off + (long long)M * d.ld, c->h_offG[i], ng, d.ld, ng, ng, ng, M});
-        tL.push_back(CopyDesc{c->h_offG[i], c->h_offG[i], ng, ng, ng, ng, 1, 0});
-        if (nn && nd > 0) {
-          const QRDesc& db = c->h_qrdesc[N + i];
-          gN.push_back(GemmDesc{c->h_offCD[i], db.off + (long long)M * db.ld, c->h_offN[i], nd, db.ld, nd, nd, nd, M});
-          tN.push_back(CopyDesc{c->h_offN[i], c->h_offN[i], nd, nd, nd, nd, 1, 0});
-        }
-      }
-      gemm_batch<double>(c, gG, c->QG.p, c->QG.p, c->Gm.p, 1, -1.0, 0.0);
-      {
-        std::vector<long long> o;
-        std::vector<int> n;
-        for (int i = 0; i < N; ++i) if (c->h_nG[i]) { o.push_back(c->h_offG[i]); n.push_back(c->h_nG[i]); }
-        if (!o.empty()) {
-          const long long* dO = c->arena.put(o, s);
-          const int* dn = c->arena.put(n, s);
-          k_add_diag<<<(unsigned)o.size(), kBlock, 0, s>>>(dO, dn, c->Gm.p, 1.0);
-          HIPCHK(hipGetLastError());
-        }
-      }
-      // A_m and E live in different buffers: run the GEMM with A = Am, B = qrA
-      if (!gL.empty()) {
-        int mm = 0, nn2 = 0;
-        for (auto& q : gL) { mm = std::max(mm, q.m); nn2 = std::max(nn2, q.n); }
-        const GemmDesc* dd = c->arena.put(gL, s);
-        k_gemm<double, double><<<dim3(ceil_div(mm, 16), ceil_div(nn2, 16), (unsigned)gL.size()), kBlock, 0, s>>>(
-            dd, c->Am.p, c->qrA.p, c->Lm.p, 0, 1.0, 0.0);
-        HIPCHK(hipGetLastError());
-      }
-      copy_batch<double>(c, tL, c->Lm.p, c->LTm.p);
-      if (!gN.empty()) {
-        int mm = 0, nn2 = 0;
-        for (auto& q : gN) { mm = std::max(mm, q.m); nn2 = std::max(nn2, q.n); }
-        const GemmDesc* dd = c->arena.put(gN, s);
-        k_gemm<double, double><<<dim3(ceil_div(mm, 16), ceil_div(nn2, 16), (unsigned)gN.size()), kBlock, 0, s>>>(
-            dd, c->CD.p, c->qrA.p, c->Nm.p, 0, 1.0, 0.0);
-        HIPCHK(hipGetLastError());
-        copy_batch<double>(c, tN, c->Nm.p, c->NTm.p);
-      }
-    }
-    c->mark(3);
-    // ---- coarse problem: D_PiPi, S_Pi = sum G_PiPi + D^T D, Cholesky, inverse, X1
-    if (c->nP > 0) {
-      const int n = c->nP;
-      const size_t nn2 = (size_t)n * n;
-      c->Dpp.alloc(nn2); c->Gs.alloc(nn2); c->Spi.alloc(nn2); c->Sfac.alloc(nn2); c->Sinv.alloc(nn2);
-      c->Zm.alloc(nn2); c->Ztm.alloc(nn2); c->Wm.alloc(nn2); c->X1.alloc(4 * nn2);
-      c->Dpp.zero(s); c->Gs.zero(s);
-      k_coarse_assemble<double><<<ceil_div(n, kBlock), kBlock, 0, s>>>(n, c->pi_own_ptr.p, c->pi_own_slot.p,
-                                                                       c->pi_slot_sub.p, c->pi_off.p, c->pi_l2g.p,
-                                                                       c->offG.p, c->nG_dev.p, c->Gm.p, c->Lm.p,
-                                                                       c->Dpp.p, c->Gs.p);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(c->Spi.p, c->Gs.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Dpp.p, c->Spi.p, 1, 1.0, 1.0);
-      HIPCHK(hipMemcpyAsync(c->Sfac.p, c->Spi.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemsetAsync(c->flags.p, 0, 8 * sizeof(unsigned), s));
-      k_cholesky<<<1, kBlock, 0, s>>>(c->Sfac.p, n, c->flags.p);
-      HIPCHK(hipGetLastError());
-      const size_t smi = (size_t)n * 4 * sizeof(double);
-      if (smi > 160 * 1024) c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
-      if (smi > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smi));
-      k_chol_inverse<<<ceil_div(n, 4), kBlock, smi, s>>>(c->Sfac.p, n, c->Sinv.p);
-      HIPCHK(hipGetLastError());
-      // Z = D Sinv, Zt = Z^T, W = D Zt, X1
-      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Sinv.p, c->Zm.p, 0, 1.0, 0.0);
-      copy_batch<double>(c, {CopyDesc{0, 0, n, n, n, n, 1, 0}}, c->Zm.p, c->Ztm.p);
-      gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Ztm.p, c->Wm.p, 0, 1.0, 0.0);
-      k_assemble_X1<<<std::min(ceil_div(4ll * nn2, kBlock), 4096), kBlock, 0, s>>>(n, c->Sinv.p, c->Zm.p, c->Wm.p,
-                                                                                   c->X1.p);
-      HIPCHK(hipGetLastError());
-    } else {
-      c->X1.alloc(1);
-    }
-    c->mark(4);
-    // offsets used by every solve
-    c->offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
-    c->offB_d.upload(std::vector<long long>(c->h_offB.begin(), c->h_offB.end() - 1), s);
-    c->offQG_d.upload(std::vector<long long>(c->h_offQG.begin(), c->h_offQG.end() - 1), s);
-    c->offAm_d.upload(std::vector<long long>(c->h_offAm.begin(), c->h_offAm.end() - 1), s);
-    unsigned fl[8];
-    HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (fl[0] & 2u) c->fail(DDELM_E_CHOLESKY, "S_Pi is not positive definite");
-    for (int k = 0; k < 4; ++k) c->phase_ms[k] = c->span(k, k + 1);
+    c->factored = false;
+    if (c->mixed) factor_impl<float>(c);
+    else factor_impl<double>(c);
     c->factored = true;
   });
 }
 
-ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, double* coef, double* mu_pi,
-                         double* mu_dl, ddelm_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of ddelm_solve (f_I, g_B given) and ddelm_solve_general (f_loc, h given).
+ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, const double* f_loc,
+                       const double* h, double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats) {
   if (!c) return DDELM_E_ARG;
-  int iters = 0;
-  double relres = 0.0;
   bool noconv = false;
-  ddelm_status st = run_guarded(c, [&]() {
-    if (!c->factored) c->fail(DDELM_E_STATE, "ddelm_solve called before ddelm_factor");
+  ddelm_stats st{};
+  const bool general = f_loc != nullptr;
+  ddelm_status code = run_guarded(c, [&]() {
+    if (!c->factored) c->fail(DDELM_E_STATE, "solve called before ddelm_factor");
     if (nrhs < 1 || nrhs > c->opt.max_nrhs) c->fail(DDELM_E_ARG, "nrhs out of range");
-    if (!f_I || !coef || (!g_B && c->geo.sum_nB > 0)) c->fail(DDELM_E_ARG, "null array");
+    if (!coef || (!general && (!f_I || (!g_B && c->geo.sum_nB > 0)))) c->fail(DDELM_E_ARG, "null array");
     hipStream_t s = c->stream;
-    const int N = c->N, M = c->M;
+    const int N = c->N;
     alloc_solve_workspace(c, nrhs);
-    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
-    c->mark(5);
-    const DBuf<long long>& offm_d = c->offm_d;
-    const DBuf<long long>& offB_d = c->offB_d;
-    // ---- f, Q^T f, projections, K^+ f, fluxes
-    k_rhs_assemble<<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, offm_d.p, offB_d.p, c->summ,
-                                                     c->geo.sum_nB, f_I, g_B, c->F.p);
-    HIPCHK(hipGetLastError());
-    const int rpt = rows_per_thread(c->geo.max_m);
-    for (int p = 0; p < c->npanel; ++p) {
-      k_qr_wy<double><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, c->qrA.p, c->Tbuf.p, p * kNB, p,
-                                                                      c->npanel, c->F.p, c->f_off.p, c->f_ld.p,
-                                                                      c->f_cn.p, 0, 1);
-      HIPCHK(hipGetLastError());
-    }
-    (void)rpt;
-    const DBuf<long long>& offQG_d = c->offQG_d;
-    const DBuf<long long>& offAm_d = c->offAm_d;
-    k_rhs_proj<<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
-                                                                  offQG_d.p, c->QG.p, offm_d.p, c->summ, c->F.p,
-                                                                  c->sumP, c->sumD, c->rho_loc.p, c->s_loc.p);
-    HIPCHK(hipGetLastError());
-    {
-      const size_t smt = (size_t)M * kTRSMC * sizeof(double);
-      const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
-      k_trsm<double><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, c->qrA.p, c->F.p, c->f_off.p,
-                                                                          c->f_ld.p, cnM, 0);
-      HIPCHK(hipGetLastError());
-      k_rhs_flux<<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
-                                                                    offAm_d.p, c->Am.p, offm_d.p, c->summ, c->F.p,
-                                                                    c->sumP, c->sumD, c->psi_loc.p, c->l_loc.p);
-      HIPCHK(hipGetLastError());
-    }
-    // ---- b of eq. nn-mixed
-    OpArgs<double> a = op_args(c, nrhs);
-    run_phases_after_stage1(c, a, nrhs, nullptr);
-    if (c->nD > 0) {
-      k_ph_sum_w<double><<<dim3(ceil_div(c->nD, kBlock), nrhs), kBlock, 0, s>>>(a, c->cg_b.p);
-      HIPCHK(hipGetLastError());
-    }
-    if (c->nP > 0) {
-      k_save_pif<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->c1.p, c->pif.p);
-      HIPCHK(hipGetLastError());
-    }
-    c->mark(6);
-    HIPCHK(hipStreamSynchronize(s));
-    auto t1 = std::chrono::steady_clock::now();
-    // ---- CG
-    if (c->nD > 0) {
-      int mode = c->opt.cg_mode == 0 ? (nrhs <= 16 ? 2 : 1) : c->opt.cg_mode;
-      if (mode == 2) cg_persistent(c, nrhs);
-      else cg_multilaunch(c, nrhs);
-      std::vector<double> sc((size_t)nrhs * 8);
-      unsigned fl[8];
-      HIPCHK(hipMemcpyAsync(sc.data(), c->cg_scal.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (fl[0] & 1u) c->fail(DDELM_E_HIP, "device grid barrier wait expired");
-      for (int r = 0; r < nrhs; ++r) {
-        iters = std::max(iters, (int)sc[8 * r + 6]);
-        const double rr = sc[8 * r], bb = sc[8 * r + 1];
-        if (!(rr == rr)) c->fail(DDELM_E_NONFINITE, "NaN in CG");
-        relres = std::max(relres, bb > 0 ? std::sqrt(rr / bb) : 0.0);
-        if (sc[8 * r + 5] == 0.0) noconv = true;
+    c->phase_ms[4] = c->phase_ms[5] = c->phase_ms[6] = 0.0;
+    auto acc = [&](const CoreOut& o) {
+      st.iters += o.iters;
+      st.rel_res = o.relres;
+      st.ms_rhs += o.ms_rhs;
+      st.ms_cg += o.ms_cg;
+      st.ms_recover += o.ms_rec;
+      noconv = noconv || o.noconv;
+    };
+    // flux right-hand side of a general solve, split into the Pi and Delta blocks
+    const double* h0P = nullptr;
+    const double* h0D = nullptr;
+    if (general && h) {
+      const int nG = c->nP + c->nD;
+      if (c->nP) {
+        HIPCHK(hipMemcpy2DAsync(c->hP0.p, c->nP * sizeof(double), h, nG * sizeof(double), c->nP * sizeof(double), nrhs,
+                                hipMemcpyDeviceToDevice, s));
+        h0P = c->hP0.p;
       }
+      if (c->nD) {
+        HIPCHK(hipMemcpy2DAsync(c->hD0.p, c->nD * sizeof(double), h + c->nP, nG * sizeof(double),
+                                c->nD * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+        h0D = c->hD0.p;
+      }
+    }
+    const double* f0P = general ? c->fGP0.p : nullptr;
+    const double* f0D = general ? c->fGD0.p : nullptr;
+    if (!c->mixed) {
+      if (general)
+        k_rhs_split<double><<<dim3(N, nrhs), kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p,
+                                                             c->summ, c->sumP, c->sumD, f_loc, c->l64.F.p, nullptr,
+                                                             c->fGP0.p, c->fGD0.p);
+      else
+        k_rhs_assemble<double><<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p,
+                                                                c->offB_d.p, c->summ, c->geo.sum_nB, f_I, g_B,
+                                                                c->l64.F.p, nullptr);
+      HIPCHK(hipGetLastError());
+      acc(solve_core<double>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.tol, coef, 0, mu_pi, mu_dl));
     } else {
-      HIPCHK(hipStreamSynchronize(s));
-    }
-    c->mark(7);
-    auto t2 = std::chrono::steady_clock::now();
-    // ---- recovery: mu_Pi = pi_f - [S^-1 (rho + D^T psi)](mu_D); c = c_f0 + E mu
-    if (c->nP > 0) {
-      if (c->nD > 0) {
-        const size_t sm = local_smem(c);
-        k_ph_local_v<double><<<dim3(N, nrhs), kBlock, sm, s>>>(a, c->cg_x.p);
-        k_ph_coarse1<double><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
-        HIPCHK(hipGetLastError());
-      } else {
-        fill(s, c->c1.p, (long long)nrhs * 2 * c->nP, 0.0);
-      }
-      k_mu_pi<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->pif.p, c->c1.p, c->pif.p);
+      // float32 local solves, refined on the float64 residual of the coupled system
+      DBuf<double> muP, muD;
+      muP.alloc((size_t)nrhs * std::max(c->nP, 1));
+      muD.alloc((size_t)nrhs * std::max(c->nD, 1));
+      muP.zero(s);
+      muD.zero(s);
+      if (general)
+        k_rhs_split<float><<<dim3(N, nrhs), kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p,
+                                                            c->summ, c->sumP, c->sumD, f_loc, c->l32.F.p, c->F64.p,
+                                                            c->fGP0.p, c->fGD0.p);
+      else
+        k_rhs_assemble<float><<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p, c->offB_d.p,
+                                                               c->summ, c->geo.sum_nB, f_I, g_B, c->l32.F.p, c->F64.p);
       HIPCHK(hipGetLastError());
-    }
-    k_recover<<<dim3(N, nrhs), kBlock, (size_t)std::max(c->geo.max_nG, 1) * sizeof(double), s>>>(
-        M, c->nP, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->qrdesc.p, c->qrA.p,
-        offm_d.p, c->summ, c->F.p, c->pif.p, c->cg_x.p, N, coef);
-    HIPCHK(hipGetLastError());
-    if (mu_pi && c->nP > 0)
-      HIPCHK(hipMemcpyAsync(mu_pi, c->pif.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (mu_dl && c->nD > 0)
-      HIPCHK(hipMemcpyAsync(mu_dl, c->cg_x.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
-    c->mark(8);
-    HIPCHK(hipStreamSynchronize(s));
-    auto t3 = std::chrono::steady_clock::now();
-    c->phase_ms[4] = c->span(5, 6);
-    c->phase_ms[5] = c->span(6, 7);
-    c->phase_ms[6] = c->span(7, 8);
-    if (stats) {
-      stats->iters = iters;
-      stats->refine_steps = 0;
-      stats->rel_res = relres;
-      stats->ms_rhs = std::chrono::duration<double, std::milli>(t1 - t0).count();
-      stats->ms_cg = std::chrono::duration<double, std::milli>(t2 - t1).count();
-      stats->ms_recover = std::chrono::duration<double, std::milli>(t3 - t2).count();
+      acc(solve_core<float>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.inner_tol, coef, 0, muP.p, muD.p));
+      const size_t shm = (size_t)c->M * sizeof(double);
+      for (int step = 0; step < c->opt.refine_maxit; ++step) {
+        k_residual<<<dim3(N, nrhs), kBlock, shm, s>>>(
+            c->M, c->nP, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,
+            c->K64.p, c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP, c->sumD,
+            c->R64.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p);
+        HIPCHK(hipGetLastError());
+        if (c->nP + c->nD > 0) {
+          k_flux_residual<<<dim3(ceil_div(c->nP + c->nD, kBlock), nrhs), kBlock, 0, s>>>(
+              c->nP, c->nD, c->sumP, c->sumD, c->pi_own_ptr.p, c->pi_own_slot.p, c->dl_own_ptr.p, c->dl_own_slot.p,
+              c->aP.p, c->aD.p, h0P, h0D, c->hPb.p, c->hDb.p);
+          HIPCHK(hipGetLastError());
+        }
+        convert<double, float>(s, c->R64.p, c->l32.F.p, (long long)nrhs * c->summ);
+        acc(solve_core<float>(c, nrhs, c->fGP.p, c->fGD.p, c->nP ? c->hPb.p : nullptr, c->nD ? c->hDb.p : nullptr,
+                              c->opt.inner_tol, coef, 1, c->dmup.p, c->dmud.p));
+        st.refine_steps += 1;
+        std::vector<double> dn, xn, dpn, xpn;
+        axpy_norms(c, c->dmud.p, muD.p, c->nD, nrhs, dn, xn);
+        axpy_norms(c, c->dmup.p, muP.p, c->nP, nrhs, dpn, xpn);
+        double worst = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+          const double num = dn[r] + dpn[r], den = xn[r] + xpn[r];
+          worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
+        }
+        if (worst <= c->opt.refine_tol) break;
+      }
+      if (mu_pi && c->nP > 0)
+        HIPCHK(hipMemcpyAsync(mu_pi, muP.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (mu_dl && c->nD > 0)
+        HIPCHK(hipMemcpyAsync(mu_dl, muD.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
     }
   });
-  if (st == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
-  return st;
+  if (stats) *stats = st;
+  if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, double* coef, double* mu_pi,
+                         double* mu_dl, ddelm_stats* stats) {
+  if (!f_I) {
+    if (c) c->err = "f_I is null";
+    return DDELM_E_ARG;
+  }
+  return solve_any(c, nrhs, f_I, g_B, nullptr, nullptr, coef, mu_pi, mu_dl, stats);
+}
+
+ddelm_status ddelm_solve_general(ddelm_ctx c, int nrhs, const double* f_loc, const double* h, double* coef,
+                                 double* mu_pi, double* mu_dl, ddelm_stats* stats) {
+  if (!f_loc) {
+    if (c) c->err = "f_loc is null";
+    return DDELM_E_ARG;
+  }
+  return solve_any(c, nrhs, nullptr, nullptr, f_loc, h, coef, mu_pi, mu_dl, stats);
 }
 
 ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long npts, const double* x, double* u,
@@ -1297,6 +1232,31 @@ ddelm_status ddelm_get_interface_points(ddelm_ctx c, double* x_pi, double* x_dl)
   });
 }
 
+}  // extern "C"
+
+namespace {
+template <typename T>
+void local_matrix_factored(ddelm_ctx c, int which, int sub, int R, int C, double* out) {
+  LocalBufs<T>& L = c->lb<T>();
+  if (which == 4) {
+    const QRDesc& d = c->h_qrdesc[sub];
+    copy_batch<T, double>(c, {CopyDesc{d.off, 0, d.ld, C, R, C, 1, 0}}, L.qrA.p, out);
+    return;
+  }
+  const T* src = nullptr;
+  long long soff = 0;
+  if (which == 5) { src = L.Gm.p; soff = c->h_offG[sub]; }
+  if (which == 6) { src = L.Lm.p; soff = c->h_offG[sub]; }
+  if (which == 7) {
+    if (!c->use_nn) c->fail(DDELM_E_STATE, "no Neumann-Neumann operator with theta = 0");
+    src = L.Nm.p; soff = c->h_offN[sub];
+  }
+  copy_batch<T, double>(c, {CopyDesc{soff, 0, R, C, R, C, 1, 0}}, src, out);
+}
+}  // namespace
+
+extern "C" {
+
 ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out, int* rows, int* cols) {
   if (!c || !rows || !cols) return DDELM_E_ARG;
   return run_guarded(c, [&]() {
@@ -1319,38 +1279,26 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
     hipStream_t s = c->stream;
     HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
-    DBuf<double> tmp;
-    tmp.alloc((size_t)R * C);
-    tmp.zero(s);
-    const double* src = nullptr;
-    long long soff = 0;
-    int ld = R;
     if (which <= 3) {
+      DBuf<double> tmp;
+      tmp.alloc((size_t)R * C);
+      tmp.zero(s);
       const RowSetDev& rs = which == 0 ? c->rsK : which == 1 ? c->rsA : which == 2 ? c->rsKb : c->rsAb;
       std::vector<long long> o(c->N, 0);
       std::vector<int> l(c->N, R);
-      assemble_features(c, rs, R, tmp.p, o, l, sub, 1);
-      src = tmp.p; soff = 0; ld = R;
-      // column-major R x C -> row-major output
-      copy_batch<double>(c, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, src, out);
+      assemble_features<double>(c, rs, R, tmp.p, o, l, sub, 1);
+      copy_batch<double, double>(c, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, tmp.p, out);
       HIPCHK(hipStreamSynchronize(s));
       return;
     }
     if (!c->factored) c->fail(DDELM_E_STATE, "matrix needs ddelm_factor");
-    if (which == 4) {
-      const QRDesc& d = c->h_qrdesc[sub];
-      copy_batch<double>(c, {CopyDesc{d.off, 0, d.ld, C, R, C, 1, 0}}, c->qrA.p, out);
-      HIPCHK(hipStreamSynchronize(s));
-      return;
+    if (which == 8) {
+      copy_batch<double, double>(c, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, c->Spi.p, out);
+    } else if (c->mixed) {
+      local_matrix_factored<float>(c, which, sub, R, C, out);
+    } else {
+      local_matrix_factored<double>(c, which, sub, R, C, out);
     }
-    if (which == 5) { src = c->Gm.p; soff = c->h_offG[sub]; }
-    if (which == 6) { src = c->Lm.p; soff = c->h_offG[sub]; }
-    if (which == 7) {
-      if (!c->use_nn) c->fail(DDELM_E_STATE, "no Neumann-Neumann operator with theta = 0");
-      src = c->Nm.p; soff = c->h_offN[sub];
-    }
-    if (which == 8) src = c->Spi.p;
-    copy_batch<double>(c, {CopyDesc{soff, 0, R, R, R, C, 1, 0}}, src, out);
     HIPCHK(hipStreamSynchronize(s));
   });
 }

@@ -1,0 +1,411 @@
+// Right-hand side, refinement residual, recovery, CG bookkeeping and
+// evaluation kernels.  T is the storage type of the local factors (double,
+// or float in mixed precision); interface vectors are always double.
+#pragma once
+#include "kernels_qr.hpp"
+#include "kernels_solve.hpp"
+
+namespace ddelm {
+
+// sizes[5*i + ...]: 0 M, 1 n_I, 2 n_B, 3 m, 4 n_G
+
+// f^i = [f_I; g_B; 0] into F[r][offm[i] + row] (type T) and optionally into
+// F64 (the double copy kept for refinement residuals)
+template <typename T>
+__global__ void k_rhs_assemble(int N, int n_int, const int* __restrict__ sizes, const long long* __restrict__ offm,
+                               const long long* __restrict__ offB, long long summ, long long sumB,
+                               const double* __restrict__ fI, const double* __restrict__ gB, T* __restrict__ F,
+                               double* __restrict__ F64) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int nB = sizes[5 * i + 2], m = sizes[5 * i + 3];
+  const size_t base = (size_t)r * summ + offm[i];
+  for (int row = threadIdx.x; row < m; row += kBlock) {
+    double v = 0.0;
+    if (row < n_int) v = fI[((size_t)r * N + i) * n_int + row];
+    else if (row < n_int + nB) v = gB[(size_t)r * sumB + offB[i] + row - n_int];
+    F[base + row] = (T)v;
+    if (F64) F64[base + row] = v;
+  }
+}
+
+// A general local right-hand side, given row by row for every subdomain
+// (f64 [nrhs][sum m]), into F (type T) and its interface rows in slot order.
+template <typename T>
+__global__ void k_rhs_split(const int* __restrict__ sizes, const int* __restrict__ pi_off,
+                            const int* __restrict__ dl_off, const long long* __restrict__ offm, long long summ,
+                            int sumP, int sumD, const double* __restrict__ ff, T* __restrict__ F,
+                            double* __restrict__ F64, double* __restrict__ fGP, double* __restrict__ fGD) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int nI = sizes[5 * i + 1], nB = sizes[5 * i + 2], m = sizes[5 * i + 3];
+  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
+  const size_t base = (size_t)r * summ + offm[i];
+  for (int row = threadIdx.x; row < m; row += kBlock) {
+    const double v = ff[base + row];
+    F[base + row] = (T)v;
+    if (F64) F64[base + row] = v;
+    const int g = row - nI - nB;
+    if (g >= 0) {
+      if (g < np) fGP[(size_t)r * sumP + p0 + g] = v;
+      else fGD[(size_t)r * sumD + d0 + g - np] = v;
+    }
+  }
+}
+
+// p_G = Q_G (Q^T f)[:M];  rho_loc = p_P - f_P (Pi slots), s_loc = p_D - f_D
+// (Delta slots), where f_P, f_D are the interface rows of f before Q^T was
+// applied (fGP, fGD; null when they are zero)
+template <typename T>
+__global__ void k_rhs_proj(int M, const int* __restrict__ sizes, const int* __restrict__ pi_off,
+                           const int* __restrict__ dl_off, const long long* __restrict__ offQG,
+                           const T* __restrict__ QG, const long long* __restrict__ offm, long long summ,
+                           const T* __restrict__ F, int sumP, int sumD, const double* __restrict__ fGP,
+                           const double* __restrict__ fGD, double* __restrict__ rho_loc, double* __restrict__ s_loc) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int ng = sizes[5 * i + 4];
+  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
+  extern __shared__ double al[];
+  const T* Fi = F + (size_t)r * summ + offm[i];
+  for (int k = threadIdx.x; k < M; k += kBlock) al[k] = (double)Fi[k];
+  __syncthreads();
+  const T* Q = QG + offQG[i];
+  for (int t = threadIdx.x; t < ng; t += kBlock) {
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) acc += (double)Q[(long long)t * M + k] * al[k];
+    if (t < np) {
+      const size_t e = (size_t)r * sumP + p0 + t;
+      rho_loc[e] = acc - (fGP ? fGP[e] : 0.0);
+    } else {
+      const size_t e = (size_t)r * sumD + d0 + t - np;
+      s_loc[e] = acc - (fGD ? fGD[e] : 0.0);
+    }
+  }
+}
+
+// ad = A_m c_f0;  psi_loc = -ad_P, l_loc = -ad_D (+ h_D at the first owner of
+// each Delta point, so that the owner sum gives h_D - A_D K^+ f)
+template <typename T, typename TA>
+__global__ void k_rhs_flux(int M, int nD, const int* __restrict__ sizes, const int* __restrict__ pi_off,
+                           const int* __restrict__ dl_off, const int* __restrict__ dl_l2g,
+                           const int* __restrict__ dl_own_ptr, const int* __restrict__ dl_own_slot,
+                           const long long* __restrict__ offAm, const TA* __restrict__ Am,
+                           const long long* __restrict__ offm, long long summ, const T* __restrict__ F, int sumP,
+                           int sumD, const double* __restrict__ hD, double* __restrict__ psi_loc,
+                           double* __restrict__ l_loc) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int ng = sizes[5 * i + 4];
+  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
+  extern __shared__ double cf[];
+  const T* Fi = F + (size_t)r * summ + offm[i];
+  for (int k = threadIdx.x; k < M; k += kBlock) cf[k] = (double)Fi[k];
+  __syncthreads();
+  const TA* A = Am + offAm[i];
+  for (int t = threadIdx.x; t < ng; t += kBlock) {
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) acc += (double)A[(long long)k * ng + t] * cf[k];
+    if (t < np) {
+      psi_loc[(size_t)r * sumP + p0 + t] = -acc;
+    } else {
+      const int slot = d0 + t - np;
+      double v = -acc;
+      if (hD) {
+        const int g = dl_l2g[slot];
+        if (dl_own_slot[dl_own_ptr[g]] == slot) v += hD[(size_t)r * nD + g];
+      }
+      l_loc[(size_t)r * sumD + slot] = v;
+    }
+  }
+}
+
+// c^i = c_f0 + E [mu_P(Pi^i); mu_D(Delta^i)], E = R^{-1} Q_G^T kept in the K_c
+// matrix (rows 0..M-1 of columns M.., leading dimension m).  accumulate = 1
+// adds the result to coef instead of overwriting it.
+template <typename T>
+__global__ void k_recover(int M, int nP, int nD, const int* __restrict__ pi_off, const int* __restrict__ dl_off,
+                          const int* __restrict__ pi_l2g, const int* __restrict__ dl_l2g,
+                          const QRDesc* __restrict__ desc, const T* __restrict__ qrA,
+                          const long long* __restrict__ offm, long long summ, const T* __restrict__ F,
+                          const double* __restrict__ mu_pi, const double* __restrict__ mu_dl, int N,
+                          double* __restrict__ coef, int accumulate) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i], nd = dl_off[i + 1] - d0;
+  extern __shared__ double mus[];
+  for (int a = threadIdx.x; a < np + nd; a += kBlock)
+    mus[a] = a < np ? mu_pi[(size_t)r * nP + pi_l2g[p0 + a]] : mu_dl[(size_t)r * nD + dl_l2g[d0 + a - np]];
+  __syncthreads();
+  const QRDesc d = desc[i];
+  const T* E = qrA + d.off + (long long)M * d.ld;
+  const T* Fi = F + (size_t)r * summ + offm[i];
+  for (int k = threadIdx.x; k < M; k += kBlock) {
+    double acc = (double)Fi[k];
+    for (int a = 0; a < np + nd; ++a) acc += (double)E[(long long)a * d.ld + k] * mus[a];
+    const size_t e = ((size_t)r * N + i) * M + k;
+    coef[e] = accumulate ? coef[e] + acc : acc;
+  }
+}
+
+// Residual of the coupled system [K B; A 0][c; mu] = [f; 0] in float64:
+//   R = f - K c - B mu   (B mu is -mu on the interface rows),
+//   flux slots  aP/aD = (A_m c) at the local Pi / Delta rows.
+// K64 (m x M) and A64 (n_G x M) are the float64 feature matrices.
+__global__ void k_residual(int M, int nP, int nD, const int* __restrict__ sizes, const int* __restrict__ pi_off,
+                           const int* __restrict__ dl_off, const int* __restrict__ pi_l2g,
+                           const int* __restrict__ dl_l2g, const long long* __restrict__ offK,
+                           const double* __restrict__ K64, const long long* __restrict__ offAm,
+                           const double* __restrict__ A64, const long long* __restrict__ offm, long long summ,
+                           const double* __restrict__ F64, const double* __restrict__ coef,
+                           const double* __restrict__ mu_pi, const double* __restrict__ mu_dl, int N, int sumP,
+                           int sumD, double* __restrict__ R64, double* __restrict__ fGP, double* __restrict__ fGD,
+                           double* __restrict__ aP, double* __restrict__ aD) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int nI = sizes[5 * i + 1], nB = sizes[5 * i + 2], m = sizes[5 * i + 3], ng = sizes[5 * i + 4];
+  const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
+  extern __shared__ double cs[];
+  for (int k = threadIdx.x; k < M; k += kBlock) cs[k] = coef[((size_t)r * N + i) * M + k];
+  __syncthreads();
+  const double* K = K64 + offK[i];
+  const size_t base = (size_t)r * summ + offm[i];
+  for (int row = threadIdx.x; row < m; row += kBlock) {
+    double acc = F64[base + row];
+    for (int k = 0; k < M; ++k) acc -= K[(long long)k * m + row] * cs[k];
+    const int g = row - nI - nB;
+    if (g >= 0) {
+      if (g < np) {
+        acc += mu_pi[(size_t)r * nP + pi_l2g[p0 + g]];
+        fGP[(size_t)r * sumP + p0 + g] = acc;
+      } else {
+        acc += mu_dl[(size_t)r * nD + dl_l2g[d0 + g - np]];
+        fGD[(size_t)r * sumD + d0 + g - np] = acc;
+      }
+    }
+    R64[base + row] = acc;
+  }
+  const double* A = A64 + offAm[i];
+  for (int t = threadIdx.x; t < ng; t += kBlock) {
+    double acc = 0.0;
+    for (int k = 0; k < M; ++k) acc += A[(long long)k * ng + t] * cs[k];
+    if (t < np) aP[(size_t)r * sumP + p0 + t] = acc;
+    else aD[(size_t)r * sumD + d0 + t - np] = acc;
+  }
+}
+
+// h = h0 - (A c) at the global interface points: hP[r][p], hD[r][g]
+// (h0P, h0D: the flux right-hand side of the original system, may be null)
+__global__ void k_flux_residual(int nP, int nD, int sumP, int sumD, const int* __restrict__ pi_own_ptr,
+                                const int* __restrict__ pi_own_slot, const int* __restrict__ dl_own_ptr,
+                                const int* __restrict__ dl_own_slot, const double* __restrict__ aP,
+                                const double* __restrict__ aD, const double* __restrict__ h0P,
+                                const double* __restrict__ h0D, double* __restrict__ hP, double* __restrict__ hD) {
+  const int e = blockIdx.x * kBlock + threadIdx.x, r = blockIdx.y;
+  if (e < nP) {
+    double s = 0.0;
+    for (int o = pi_own_ptr[e]; o < pi_own_ptr[e + 1]; ++o) s += aP[(size_t)r * sumP + pi_own_slot[o]];
+    hP[(size_t)r * nP + e] = (h0P ? h0P[(size_t)r * nP + e] : 0.0) - s;
+  } else if (e < nP + nD) {
+    const int g = e - nP;
+    double s = 0.0;
+    for (int o = dl_own_ptr[g]; o < dl_own_ptr[g + 1]; ++o) s += aD[(size_t)r * sumD + dl_own_slot[o]];
+    hD[(size_t)r * nD + g] = (h0D ? h0D[(size_t)r * nD + g] : 0.0) - s;
+  }
+}
+
+template <typename TS, typename TD>
+__global__ void k_convert(const TS* __restrict__ s, TD* __restrict__ d, long long n) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock)
+    d[e] = (TD)s[e];
+}
+
+// y += x; partial sums of x.x and y.y per rhs (rows of length n), one block per (chunk, rhs)
+__global__ void k_axpy_norms(const double* __restrict__ x, double* __restrict__ y, int n, int nblk,
+                             double* __restrict__ part) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  double sx = 0.0, sy = 0.0;
+  for (int g = blk * kBlock + threadIdx.x; g < n; g += nblk * kBlock) {
+    const size_t e = (size_t)r * n + g;
+    const double xv = x[e];
+    const double yv = y[e] + xv;
+    y[e] = yv;
+    sx += xv * xv;
+    sy += yv * yv;
+  }
+  sx = block_sum(sx, red);
+  sy = block_sum(sy, red);
+  if (threadIdx.x == 0) {
+    part[((size_t)r * nblk + blk) * 2] = sx;
+    part[((size_t)r * nblk + blk) * 2 + 1] = sy;
+  }
+}
+
+// mu_Pi = pi_f - mu_Pi(v)
+__global__ void k_mu_pi(int nP, int nrhs, const double* __restrict__ pif, const double* __restrict__ c1,
+                        double* __restrict__ out) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nP * nrhs) return;
+  const int r = e / nP, p = e % nP;
+  out[e] = pif[e] - c1[(size_t)r * 2 * nP + p];
+}
+
+__global__ void k_save_pif(int nP, int nrhs, const double* __restrict__ c1, double* __restrict__ pif) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nP * nrhs) return;
+  const int r = e / nP, p = e % nP;
+  pif[e] = c1[(size_t)r * 2 * nP + p];
+}
+
+// set the unit entries of the appended identity columns
+template <typename T>
+__global__ void k_set_units(const long long* __restrict__ pos, long long n, T* __restrict__ A) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) A[pos[e]] = T(1);
+}
+
+// X1 = [[Sinv, Z^T], [-Z, I - W]] (column-major, 2n x 2n) with Z = D Sinv, W = D Z^T
+__global__ void k_assemble_X1(int n, const double* __restrict__ Sinv, const double* __restrict__ Z,
+                              const double* __restrict__ W, double* __restrict__ X1) {
+  const long long tot = 4ll * n * n;
+  const int ld = 2 * n;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < tot; e += (long long)gridDim.x * kBlock) {
+    const int r = (int)(e % ld), c = (int)(e / ld);
+    double v;
+    if (r < n && c < n) v = Sinv[(long long)c * n + r];
+    else if (r < n) v = Z[(long long)r * n + (c - n)];               // Z^T[r][c-n] = Z[c-n][r]
+    else if (c < n) v = -Z[(long long)c * n + (r - n)];
+    else v = (r == c ? 1.0 : 0.0) - W[(long long)(c - n) * n + (r - n)];
+    X1[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------- CG kernels (one launch per phase)
+
+// w = sum of owners, partial p.w
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_wdot(OpArgs<T> a, CGState s) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  double acc = 0.0;
+  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
+    const double wv = dl_sum(a.dl_own_ptr, a.dl_own_slot, a.w_loc + (size_t)r * a.sumD, g);
+    s.w[(size_t)r * s.n + g] = wv;
+    acc += wv * s.p[(size_t)r * s.n + g];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
+}
+
+// alpha = rr / p.w (one block per rhs)
+__global__ void __launch_bounds__(kBlock) k_cg_alpha(CGState s) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.x;
+  const double pw = cg_reduce_parts(s.part, s.nblk, r, red);
+  if (threadIdx.x == 0) {
+    double* sc = s.scal + (size_t)r * 8;
+    sc[2] = pw;
+    sc[3] = (sc[5] != 0.0 || pw == 0.0) ? 0.0 : sc[0] / pw;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_axpy(CGState s) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  const double al = s.scal[(size_t)r * 8 + 3];
+  double acc = 0.0;
+  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
+    const size_t e = (size_t)r * s.n + g;
+    s.x[e] += al * s.p[e];
+    const double rv = s.r[e] - al * s.w[e];
+    s.r[e] = rv;
+    acc += rv * rv;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_beta(CGState s) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.x;
+  const double rr = cg_reduce_parts(s.part, s.nblk, r, red);
+  if (threadIdx.x == 0) {
+    double* sc = s.scal + (size_t)r * 8;
+    if (sc[5] != 0.0) {
+      sc[4] = 0.0;
+    } else {
+      sc[4] = sc[0] > 0.0 ? rr / sc[0] : 0.0;
+      sc[0] = rr;
+      sc[6] += 1.0;
+      if (!(rr == rr) || isinf(rr)) sc[7] = 1.0;
+      if (sqrt(rr) <= s.tol * sqrt(sc[1]) || !(rr == rr)) sc[5] = 1.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_pupd(CGState s) {
+  const int r = blockIdx.y, blk = blockIdx.x;
+  const double be = s.scal[(size_t)r * 8 + 4];
+  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
+    const size_t e = (size_t)r * s.n + g;
+    s.p[e] = s.r[e] + be * s.p[e];
+  }
+}
+
+// r = p = b, x = 0; partial b.b
+__global__ void __launch_bounds__(kBlock) k_cg_init(CGState s, const double* __restrict__ b) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  double acc = 0.0;
+  for (int g = blk * kBlock + threadIdx.x; g < s.n; g += s.nblk * kBlock) {
+    const size_t e = (size_t)r * s.n + g;
+    const double bv = b[e];
+    s.x[e] = 0.0;
+    s.r[e] = bv;
+    s.p[e] = bv;
+    acc += bv * bv;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) s.part[(size_t)r * s.nblk + blk] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
+  __shared__ double red[kWaves];
+  const int r = blockIdx.x;
+  const double bb = cg_reduce_parts(s.part, s.nblk, r, red);
+  if (threadIdx.x == 0) {
+    double* sc = s.scal + (size_t)r * 8;
+    sc[0] = bb; sc[1] = bb; sc[2] = 0; sc[3] = 0; sc[4] = 0;
+    sc[5] = (bb == 0.0) ? 1.0 : 0.0;
+    sc[6] = 0; sc[7] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- evaluation
+__global__ void k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0, double h1,
+                           const double* __restrict__ W, const double* __restrict__ bias,
+                           const double* __restrict__ coef, long long npts, const double* __restrict__ x,
+                           double* __restrict__ u, double* __restrict__ grad, int r) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= npts) return;
+  const double px = x[2 * e], py = x[2 * e + 1];
+  int ix = (int)ceil((px - lo0) / h0) - 1, iy = (int)ceil((py - lo1) / h1) - 1;
+  ix = ix < 0 ? 0 : (ix > nx - 1 ? nx - 1 : ix);
+  iy = iy < 0 ? 0 : (iy > ny - 1 ? ny - 1 : iy);
+  const int i = iy * nx + ix;
+  const double hx = 0.5 * h0, hy = 0.5 * h1;
+  const double cx = lo0 + (ix + 0.5) * h0, cy = lo1 + (iy + 0.5) * h1;
+  const double xi0 = (px - cx) / hx, xi1 = (py - cy) / hy;
+  const double* c = coef + ((size_t)r * N + i) * M;
+  double acc = 0.0, g0 = 0.0, g1 = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const double w0 = W[((size_t)i * M + j) * 2], w1 = W[((size_t)i * M + j) * 2 + 1];
+    const double t = tanh(w0 * xi0 + w1 * xi1 + bias[(size_t)i * M + j]);
+    acc += c[j] * t;
+    const double dt = c[j] * (1.0 - t * t);
+    g0 += dt * w0;
+    g1 += dt * w1;
+  }
+  u[(size_t)r * npts + e] = acc;
+  if (grad) {
+    grad[((size_t)r * npts + e) * 2] = g0 / hx;
+    grad[((size_t)r * npts + e) * 2 + 1] = g1 / hy;
+  }
+}
+
+}  // namespace ddelm

@@ -282,9 +282,9 @@ struct GemmDesc {
   int m, n, k;
 };
 
-template <typename TA, typename TC>
+template <typename TA, typename TB, typename TC>
 __global__ void __launch_bounds__(kBlock) k_gemm(const GemmDesc* __restrict__ desc, const TA* __restrict__ A,
-                                                 const TA* __restrict__ B, TC* __restrict__ C, int transA,
+                                                 const TB* __restrict__ B, TC* __restrict__ C, int transA,
                                                  double alpha, double beta) {
   const GemmDesc g = desc[blockIdx.z];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;

@@ -178,6 +178,32 @@ class DDELMSolver:
                      ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
         return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
 
+    def solve_general(self, f_loc, h=None, want_mu: bool = True):
+        """General right-hand side: f_loc (nrhs, sum m) on every local row, h
+        (nrhs, n_pi + n_dl) on the flux rows (None = 0)."""
+        dev = self.device
+        f_loc = torch.as_tensor(f_loc, dtype=torch.float64, device=dev).contiguous()
+        if f_loc.ndim == 1:
+            f_loc = f_loc[None]
+        nrhs = f_loc.shape[0]
+        summ = int(self.counts()["m"].sum())
+        assert f_loc.shape == (nrhs, summ), f_loc.shape
+        hh = None
+        if h is not None:
+            hh = torch.as_tensor(h, dtype=torch.float64, device=dev).contiguous().reshape(nrhs, self.n_pi + self.n_dl)
+        coef = torch.empty((nrhs, self.N, self.M), dtype=torch.float64, device=dev)
+        mu_pi = torch.zeros((nrhs, self.n_pi), dtype=torch.float64, device=dev) if want_mu else None
+        mu_dl = torch.zeros((nrhs, self.n_dl), dtype=torch.float64, device=dev) if want_mu else None
+        st = L.Stats()
+        with torch.cuda.device(dev):
+            code = self._check(self.lib.ddelm_solve_general(
+                self.ctx, nrhs, f_loc.data_ptr(), _ptr(hh), coef.data_ptr(),
+                _ptr(mu_pi) if self.n_pi else None, _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)),
+                "solve_general")
+        stats = dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
+                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
+        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
+
     def evaluate(self, coef: torch.Tensor, x, grad: bool = False):
         dev = self.device
         x = torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
