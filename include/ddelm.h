@@ -171,6 +171,53 @@ ddelm_status ddelm_solve_general(ddelm_ctx ctx, int nrhs, const double* f_loc, c
 ddelm_status ddelm_evaluate(ddelm_ctx ctx, int nrhs, const double* coef, long long npts,
                             const double* x, double* u, double* grad);
 
+/* Adjoint (transpose) of ddelm_solve, for gradients of a loss of the
+ * coefficients with respect to the data.  The solve is a linear map
+ * (f_I, g_B) -> c; this call applies its transpose to coef_bar, reusing the
+ * stored factors: the transposed recovery, one CG with the same symmetric
+ * operator S_theta of eq. nn-mixed, and the transposed right-hand-side map
+ * (which contains theta P^T P + (1 - theta) I of sec. 3.2 and the
+ * (K~^+)^T recipe of sec. 3).  Not in the paper; derived from its equations.
+ *   coef_bar [nrhs][N][M]      cotangent of coef
+ *   f_I_bar  [nrhs][N][n_int]  output: cotangent of f_I
+ *   g_B_bar  [nrhs][sum_nB]    output, may be NULL: cotangent of g_B
+ *   stats    as in ddelm_solve (iters = CG iterations of the transposed solve)
+ * The CG stops at the relative residual tol, so in float64 the result is
+ * exact up to that tolerance.  In mixed precision the float32 transposed
+ * solve is refined on the float64 transposed residual of the coupled system
+ * (refine_maxit, refine_tol, inner_tol as for the forward solve).  That
+ * removes only the part of the float32 error the transposed residual sees;
+ * the rest, along the difference between the float32 range of Q_i and the
+ * range of K_c^i (of order eps32 * cond(K_c^i)), stays, so the result
+ * carries a float32-level error.  Use precision 0 for gradients to float64
+ * accuracy.
+ * Errors as in ddelm_solve. */
+ddelm_status ddelm_solve_adjoint(ddelm_ctx ctx, int nrhs, const double* coef_bar, double* f_I_bar,
+                                 double* g_B_bar, ddelm_stats* stats);
+
+/* Adjoint of ddelm_solve_general: cotangents of (coef, mu_Pi, mu_Delta) to
+ * those of (f_loc, h).
+ *   coef_bar  [nrhs][N][M]
+ *   mu_pi_bar [nrhs][n_pi]          may be NULL (zero)
+ *   mu_dl_bar [nrhs][n_dl]          may be NULL (zero)
+ *   f_loc_bar [nrhs][sum m]         output, every local row
+ *   h_bar     [nrhs][n_pi + n_dl]   output, may be NULL
+ * Errors as in ddelm_solve. */
+ddelm_status ddelm_solve_adjoint_general(ddelm_ctx ctx, int nrhs, const double* coef_bar,
+                                         const double* mu_pi_bar, const double* mu_dl_bar,
+                                         double* f_loc_bar, double* h_bar, ddelm_stats* stats);
+
+/* Adjoint of ddelm_evaluate: coef_bar[r][i][j] = sum over the points p owned
+ * by subdomain i (the owner rule of ddelm_evaluate) of
+ * u_bar[r][p] phi_j(x_p) + grad_bar[r][p] . grad phi_j(x_p).
+ *   x [npts][2], u_bar [nrhs][npts], grad_bar [nrhs][npts][2] (may be NULL),
+ *   coef_bar [nrhs][N][M] output (overwritten).
+ * The summation order over points is fixed (ascending point index), so the
+ * result is reproducible bit for bit.  Errors: DDELM_E_ARG, DDELM_E_STATE,
+ * DDELM_E_HIP. */
+ddelm_status ddelm_evaluate_adjoint(ddelm_ctx ctx, int nrhs, long long npts, const double* x,
+                                    const double* u_bar, const double* grad_bar, double* coef_bar);
+
 /* Sizes of the problem. */
 ddelm_status ddelm_get_sizes(ddelm_ctx ctx, ddelm_sizes* out);
 

@@ -470,10 +470,17 @@ class DDELMNN:
         cs = self.Kplus(self._add(phi, self.B_Pi(mu_pi), -1.0))
         return cs, mu_pi
 
-    def Kt_plus_T(self, phi):
-        """(K~^+)^T [phi; 0] by the paper's recipe."""
+    def Kt_plus_T(self, phi, psi=None):
+        """(K~^+)^T [phi; psi] (phi over the c blocks, psi over Pi).
+
+        With psi = 0 this is the paper's recipe; a nonzero psi only adds to
+        the right-hand side of the coarse solve, since K~^+ reaches mu_Pi
+        through S_Pi^{-1} alone (transpose of `Kt_plus`)."""
         KpTphi = self.KplusT(phi)
-        nu = self.S_Pi_solve(-self.B_Pi_T(KpTphi))
+        r = -self.B_Pi_T(KpTphi)
+        if psi is not None:
+            r = r + psi
+        nu = self.S_Pi_solve(r)
         Bnu = self.B_Pi(nu)
         KKBnu = self.Kmul(self.Kplus(Bnu))
         top = [KpTphi[i] - KKBnu[i] + Bnu[i] for i in range(self.N)]
@@ -571,6 +578,48 @@ class DDELMNN:
         cs, mu_pi = self.recover(f, d_pi, mu_dl)
         return dict(c=cs, mu_pi=mu_pi, mu_dl=mu_dl, iters=it, relres=relres, b=b)
 
+    # ---------------- adjoint (transpose) of solve, derived from its equations
+    def adjoint(self, cbar, mubar_pi=None, mubar_dl=None, tol=1e-12, maxit=10000, direct=False):
+        """Transpose of the linear map (f, h) -> (c, mu_Pi, mu_Delta) of `solve`.
+
+        The forward map, in the notation of sec. 3:
+          f~ = [f; d_Pi],  d_Pi = h_Pi - A_Pi K^+ f,
+          b  = B~^T (I - K~ K~^+) f~ + D~^T M (h_Delta - A~ K~^+ f~),
+               M = theta P^T P + (1 - theta) I             (eq. nn-mixed)
+          mu_Delta = S_theta^{-1} b,
+          [c; mu_Pi] = K~^+ (f~ - B~ mu_Delta)             (eq. coarse_sol_2).
+        K~ K~^+, S_theta and M are symmetric, so the transpose is
+          g = (K~^+)^T [cbar; mubar_Pi],
+          bbar = S_theta^{-1} (mubar_Delta - B~^T g),
+          fbar~ = g + (I - K~ K~^+) B~ bbar - (K~^+)^T A~^T M D~ bbar,
+          hbar_Delta = M D~ bbar,  hbar_Pi = fbar~ (Pi part),
+          fbar = fbar~ (c part) - (K^+)^T A_Pi^T hbar_Pi.
+        Returns (fbar as a list over subdomains, (hbar_Pi, hbar_Delta), CG iterations).
+        direct=True solves with the assembled S_theta (small problems)."""
+        nP, nD = self.nP, self.nD
+        mP = np.zeros(nP) if mubar_pi is None else np.asarray(mubar_pi, float)
+        mD = np.zeros(nD) if mubar_dl is None else np.asarray(mubar_dl, float)
+        gtop, gbot = self.Kt_plus_T(cbar, mP)
+        rhs = mD - self.Bt_T(gtop, gbot)
+        it = 0
+        if nD == 0:
+            bbar = np.zeros(0)
+        elif direct:
+            S = assemble_S_theta(self)
+            bbar = sla.cho_solve(sla.cho_factor(0.5 * (S + S.T), lower=True), rhs)
+        else:
+            bbar, it, _ = cg(self.S_theta, rhs, tol, maxit)
+        top, bot = self.Bt(bbar)
+        cs, mp = self.Kt_plus(top, bot)
+        ktop, kbot = self.Kt_mul(cs, mp)
+        q = self.Mtheta(self.Dt(bbar))
+        ttop, tbot = self.Kt_plus_T(self.A_Dl_T(q))
+        ft_top = [gtop[i] + top[i] - ktop[i] - ttop[i] for i in range(self.N)]
+        ft_bot = gbot + bot - kbot - tbot
+        corr = self.KplusT(self.A_Pi_T(ft_bot))
+        fbar = [ft_top[i] - corr[i] for i in range(self.N)]
+        return fbar, (ft_bot, q), it
+
 
 def cg(apply, b, tol, maxit, x0=None):
     """Plain conjugate gradients; stops when ||r_k|| <= tol ||b||."""
@@ -632,6 +681,22 @@ def evaluate(geo: Geometry2D, W, b, cs, x, grad=False):
         u[sel] = t @ cs[i]
         g[sel] = np.einsum("nmk,m->nk", gr, cs[i])
     return (u, g) if grad else u
+
+
+def evaluate_adjoint(geo: Geometry2D, W, b, x, ubar, gbar=None):
+    """Transpose of `evaluate` in the coefficients: for each subdomain i,
+    cbar_i = Phi_i(x_own)^T ubar_own (+ the gradient features against gbar)."""
+    x = np.asarray(x, float)
+    own = owner_of(geo, x)
+    out = []
+    for i, sb in enumerate(geo.subs):
+        sel = own == i
+        t, gr, _ = tanh_features(W[i], b[i], sb.half, sb.center, x[sel])
+        cb = t.T @ ubar[sel]
+        if gbar is not None:
+            cb = cb + np.einsum("nmk,nk->m", gr, gbar[sel])
+        out.append(cb)
+    return out
 
 
 def rel_errors(u_ref, u, g_ref=None, g=None):

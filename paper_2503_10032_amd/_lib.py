@@ -65,6 +65,13 @@ SIGNATURES = {
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ddelm_evaluate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ddelm_solve_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.POINTER(Stats)]),
+    "ddelm_solve_adjoint_general": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.POINTER(Stats)]),
+    "ddelm_evaluate_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ddelm_get_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Sizes)]),
     "ddelm_get_counts": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_int_p, c_int_p]),
     "ddelm_get_indexing": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p]),

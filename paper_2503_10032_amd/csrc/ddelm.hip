@@ -19,6 +19,7 @@
 #include "kernels_cg.hpp"
 #include "kernels_qr.hpp"
 #include "kernels_rhs.hpp"
+#include "kernels_adj.hpp"
 
 using namespace ddelm;
 
@@ -186,6 +187,12 @@ struct ddelm_ctx_s {
   // refinement workspaces (mixed precision)
   DBuf<double> F64, R64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
   DBuf<double> fGP0, fGD0, hP0, hD0;   // interface rows and flux rows of a general right-hand side
+  // adjoint workspaces
+  int adj_cap = 0;
+  DBuf<double> adj_yP, adj_yD, adj_zD, adj_mloc, adj_eloc, adj_etaD, adj_lbar;   // slot vectors
+  DBuf<double> adj_gP, adj_u, adj_c2, adj_nu, adj_pbar;                          // coarse / interface
+  DBuf<double> adj_fb, adj_hP, adj_hD;                                           // result (f, h cotangents)
+  DBuf<double> adj_fw, adj_hwP, adj_hwD, adj_zc, adj_zP, adj_zDg, adj_fbGP, adj_fbGD;   // refinement
   DBuf<unsigned> bar;
   DBuf<int> sizes_dev;                 // per subdomain M, n_I, n_B, m, n_G
   Arena arena;
@@ -769,6 +776,29 @@ struct CoreOut {
   double ms_rhs = 0, ms_cg = 0, ms_rec = 0;
 };
 
+// CG on eq. nn-mixed for the right-hand sides in cg_b (solution in cg_x)
+template <typename T>
+void run_cg(ddelm_ctx c, int nrhs, double tol, CoreOut& res) {
+  if (c->nD == 0) return;
+  hipStream_t s = c->stream;
+  const int mode = c->opt.cg_mode == 0 ? (nrhs <= 16 ? 2 : 1) : c->opt.cg_mode;
+  if (mode == 2) cg_persistent<T>(c, nrhs, tol);
+  else cg_multilaunch<T>(c, nrhs, tol);
+  std::vector<double> sc((size_t)nrhs * 8);
+  unsigned fl[8];
+  HIPCHK(hipMemcpyAsync(sc.data(), c->cg_scal.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl[0] & 1u) c->fail(DDELM_E_HIP, "device grid barrier wait expired");
+  for (int r = 0; r < nrhs; ++r) {
+    res.iters = std::max(res.iters, (int)sc[8 * r + 6]);
+    const double rr = sc[8 * r], bb = sc[8 * r + 1];
+    if (!(rr == rr)) c->fail(DDELM_E_NONFINITE, "NaN in CG");
+    res.relres = std::max(res.relres, bb > 0 ? std::sqrt(rr / bb) : 0.0);
+    if (sc[8 * r + 5] == 0.0) res.noconv = true;
+  }
+}
+
 template <typename T>
 CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, const double* hP, const double* hD,
                    double tol, double* coef, int accumulate, double* mu_pi_out, double* mu_dl_out) {
@@ -821,24 +851,7 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   HIPCHK(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
   // ---- CG
-  if (c->nD > 0) {
-    const int mode = c->opt.cg_mode == 0 ? (nrhs <= 16 ? 2 : 1) : c->opt.cg_mode;
-    if (mode == 2) cg_persistent<T>(c, nrhs, tol);
-    else cg_multilaunch<T>(c, nrhs, tol);
-    std::vector<double> sc((size_t)nrhs * 8);
-    unsigned fl[8];
-    HIPCHK(hipMemcpyAsync(sc.data(), c->cg_scal.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (fl[0] & 1u) c->fail(DDELM_E_HIP, "device grid barrier wait expired");
-    for (int r = 0; r < nrhs; ++r) {
-      res.iters = std::max(res.iters, (int)sc[8 * r + 6]);
-      const double rr = sc[8 * r], bb = sc[8 * r + 1];
-      if (!(rr == rr)) c->fail(DDELM_E_NONFINITE, "NaN in CG");
-      res.relres = std::max(res.relres, bb > 0 ? std::sqrt(rr / bb) : 0.0);
-      if (sc[8 * r + 5] == 0.0) res.noconv = true;
-    }
-  }
+  run_cg<T>(c, nrhs, tol, res);
   c->mark(7);
   auto t2 = std::chrono::steady_clock::now();
   // ---- recovery: mu_Pi = pi_f - [S^-1 (rho + D^T psi)](mu_D); c = c_f0 + E mu
@@ -891,6 +904,259 @@ void axpy_norms(ddelm_ctx c, const double* dx, double* x, int n, int nrhs, std::
       dn[r] += h[((size_t)r * nblk + b) * 2];
       xn[r] += h[((size_t)r * nblk + b) * 2 + 1];
     }
+}
+
+// --------------------------------------------------------------- adjoint of the solve
+
+void alloc_adjoint_workspace(ddelm_ctx c, int nrhs) {
+  if (nrhs <= c->adj_cap) return;
+  const size_t D = (size_t)nrhs * std::max(c->sumD, 1), P = (size_t)nrhs * std::max(c->sumP, 1);
+  const size_t nP = (size_t)nrhs * std::max(c->nP, 1), nD = (size_t)nrhs * std::max(c->nD, 1);
+  const size_t C2 = (size_t)nrhs * std::max(2 * c->nP, 1);
+  for (DBuf<double>* b : {&c->adj_yP, &c->adj_mloc, &c->adj_eloc}) b->alloc(P);
+  for (DBuf<double>* b : {&c->adj_yD, &c->adj_zD, &c->adj_etaD, &c->adj_lbar}) b->alloc(D);
+  c->adj_gP.alloc(nP);
+  c->adj_nu.alloc(nP);
+  c->adj_u.alloc(C2);
+  c->adj_c2.alloc(C2);
+  c->adj_pbar.alloc((size_t)nrhs * std::max(c->sumP + c->sumD, 1));
+  c->adj_fb.alloc((size_t)nrhs * c->summ);
+  c->adj_hP.alloc(nP);
+  c->adj_hD.alloc(nD);
+  for (DBuf<double>* b : {&c->adj_yP, &c->adj_yD, &c->adj_zD, &c->adj_mloc, &c->adj_eloc, &c->adj_etaD,
+                          &c->adj_lbar, &c->adj_gP, &c->adj_nu, &c->adj_u, &c->adj_c2, &c->adj_hP, &c->adj_hD})
+    b->zero(c->stream);
+  if (c->mixed) {
+    c->adj_fw.alloc((size_t)nrhs * c->summ);
+    c->adj_hwP.alloc(nP);
+    c->adj_hwD.alloc(nD);
+    c->adj_zc.alloc((size_t)nrhs * c->N * c->M);
+    c->adj_zP.alloc(nP);
+    c->adj_zDg.alloc(nD);
+    c->adj_fbGP.alloc(P);
+    c->adj_fbGD.alloc(D);
+    for (DBuf<double>* b : {&c->adj_hwP, &c->adj_hwD, &c->adj_zP, &c->adj_zDg, &c->adj_fbGP, &c->adj_fbGD})
+      b->zero(c->stream);
+  }
+  c->adj_cap = nrhs;
+}
+
+// One transposed DDELM-NN solve with the factors of type T: from the
+// cotangents (cbar [nrhs][N][M], mubP [nrhs][nP], mubD [nrhs][nD]; the last
+// two may be null) of (c, mu_Pi, mu_Delta) to those of the local right-hand
+// side (fbar [nrhs][sum m], all rows) and of the flux rows (hbP, hbD).
+// fbGP / fbGD (optional) receive the interface rows of fbar in slot order.
+template <typename T>
+CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mubP, const double* mubD, double tol,
+                     double* fbar, double* hbP, double* hbD, double* fbGP, double* fbGD) {
+  CoreOut res;
+  hipStream_t s = c->stream;
+  const int N = c->N, M = c->M, nP = c->nP, nD = c->nD;
+  const int sumG = c->sumP + c->sumD;
+  LocalBufs<T>& L = c->lb<T>();
+  OpArgs<T> a = op_args<T>(c, nrhs);
+  const size_t sm = local_smem(c);
+  const size_t smG = sizeof(double) * (size_t)std::max(c->geo.max_nG, 1);
+  const dim3 gl(N, nrhs);
+  const dim3 gP(ceil_div(std::max(nP, 1), kBlock), nrhs), gP2(ceil_div(std::max(2 * nP, 1), kBlock), nrhs);
+  const dim3 gD(ceil_div(std::max(nD, 1), kBlock), nrhs);
+  auto t0 = std::chrono::steady_clock::now();
+  c->mark(5);
+  // ---- transpose of the recovery c = cf0 + E mu, mu_Pi = mu1 - (X1 u')[:nP]
+  k_adj_Et<T><<<gl, kBlock, (size_t)M * sizeof(double), s>>>(M, N, c->pi_off.p, c->dl_off.p, c->qrdesc.p, L.qrA.p,
+                                                              cbar, c->sumP, c->sumD, c->adj_yP.p, c->adj_yD.p);
+  HIPCHK(hipGetLastError());
+  if (nP > 0) {
+    k_owner_sum<<<gP, kBlock, 0, s>>>(nP, c->pi_own_ptr.p, c->pi_own_slot.p, c->adj_yP.p, c->sumP, mubP, c->adj_gP.p,
+                                      nP, 0);
+    k_x1t<<<gP2, kBlock, 0, s>>>(c->X1.p, 2 * nP, 0, nP, c->adj_gP.p, nP, 2 * nP, -1.0, c->adj_u.p, 2 * nP);
+    HIPCHK(hipGetLastError());
+  }
+  if (nD > 0) {
+    k_adj_rec<T><<<gl, kBlock, 0, s>>>(a, c->adj_yD.p, c->adj_u.p, c->adj_zD.p);
+    k_owner_sum<<<gD, kBlock, 0, s>>>(nD, c->dl_own_ptr.p, c->dl_own_slot.p, c->adj_zD.p, c->sumD, mubD, c->cg_b.p,
+                                      nD, 0);
+    HIPCHK(hipGetLastError());
+  }
+  c->mark(6);
+  HIPCHK(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  // ---- the transposed interface system: S_theta is symmetric, so the same CG
+  run_cg<T>(c, nrhs, tol, res);
+  c->mark(7);
+  auto t2 = std::chrono::steady_clock::now();
+  // ---- transpose of the right-hand-side map
+  k_adj_A1<T><<<gl, kBlock, sm, s>>>(a, c->cg_x.p, c->adj_mloc.p, c->adj_eloc.p, c->adj_etaD.p);
+  HIPCHK(hipGetLastError());
+  if (nP > 0) {
+    k_owner_sum<<<gP, kBlock, 0, s>>>(nP, c->pi_own_ptr.p, c->pi_own_slot.p, c->adj_mloc.p, c->sumP, nullptr,
+                                      c->adj_c2.p, 2 * nP, 0);
+    k_owner_sum<<<gP, kBlock, 0, s>>>(nP, c->pi_own_ptr.p, c->pi_own_slot.p, c->adj_eloc.p, c->sumP, nullptr,
+                                      c->adj_c2.p, 2 * nP, nP);
+    k_x1t<<<gP, kBlock, 0, s>>>(c->X1.p, 2 * nP, 0, 2 * nP, c->adj_c2.p, 2 * nP, nP, 1.0, c->adj_nu.p, nP);
+    HIPCHK(hipGetLastError());
+  }
+  if (nD > 0) {
+    k_adj_A2<T><<<gl, kBlock, 0, s>>>(a, c->adj_etaD.p, c->adj_nu.p);
+    if (a.theta != 0.0) {
+      k_ph_P1<T><<<gl, kBlock, sm, s>>>(a);
+      k_ph_P2<T><<<gl, kBlock, sm, s>>>(a);
+    }
+    k_adj_A3<T><<<gl, kBlock, sm, s>>>(a, c->adj_lbar.p, c->adj_mloc.p);
+    k_adj_hD<T><<<gD, kBlock, 0, s>>>(a, hbD);
+    HIPCHK(hipGetLastError());
+  }
+  if (nP > 0) {
+    // [mu1_bar; e1_bar] (e1_bar is already in the second half), then u = X1^T [mu1_bar; e1_bar]
+    k_owner_sum<<<gP, kBlock, 0, s>>>(nP, c->pi_own_ptr.p, c->pi_own_slot.p, c->adj_mloc.p, c->sumP, c->adj_gP.p,
+                                      c->adj_c2.p, 2 * nP, 0);
+    k_x1t<<<gP2, kBlock, 0, s>>>(c->X1.p, 2 * nP, 0, 2 * nP, c->adj_c2.p, 2 * nP, 2 * nP, 1.0, c->adj_u.p, 2 * nP);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy2DAsync(hbP, nP * sizeof(double), c->adj_u.p + nP, 2 * nP * sizeof(double), nP * sizeof(double),
+                            nrhs, hipMemcpyDeviceToDevice, s));
+  }
+  // ---- local stage: f_bar_i = Q [R^{-T} cf0_bar + Q_G^T pbar; 0] - pbar on the interface rows
+  if (c->mixed)
+    k_adj_F<T, double><<<gl, kBlock, smG, s>>>(M, N, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p,
+                                               c->dl_l2g.p, c->offAm_d.p, c->A64.p, cbar, c->adj_u.p, c->adj_lbar.p,
+                                               c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
+  else
+    k_adj_F<T, T><<<gl, kBlock, smG, s>>>(M, N, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p,
+                                          c->dl_l2g.p, c->offAm_d.p, L.Am.p, cbar, c->adj_u.p, c->adj_lbar.p,
+                                          c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
+  HIPCHK(hipGetLastError());
+  const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
+  k_trsm<T><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, (size_t)M * kTRSMC * sizeof(T), s>>>(
+      c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p, cnM, 1);
+  k_adj_alpha<T><<<gl, kBlock, smG, s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offQG_d.p, L.QG.p,
+                                         c->adj_pbar.p, sumG, c->offm_d.p, c->summ, L.F.p);
+  HIPCHK(hipGetLastError());
+  for (int p = c->npanel - 1; p >= 0; --p) {
+    k_qr_wy<T><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, p * kNB, p, c->npanel,
+                                                               L.F.p, c->f_off.p, c->f_ld.p, cnM, 0, 0);
+    HIPCHK(hipGetLastError());
+  }
+  k_adj_fout<T><<<gl, kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p, c->summ, L.F.p,
+                                      c->adj_pbar.p, sumG, c->sumP, c->sumD, fbar, fbGP, fbGD);
+  HIPCHK(hipGetLastError());
+  c->mark(8);
+  HIPCHK(hipStreamSynchronize(s));
+  auto t3 = std::chrono::steady_clock::now();
+  c->phase_ms[4] += c->span(5, 6) + c->span(7, 8);
+  c->phase_ms[5] += c->span(6, 7);
+  res.ms_rhs = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  res.ms_cg = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  res.ms_rec = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  return res;
+}
+
+// Shared body of ddelm_solve_adjoint and ddelm_solve_adjoint_general.
+ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double* mubP, const double* mubD,
+                         double* f_I_bar, double* g_B_bar, double* f_loc_bar, double* h_bar, ddelm_stats* stats) {
+  if (!c) return DDELM_E_ARG;
+  bool noconv = false;
+  ddelm_stats st{};
+  ddelm_status code = run_guarded(c, [&]() {
+    if (!c->factored) c->fail(DDELM_E_STATE, "adjoint solve called before ddelm_factor");
+    if (nrhs < 1 || nrhs > c->opt.max_nrhs) c->fail(DDELM_E_ARG, "nrhs out of range");
+    if (!cbar) c->fail(DDELM_E_ARG, "coef_bar is null");
+    hipStream_t s = c->stream;
+    const int N = c->N, nP = c->nP, nD = c->nD;
+    alloc_solve_workspace(c, nrhs);
+    alloc_adjoint_workspace(c, nrhs);
+    HIPCHK(hipStreamSynchronize(s));
+    c->arena.reset();
+    c->phase_ms[4] = c->phase_ms[5] = c->phase_ms[6] = 0.0;
+    auto acc = [&](const CoreOut& o) {
+      st.iters += o.iters;
+      st.rel_res = o.relres;
+      st.ms_rhs += o.ms_rhs;
+      st.ms_cg += o.ms_cg;
+      st.ms_recover += o.ms_rec;
+      noconv = noconv || o.noconv;
+    };
+    if (!c->mixed) {
+      acc(adjoint_core<double>(c, nrhs, cbar, mubP, mubD, c->opt.tol, c->adj_fb.p, c->adj_hP.p, c->adj_hD.p, nullptr,
+                               nullptr));
+    } else {
+      // float32 transposed solves, refined on the float64 transposed residual:
+      // z = (cbar, mubar) - Op^T y, y += adjoint(z).  This removes the part of
+      // the float32 error that the transposed residual sees and stalls after
+      // one or two steps: the rest lies along the difference between the
+      // float32 range of Q_i and the range of K_c^i, which Op^T does not see.
+      const long long nc = (long long)nrhs * N * c->M;
+      HIPCHK(hipMemcpyAsync(c->adj_zc.p, cbar, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (nP) {
+        if (mubP)
+          HIPCHK(hipMemcpyAsync(c->adj_zP.p, mubP, (size_t)nrhs * nP * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else
+          fill(s, c->adj_zP.p, (long long)nrhs * nP, 0.0);
+      }
+      if (nD) {
+        if (mubD)
+          HIPCHK(hipMemcpyAsync(c->adj_zDg.p, mubD, (size_t)nrhs * nD * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else
+          fill(s, c->adj_zDg.p, (long long)nrhs * nD, 0.0);
+      }
+      fill(s, c->adj_fb.p, (long long)nrhs * c->summ, 0.0);
+      if (nP) fill(s, c->adj_hP.p, (long long)nrhs * nP, 0.0);
+      if (nD) fill(s, c->adj_hD.p, (long long)nrhs * nD, 0.0);
+      size_t shm = 0;
+      for (int i = 0; i < N; ++i) shm = std::max(shm, (size_t)(c->h_m[i] + c->h_nG[i]));
+      shm *= sizeof(double);
+      for (int step = 0; step <= c->opt.refine_maxit; ++step) {
+        acc(adjoint_core<float>(c, nrhs, c->adj_zc.p, nP ? c->adj_zP.p : nullptr, nD ? c->adj_zDg.p : nullptr,
+                                c->opt.inner_tol, c->adj_fw.p, c->adj_hwP.p, c->adj_hwD.p, c->adj_fbGP.p,
+                                c->adj_fbGD.p));
+        if (step > 0) st.refine_steps += 1;
+        std::vector<double> dn, xn, dpn, xpn, ddn, xdn;
+        axpy_norms(c, c->adj_fw.p, c->adj_fb.p, (int)c->summ, nrhs, dn, xn);
+        axpy_norms(c, c->adj_hwP.p, c->adj_hP.p, nP, nrhs, dpn, xpn);
+        axpy_norms(c, c->adj_hwD.p, c->adj_hD.p, nD, nrhs, ddn, xdn);
+        double worst = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+          const double num = dn[r] + (nP ? dpn[r] : 0.0) + (nD ? ddn[r] : 0.0);
+          const double den = xn[r] + (nP ? xpn[r] : 0.0) + (nD ? xdn[r] : 0.0);
+          worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
+        }
+        if ((step > 0 && worst <= c->opt.refine_tol) || step == c->opt.refine_maxit) break;
+        k_adj_resid<<<dim3(N, nrhs), kBlock, shm, s>>>(
+            c->M, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p, c->K64.p,
+            c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, c->adj_fw.p, nP ? c->adj_hwP.p : nullptr,
+            nD ? c->adj_hwD.p : nullptr, N, c->adj_zc.p);
+        HIPCHK(hipGetLastError());
+        if (nP)
+          k_owner_sum<<<dim3(ceil_div(nP, kBlock), nrhs), kBlock, 0, s>>>(
+              nP, c->pi_own_ptr.p, c->pi_own_slot.p, c->adj_fbGP.p, c->sumP, c->adj_zP.p, c->adj_zP.p, nP, 0);
+        if (nD)
+          k_owner_sum<<<dim3(ceil_div(nD, kBlock), nrhs), kBlock, 0, s>>>(
+              nD, c->dl_own_ptr.p, c->dl_own_slot.p, c->adj_fbGD.p, c->sumD, c->adj_zDg.p, c->adj_zDg.p, nD, 0);
+        HIPCHK(hipGetLastError());
+      }
+    }
+    // ---- outputs
+    if (f_loc_bar)
+      HIPCHK(hipMemcpyAsync(f_loc_bar, c->adj_fb.p, (size_t)nrhs * c->summ * sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    if (h_bar) {
+      const int nG = nP + nD;
+      if (nP)
+        HIPCHK(hipMemcpy2DAsync(h_bar, nG * sizeof(double), c->adj_hP.p, nP * sizeof(double), nP * sizeof(double),
+                                nrhs, hipMemcpyDeviceToDevice, s));
+      if (nD)
+        HIPCHK(hipMemcpy2DAsync(h_bar + nP, nG * sizeof(double), c->adj_hD.p, nD * sizeof(double),
+                                nD * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+    }
+    if (f_I_bar) {
+      k_adj_out<<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p, c->offB_d.p, c->summ,
+                                                 c->geo.sum_nB, c->adj_fb.p, f_I_bar, g_B_bar);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  });
+  if (stats) *stats = st;
+  if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
+  return code;
 }
 
 }  // namespace
@@ -1174,6 +1440,39 @@ ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long
                                                                   g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, r);
       HIPCHK(hipGetLastError());
     }
+  });
+}
+
+ddelm_status ddelm_solve_adjoint(ddelm_ctx c, int nrhs, const double* coef_bar, double* f_I_bar, double* g_B_bar,
+                                 ddelm_stats* stats) {
+  if (!f_I_bar) {
+    if (c) c->err = "f_I_bar is null";
+    return DDELM_E_ARG;
+  }
+  return adjoint_any(c, nrhs, coef_bar, nullptr, nullptr, f_I_bar, g_B_bar, nullptr, nullptr, stats);
+}
+
+ddelm_status ddelm_solve_adjoint_general(ddelm_ctx c, int nrhs, const double* coef_bar, const double* mu_pi_bar,
+                                         const double* mu_dl_bar, double* f_loc_bar, double* h_bar,
+                                         ddelm_stats* stats) {
+  if (!f_loc_bar) {
+    if (c) c->err = "f_loc_bar is null";
+    return DDELM_E_ARG;
+  }
+  return adjoint_any(c, nrhs, coef_bar, mu_pi_bar, mu_dl_bar, nullptr, nullptr, f_loc_bar, h_bar, stats);
+}
+
+ddelm_status ddelm_evaluate_adjoint(ddelm_ctx c, int nrhs, long long npts, const double* x, const double* u_bar,
+                                    const double* grad_bar, double* coef_bar) {
+  if (!c) return DDELM_E_ARG;
+  return run_guarded(c, [&]() {
+    if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
+    if (nrhs < 1 || nrhs > 65535 || npts < 0 || !coef_bar || (npts > 0 && (!x || !u_bar)))
+      c->fail(DDELM_E_ARG, "bad evaluate_adjoint arguments");
+    const Geometry& g = c->geo;
+    k_eval_adj<<<dim3(c->N, ceil_div(c->M, kBlock), nrhs), kBlock, 0, c->stream>>>(
+        g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p, npts, x, u_bar, grad_bar, coef_bar);
+    HIPCHK(hipGetLastError());
   });
 }
 

@@ -216,3 +216,72 @@ class DDELMSolver:
             self._check(self.lib.ddelm_evaluate(self.ctx, nrhs, coef.data_ptr(), npts, x.data_ptr(), u.data_ptr(),
                                                 _ptr(g)), "evaluate")
         return (u, g) if grad else u
+
+    # ------------------------------------------------------------ adjoints
+    def _stats(self, st, code):
+        return dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
+                    ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
+
+    def solve_adjoint(self, coef_bar):
+        """Transpose of solve: coef_bar (nrhs, N, M) -> dict(f_I_bar (nrhs, N, n_int),
+        g_B_bar (nrhs, sum_nB), stats)."""
+        dev = self.device
+        cb = torch.as_tensor(coef_bar, dtype=torch.float64, device=dev).contiguous()
+        if cb.ndim == 2:
+            cb = cb[None]
+        nrhs = cb.shape[0]
+        assert cb.shape == (nrhs, self.N, self.M), cb.shape
+        fI = torch.empty((nrhs, self.N, self.sizes.n_int), dtype=torch.float64, device=dev)
+        gB = torch.empty((nrhs, max(self.sizes.sum_nB, 1)), dtype=torch.float64, device=dev)
+        st = L.Stats()
+        with torch.cuda.device(dev):
+            code = self._check(self.lib.ddelm_solve_adjoint(self.ctx, nrhs, cb.data_ptr(), fI.data_ptr(),
+                                                            gB.data_ptr() if self.sizes.sum_nB else None,
+                                                            ctypes.byref(st)), "solve_adjoint")
+        return dict(f_I_bar=fI, g_B_bar=gB[:, : self.sizes.sum_nB], stats=self._stats(st, code))
+
+    def solve_adjoint_general(self, coef_bar, mu_pi_bar=None, mu_dl_bar=None):
+        """Transpose of solve_general: cotangents of (coef, mu_pi, mu_dl) ->
+        dict(f_loc_bar (nrhs, sum m), h_bar (nrhs, n_pi + n_dl), stats)."""
+        dev = self.device
+        cb = torch.as_tensor(coef_bar, dtype=torch.float64, device=dev).contiguous()
+        if cb.ndim == 2:
+            cb = cb[None]
+        nrhs = cb.shape[0]
+        assert cb.shape == (nrhs, self.N, self.M), cb.shape
+
+        def opt(t, n):
+            if t is None or n == 0:
+                return None
+            t = torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous().reshape(nrhs, n)
+            return t
+
+        mp, md = opt(mu_pi_bar, self.n_pi), opt(mu_dl_bar, self.n_dl)
+        summ = int(self.counts()["m"].sum())
+        fb = torch.empty((nrhs, summ), dtype=torch.float64, device=dev)
+        hb = torch.zeros((nrhs, max(self.n_pi + self.n_dl, 1)), dtype=torch.float64, device=dev)
+        st = L.Stats()
+        with torch.cuda.device(dev):
+            code = self._check(self.lib.ddelm_solve_adjoint_general(
+                self.ctx, nrhs, cb.data_ptr(), _ptr(mp), _ptr(md), fb.data_ptr(),
+                hb.data_ptr() if self.n_pi + self.n_dl else None, ctypes.byref(st)), "solve_adjoint_general")
+        return dict(f_loc_bar=fb, h_bar=hb[:, : self.n_pi + self.n_dl], stats=self._stats(st, code))
+
+    def evaluate_adjoint(self, x, u_bar, grad_bar=None):
+        """Transpose of evaluate in the coefficients: u_bar (nrhs, npts) and
+        optionally grad_bar (nrhs, npts, 2) -> coef_bar (nrhs, N, M)."""
+        dev = self.device
+        x = torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
+        ub = torch.as_tensor(u_bar, dtype=torch.float64, device=dev).contiguous()
+        if ub.ndim == 1:
+            ub = ub[None]
+        nrhs, npts = ub.shape
+        assert x.shape == (npts, 2), x.shape
+        gb = None
+        if grad_bar is not None:
+            gb = torch.as_tensor(grad_bar, dtype=torch.float64, device=dev).contiguous().reshape(nrhs, npts, 2)
+        cb = torch.empty((nrhs, self.N, self.M), dtype=torch.float64, device=dev)
+        with torch.cuda.device(dev):
+            self._check(self.lib.ddelm_evaluate_adjoint(self.ctx, nrhs, npts, x.data_ptr(), ub.data_ptr(), _ptr(gb),
+                                                        cb.data_ptr()), "evaluate_adjoint")
+        return cb

@@ -1,0 +1,175 @@
+"""Pins of the oracle's adjoint (transpose) of the DDELM-NN solve and of the
+evaluation.  The adjoint is not in the paper; it is derived from the
+forward equations, so it is checked against things that do not share that
+derivation: the Jacobian of the dense definition (pinv + one stacked lstsq)
+built column by column, the transpose identity <J z, y> = <z, J^T y>
+against the forward solve, the single-subdomain case (pinv(K)^T), and the
+gradient of a least-squares loss in the 64 + 32 data coefficients against
+one forward solve per coefficient.
+"""
+import numpy as np
+import pytest
+
+from oracle import ddelm_oracle as O
+from paper_2503_10032_amd import inputs as I
+
+
+def tiny(nx, ny, M, n_int, p, coarse=2, seed=3, a=1.5):
+    w = I.Workload("tiny", nx, ny, M, a, seed, n_int, p)
+    W, b = I.hidden_params(w.N, M, 2, a, seed)
+    geo = O.Geometry2D(nx, ny, I.edge_params(p), I.extra_boundary_params(w), I.interior_points(w), coarse=coarse)
+    return w, W, b, geo
+
+
+def _flat_out(s, r):
+    return np.concatenate(list(r["c"]) + [r["mu_pi"], r["mu_dl"]])
+
+
+def _split_f(s, z):
+    ms = [sb.m for sb in s.geo.subs]
+    off = np.concatenate([[0], np.cumsum(ms)])
+    f = [z[off[i]:off[i + 1]] for i in range(s.N)]
+    hP = z[off[-1]:off[-1] + s.nP]
+    hD = z[off[-1] + s.nP:]
+    return f, (hP, hD)
+
+
+def _split_y(s, y):
+    Ms = [s.K[i].shape[1] for i in range(s.N)]
+    off = np.concatenate([[0], np.cumsum(Ms)])
+    cbar = [y[off[i]:off[i + 1]] for i in range(s.N)]
+    return cbar, y[off[-1]:off[-1] + s.nP], y[off[-1] + s.nP:]
+
+
+def _adjoint_flat(s, y, **kw):
+    cbar, mP, mD = _split_y(s, y)
+    fbar, (hP, hD), _ = s.adjoint(cbar, mP, mD, **kw)
+    return np.concatenate(list(fbar) + [hP, hD])
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2)])
+@pytest.mark.parametrize("coarse,theta", [(1, 0.0), (2, 0.0), (2, 0.999), (2, 1.0)])
+def test_adjoint_is_transpose_of_dense_jacobian(nx, ny, coarse, theta):
+    """J from the dense definition of the result, one column per input."""
+    w, W, b, geo = tiny(nx, ny, 12, 2, 4, coarse=coarse)
+    s = O.DDELMNN(geo, W, b, theta=theta)
+    nin = sum(sb.m for sb in geo.subs) + s.nP + s.nD
+    cols = []
+    for k in range(nin):
+        z = np.zeros(nin)
+        z[k] = 1.0
+        f, h = _split_f(s, z)
+        d = O.dense_reference_solve(s, f, h=h)
+        cols.append(np.concatenate(list(d["c"]) + [d["mu_pi"], d["mu_dl"]]))
+    J = np.stack(cols, axis=1)
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        y = rng.standard_normal(J.shape[0])
+        ref = J.T @ y
+        got = _adjoint_flat(s, y, direct=True)
+        np.testing.assert_allclose(got, ref, atol=1e-8 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("coarse,theta", [(0, 0.0), (1, 0.999), (2, 0.5), (2, 0.999)])
+def test_adjoint_transpose_identity_against_forward_solve(coarse, theta):
+    w, W, b, geo = tiny(3, 3, 14, 3, 5, coarse=coarse)
+    s = O.DDELMNN(geo, W, b, theta=theta)
+    rng = np.random.default_rng(5)
+    nin = sum(sb.m for sb in geo.subs) + s.nP + s.nD
+    nout = sum(s.K[i].shape[1] for i in range(s.N)) + s.nP + s.nD
+    for _ in range(2):
+        z = rng.standard_normal(nin)
+        y = rng.standard_normal(nout)
+        f, h = _split_f(s, z)
+        Jz = _flat_out(s, s.solve_direct(f, h=h))
+        JTy = _adjoint_flat(s, y, direct=True)
+        lhs, rhs = Jz @ y, z @ JTy
+        scale = np.linalg.norm(Jz) * np.linalg.norm(y) + np.linalg.norm(z) * np.linalg.norm(JTy)
+        assert abs(lhs - rhs) <= 1e-10 * scale, (lhs, rhs)
+
+
+def test_adjoint_with_cg_matches_direct():
+    w, W, b, geo = tiny(3, 3, 14, 3, 5)
+    s = O.DDELMNN(geo, W, b, theta=0.999)
+    rng = np.random.default_rng(2)
+    cbar = [rng.standard_normal(s.K[i].shape[1]) for i in range(s.N)]
+    f1, h1, it = s.adjoint(cbar, tol=1e-14, maxit=5000)
+    f2, h2, _ = s.adjoint(cbar, direct=True)
+    assert it > 0
+    scale = max(np.abs(np.concatenate(f2)).max(), 1.0)
+    np.testing.assert_allclose(np.concatenate(f1), np.concatenate(f2), atol=1e-9 * scale)
+    np.testing.assert_allclose(h1[1], h2[1], atol=1e-9 * scale)
+
+
+def test_adjoint_of_single_subdomain_is_pinv_transpose():
+    w, W, b, geo = tiny(1, 1, 30, 6, 7)
+    s = O.DDELMNN(geo, W, b, theta=0.999)
+    rng = np.random.default_rng(4)
+    cbar = [rng.standard_normal(30)]
+    fbar, (hP, hD), _ = s.adjoint(cbar)
+    assert hP.size == 0 and hD.size == 0
+    ref = np.linalg.pinv(s.K[0]).T @ cbar[0]
+    np.testing.assert_allclose(fbar[0], ref, atol=1e-10 * np.abs(ref).max())
+
+
+def test_evaluate_adjoint_transpose_identity():
+    w, W, b, geo = tiny(3, 2, 16, 3, 5)
+    rng = np.random.default_rng(9)
+    cs = [rng.standard_normal(16) for _ in range(geo.nx * geo.ny)]
+    x = np.concatenate([I.observation_points(500, seed=1), I.eval_grid(w)])   # includes shared edges
+    ub = rng.standard_normal(len(x))
+    gb = rng.standard_normal((len(x), 2))
+    u, g = O.evaluate(geo, W, b, cs, x, grad=True)
+    cb = O.evaluate_adjoint(geo, W, b, x, ub, gb)
+    lhs = u @ ub + np.sum(g * gb)
+    rhs = sum(c @ d for c, d in zip(cs, cb))
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(u * ub).sum() + np.abs(g * gb).sum())
+
+
+def test_gradient_in_data_coefficients_matches_one_solve_per_coefficient():
+    """L = 1/(2 n) sum (u(x_k) - u_obs_k)^2 with f = f_basis theta and
+    g = g_basis eta (64 + 32 coefficients): the adjoint gradient equals the
+    gradient assembled from the 96 forward solutions (the map is linear)."""
+    w, W, b, geo = tiny(2, 2, 20, 3, 5)
+    s = O.DDELMNN(geo, W, b, theta=0.999)
+    ap = I.adjoint_params(seed=5)
+    xo = I.observation_points(300, seed=6)
+    u_obs = np.sin(np.pi * xo[:, 0]) * np.cos(np.pi * xo[:, 1])
+    PhiI = [I.AdjointParams.f_basis(sb.x_I) for sb in geo.subs]
+    PhiB = [I.AdjointParams.g_basis(sb.x_B) for sb in geo.subs]
+
+    def coef(th, et):
+        f = O.local_rhs_from_values(geo, [P @ th for P in PhiI], [P @ et for P in PhiB])
+        return s.solve_direct(f)["c"]
+
+    c0 = coef(ap.theta, ap.eta)
+    u = O.evaluate(geo, W, b, c0, xo)
+    n = len(xo)
+    # forward-mode reference: dL/dq_k = <dc/dq_k, E^T (E c - u_obs)> / n
+    cbar = O.evaluate_adjoint(geo, W, b, xo, (u - u_obs) / n)
+    ref = np.zeros(96)
+    for k in range(96):
+        th = np.zeros(64)
+        et = np.zeros(32)
+        if k < 64:
+            th[k] = 1.0
+        else:
+            et[k - 64] = 1.0
+        ck = coef(th, et)
+        ref[k] = sum(a @ c for a, c in zip(ck, cbar))
+    # adjoint
+    fbar, _, _ = s.adjoint(cbar, direct=True)
+    g_th = sum(PhiI[i].T @ fbar[i][:sb.n_I] for i, sb in enumerate(geo.subs))
+    g_et = sum(PhiB[i].T @ fbar[i][sb.n_I:sb.n_I + sb.n_B] for i, sb in enumerate(geo.subs))
+    got = np.concatenate([g_th, g_et])
+    np.testing.assert_allclose(got, ref, atol=1e-9 * np.abs(ref).max())
+    # and central finite differences of L along a few directions (exact for a quadratic)
+    def loss(th, et):
+        return 0.5 * np.mean((O.evaluate(geo, W, b, coef(th, et), xo) - u_obs) ** 2)
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        d = rng.standard_normal(96)
+        eps = 1e-3
+        fd = (loss(ap.theta + eps * d[:64], ap.eta + eps * d[64:]) -
+              loss(ap.theta - eps * d[:64], ap.eta - eps * d[64:])) / (2 * eps)
+        assert abs(fd - got @ d) <= 1e-6 * (abs(fd) + 1e-12)
