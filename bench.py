@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium")
     ap.add_argument("--cg-mode", type=int, default=0)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
@@ -98,9 +99,13 @@ def main():
     X = torch.as_tensor(I.eval_grid(w), device=dev)
     f_fn, g_fn = I.rhs_functions(w)
     fI = torch.as_tensor(f_fn(xi), device=dev)
+    prec = 1 if args.precision == "mixed" else 0
     probe = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=w.theta, tol=1e-8,
-                        max_nrhs=w.nrhs, cg_mode=args.cg_mode)
+                        max_nrhs=w.nrhs, cg_mode=args.cg_mode, precision=prec)
     gB = torch.as_tensor(g_fn(probe.boundary_points().cpu().numpy()), device=dev)
+    if not args.quiet:
+        print(f"bench: workload {w.name} ({w.nx}x{w.ny}, M={w.M}, nrhs={w.nrhs}) precision {args.precision}",
+              file=sys.stderr, flush=True)
     counts = probe.counts()
     n_pi = probe.n_pi
     probe.close()
@@ -108,7 +113,7 @@ def main():
     def step():
         t0 = time.perf_counter()
         s = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=w.theta, tol=1e-8,
-                        max_nrhs=w.nrhs, cg_mode=args.cg_mode)
+                        max_nrhs=w.nrhs, cg_mode=args.cg_mode, precision=prec)
         t1 = time.perf_counter()
         s.factor()
         t2 = time.perf_counter()

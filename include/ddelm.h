@@ -101,7 +101,8 @@ typedef struct {
                                cooperative launch per CG solve */
   int refine_maxit;         /* mixed precision: outer refinement steps cap (>= 1) */
   double refine_tol;        /* mixed precision: stop when the correction of mu is
-                               <= refine_tol relative to mu */
+                               <= refine_tol relative to mu, or when a step shrinks
+                               the correction by less than a factor 2 (stall) */
   double inner_tol;         /* mixed precision: CG tolerance of each inner solve */
 } ddelm_options;
 
@@ -124,7 +125,7 @@ typedef struct {
 
 /* Default options: theta 0.999 (sec. 4.2), coarse 2, fp64, tol 1e-8,
  * maxit 20000, max_nrhs 1, cg_mode auto, refine_maxit 10, refine_tol 1e-9,
- * inner_tol 1e-6. */
+ * inner_tol 1e-3. */
 void ddelm_default_options(ddelm_options* opt);
 
 /* Validate, build the interface indexing on the host and allocate the

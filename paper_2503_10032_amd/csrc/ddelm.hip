@@ -112,6 +112,11 @@ struct Arena {
 
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Mixed-precision refinement stops once a step shrinks the correction by less
+// than this factor: the iteration then sits near its float32 fixed point and
+// further steps cost a full inner solve each for little change.
+constexpr double kRefineStall = 0.5;
+
 struct RowSetDev {
   DBuf<int> row0, ptr;
   DBuf<Term> terms;
@@ -172,7 +177,7 @@ struct ddelm_ctx_s {
   DBuf<double> K64, A64, CD64;
   DBuf<long long> offK_d;
   // coarse (always float64)
-  DBuf<double> Spi, Sfac, Sinv, Dpp, Gs, Zm, Ztm, Wm, X1;
+  DBuf<double> Spi, Sfac, Sinv, Dpp, Gs, Zm, Ztm, Wm, X1, X1t;
   DBuf<unsigned> flags;                // [0] barrier expired (1) / Cholesky (2)
   // indexing on device
   DBuf<int> pi_off, dl_off, pi_l2g, dl_l2g, pi_own_ptr, pi_own_slot, dl_own_ptr, dl_own_slot, pi_slot_sub;
@@ -183,6 +188,7 @@ struct ddelm_ctx_s {
   DBuf<int> f_ld, f_cn;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
+  DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
   int cg_blocks = 0, cg_slices = 0;
   // refinement workspaces (mixed precision)
   DBuf<double> F64, R64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
@@ -358,6 +364,8 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   const size_t C = (size_t)nrhs * std::max(2 * c->nP, 1);
   c->c1.alloc(C);
   c->c2.alloc(C);
+  c->cg_u.alloc(C);
+  c->cg_c.alloc(C);
   c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
   const size_t V = (size_t)nrhs * std::max(c->nD, 1);
   for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b}) b->alloc(V);
@@ -491,6 +499,14 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.lds_ys = xs;
   f.lds_part = xs + ys;
   f.lds_cu = xs + ys + part;
+  f.lds_total = xs + ys + part + cu;
+  // distributed coarse phases when every unit gathering the whole coarse
+  // right-hand side would cost more than the two extra synchronisations
+  f.dist = (long long)c->nP * nrhs > 512 ? 1 : 0;
+  if (const char* env = getenv("DDELM_CG_COARSE")) f.dist = atoi(env) != 0 ? 1 : 0;
+  f.X1t = c->X1t.p;
+  f.ug = c->cg_u.p;
+  f.cg1 = c->cg_c.p;
   const size_t smem = sizeof(double) * (size_t)(xs + ys + part + cu);
   if (smem > 160 * 1024) c->fail(DDELM_E_SHAPE, "CG workspace exceeds the LDS of one compute unit");
   const void* fn = (const void*)k_cg_fused<T, NR>;
@@ -736,8 +752,24 @@ void factor_impl(ddelm_ctx c) {
     gemm_batch<double>(c, {GemmDesc{0, 0, 0, n, n, n, n, n, n}}, c->Dpp.p, c->Dpp.p, c->Spi.p, 1, 1.0, 1.0);
     HIPCHK(hipMemcpyAsync(c->Sfac.p, c->Spi.p, nn2 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(c->flags.p, 0, 8 * sizeof(unsigned), s));
-    k_cholesky<<<1, kBlock, 0, s>>>(c->Sfac.p, n, c->flags.p);
-    HIPCHK(hipGetLastError());
+    {
+      DBuf<double> lt;   // L21^T of the current block column
+      lt.alloc((size_t)kCB * n);
+      for (int k0 = 0; k0 < n; k0 += kCB) {
+        const int nbk = std::min(kCB, n - k0), m = n - k0 - nbk;
+        k_chol_diag<<<1, kBlock, 0, s>>>(c->Sfac.p, n, k0, nbk, c->flags.p);
+        HIPCHK(hipGetLastError());
+        if (m == 0) break;
+        k_chol_panel<<<ceil_div(m, kBlock), kBlock, 0, s>>>(c->Sfac.p, n, k0, nbk);
+        HIPCHK(hipGetLastError());
+        copy_batch<double, double>(c, {CopyDesc{(long long)k0 * n + k0 + nbk, 0, n, nbk, m, nbk, 1, 0}}, c->Sfac.p,
+                                   lt.p);
+        gemm_batch<double>(c, {GemmDesc{(long long)k0 * n + k0 + nbk, 0, (long long)(k0 + nbk) * n + k0 + nbk, n, nbk,
+                                        n, m, m, nbk}},
+                           c->Sfac.p, lt.p, c->Sfac.p, 0, -1.0, 1.0);
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
     const size_t smi = (size_t)n * 4 * sizeof(double);
     if (smi > 160 * 1024) c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
     if (smi > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smi));
@@ -749,8 +781,11 @@ void factor_impl(ddelm_ctx c) {
     k_assemble_X1<<<std::min(ceil_div(4ll * nn2, kBlock), 4096), kBlock, 0, s>>>(n, c->Sinv.p, c->Zm.p, c->Wm.p,
                                                                                  c->X1.p);
     HIPCHK(hipGetLastError());
+    c->X1t.alloc(4 * nn2);
+    copy_batch<double, double>(c, {CopyDesc{0, 0, 2 * n, 2 * n, 2 * n, 2 * n, 1, 0}}, c->X1.p, c->X1t.p);
   } else {
     c->X1.alloc(1);
+    c->X1t.alloc(1);
   }
   c->mark(4);
   c->offm_d.upload(std::vector<long long>(c->h_offm.begin(), c->h_offm.end() - 1), s);
@@ -1104,6 +1139,7 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
       size_t shm = 0;
       for (int i = 0; i < N; ++i) shm = std::max(shm, (size_t)(c->h_m[i] + c->h_nG[i]));
       shm *= sizeof(double);
+      double prev_worst = 0.0;
       for (int step = 0; step <= c->opt.refine_maxit; ++step) {
         acc(adjoint_core<float>(c, nrhs, c->adj_zc.p, nP ? c->adj_zP.p : nullptr, nD ? c->adj_zDg.p : nullptr,
                                 c->opt.inner_tol, c->adj_fw.p, c->adj_hwP.p, c->adj_hwD.p, c->adj_fbGP.p,
@@ -1119,7 +1155,10 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
           const double den = xn[r] + (nP ? xpn[r] : 0.0) + (nD ? xdn[r] : 0.0);
           worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
         }
-        if ((step > 0 && worst <= c->opt.refine_tol) || step == c->opt.refine_maxit) break;
+        if ((step > 0 && (worst <= c->opt.refine_tol || worst > kRefineStall * prev_worst)) ||
+            step == c->opt.refine_maxit)
+          break;
+        prev_worst = worst;
         k_adj_resid<<<dim3(N, nrhs), kBlock, shm, s>>>(
             c->M, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p, c->K64.p,
             c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, c->adj_fw.p, nP ? c->adj_hwP.p : nullptr,
@@ -1176,7 +1215,7 @@ void ddelm_default_options(ddelm_options* o) {
   o->cg_mode = 0;
   o->refine_maxit = 10;
   o->refine_tol = 1e-9;
-  o->inner_tol = 1e-6;
+  o->inner_tol = 1e-3;
 }
 
 ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_options* opt, void* stream) {
@@ -1368,6 +1407,7 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
       HIPCHK(hipGetLastError());
       acc(solve_core<float>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.inner_tol, coef, 0, muP.p, muD.p));
       const size_t shm = (size_t)c->M * sizeof(double);
+      double prev_worst = 0.0;
       for (int step = 0; step < c->opt.refine_maxit; ++step) {
         k_residual<<<dim3(N, nrhs), kBlock, shm, s>>>(
             c->M, c->nP, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,
@@ -1392,7 +1432,10 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
           const double num = dn[r] + dpn[r], den = xn[r] + xpn[r];
           worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
         }
-        if (worst <= c->opt.refine_tol) break;
+        // stop at the tolerance, or when the refinement stalls: the correction
+        // shrank by less than kRefineStall, so the float32 fixed point is near
+        if (worst <= c->opt.refine_tol || (step > 0 && worst > kRefineStall * prev_worst)) break;
+        prev_worst = worst;
       }
       if (mu_pi && c->nP > 0)
         HIPCHK(hipMemcpyAsync(mu_pi, muP.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -12,10 +12,16 @@
 //   C  y = -N lambda rows               D  z = -N^T (P lambda) rows
 //   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, w rows
 //   G  w = sum of owners, partial p.w   H  alpha, x and r updates, partial r.r
-// The coarse solves are done redundantly by every unit for its own corners
-// (rows of X1 against the full coarse right-hand side), which removes two
-// synchronisations.  Scalar reductions are repeated by every workgroup in
-// the same order, so all take identical decisions.
+// With few coarse unknowns the coarse solves are done redundantly by every
+// unit for its own corners (rows of X1 against the full coarse right-hand
+// side), which removes synchronisations.  With many (nP * nrhs large) every
+// unit gathering the whole coarse right-hand side costs more than two extra
+// synchronisations, so B and F are split: the coarse right-hand side is
+// gathered once, distributed over workgroups (B1, F1); the rows of X1 times
+// it are distributed over workgroups with X1 read about once (B2, F2); the
+// units then read their corner values (B3, F3).  Scalar reductions are
+// repeated by every workgroup in the same order, so all take identical
+// decisions.
 //
 // Synchronisation: every workgroup publishes an epoch in its own flag once
 // its memory operations have completed, then waits for all flags to reach
@@ -81,7 +87,88 @@ struct FusedArgs {
   unsigned* flags;       // [nb * kFlagStride]
   unsigned* err;
   int lds_ys, lds_part, lds_cu;   // LDS offsets (doubles) of the output, partial-sum and coarse areas
+  int lds_total;         // doubles of dynamic LDS
+  int dist;              // 1: distributed coarse phases
+  const double* X1t;     // X1 transposed (row-major X1), for the distributed coarse rows
+  double* ug;            // [nrhs][2 nP] gathered coarse right-hand side (distributed mode)
+  double* cg1;           // [nrhs][2 nP] X1 times it (distributed mode)
 };
+
+// Distributed coarse gather: for the Pi points of this workgroup's share,
+// ug[r][p] = sum over owners of A, ug[r][nP + p] = sum over owners of B (B may be null).
+template <typename T>
+__device__ void coarse_gather(const OpArgs<T>& a, const double* A, const double* B, int nrhs, double* ug) {
+  const unsigned nb = gridDim.x;
+  const int chunk = (a.nP + (int)nb - 1) / (int)nb;
+  const int p0 = blockIdx.x * chunk, p1 = min(a.nP, p0 + chunk);
+  for (int e = threadIdx.x; e < (p1 - p0) * nrhs; e += kBlock) {
+    const int pq = p0 + e / nrhs, r = e % nrhs;
+    double s1 = 0.0, s2 = 0.0;
+    for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o) {
+      const int sl = a.pi_own_slot[o];
+      s1 += ld_co(&A[(size_t)r * a.sumP + sl]);
+      if (B) s2 += ld_co(&B[(size_t)r * a.sumP + sl]);
+    }
+    st_co(&ug[(size_t)r * 2 * a.nP + pq], s1);
+    if (B) st_co(&ug[(size_t)r * 2 * a.nP + a.nP + pq], s2);
+  }
+}
+
+// Distributed coarse rows: out[r][row] = sum_{c < ncol} X1[row][c] ug[r][c]
+// for this workgroup's share of the 2 nP rows.  Right-hand sides are staged
+// in LDS in groups; each wave holds a 512-column tile of one X1 row in
+// registers and applies it to the whole group.
+template <int NR>
+__device__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, const double* ug, int nrhs, double* lds,
+                            int lds_cap, double* out) {
+  const unsigned nb = gridDim.x;
+  const int ld = 2 * nP;
+  const int chunk = (ld + (int)nb - 1) / (int)nb;
+  const int row0 = blockIdx.x * chunk, row1 = min(ld, row0 + chunk);
+  const int G = max(1, min(nrhs, lds_cap / max(ncol, 1)));
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int g0 = 0; g0 < nrhs; g0 += G) {
+    const int gn = min(G, nrhs - g0);
+    if (row1 > row0) {
+      for (int e = threadIdx.x; e < gn * ncol; e += kBlock) {
+        const int g = e / ncol, c = e % ncol;
+        lds[e] = ld_co(&ug[(size_t)(g0 + g) * ld + c]);
+      }
+    }
+    __syncthreads();
+    for (int row = row0 + wid; row < row1; row += kWaves) {
+      double acc[NR];
+#pragma unroll
+      for (int g = 0; g < NR; ++g) acc[g] = 0.0;
+      const double* xr = X1t + (long long)row * ld;
+      for (int c0 = 0; c0 < ncol; c0 += 64 * 8) {
+        double xv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int c = c0 + k * 64 + lane;
+          xv[k] = c < ncol ? xr[c] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int c = c0 + k * 64 + lane;
+          if (c < ncol) {
+#pragma unroll
+            for (int g = 0; g < NR; ++g)
+              if (g < gn) acc[g] += xv[k] * lds[g * ncol + c];
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < NR; ++g) {
+        if (g < gn) {
+          const double sum = wave_sum(acc[g]);
+          if (lane == 0) st_co(&out[(size_t)(g0 + g) * ld + row], sum);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 
 __device__ __forceinline__ void slice_rows(int n, int S, int q, int& r0, int& r1) {
   const int len = (n + S - 1) / S;
@@ -283,12 +370,31 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     flag_sync(f.flags, nb, ++epoch, f.err);
 
     // ---- B: coarse solve at the corners, lam rows
+    if (f.dist) {
+      coarse_gather(a, a.rho_loc, a.psi_loc, nrhs, f.ug);
+      flag_sync(f.flags, nb, ++epoch, f.err);
+      coarse_rows<NR>(f.X1t, a.nP, 2 * a.nP, f.ug, nrhs, lds, f.lds_total, f.cg1);
+      flag_sync(f.flags, nb, ++epoch, f.err);
+    }
     for (int u = blockIdx.x; u < nunits; u += nb) {
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
       const int ng = np + nd;
-      if (np > 0) {
+      if (np > 0 && f.dist) {
+        for (int e = threadIdx.x; e < 2 * np * nrhs; e += kBlock) {
+          const int kind = e / (np * nrhs), b = (e / nrhs) % np, r = e % nrhs;
+          cor[kind][b][r] = ld_co(&f.cg1[(size_t)r * 2 * a.nP + (kind ? a.nP : 0) + a.pi_l2g[p0 + b]]);
+        }
+        __syncthreads();
+        if (q == 0) {
+          for (int e = threadIdx.x; e < np * nrhs; e += kBlock) {
+            const int b = e / nrhs, r = e % nrhs;
+            st_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r]);
+            st_co(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r]);
+          }
+        }
+      } else if (np > 0) {
         for (int r = 0; r < nrhs; ++r) {
           for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
             double s1 = 0.0, s2 = 0.0;
@@ -400,12 +506,24 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     flag_sync(f.flags, nb, ++epoch, f.err);
 
     // ---- F: coarse nu at the corners, w rows
+    if (f.dist) {
+      coarse_gather(a, a.nu_loc, (const double*)nullptr, nrhs, f.ug);
+      flag_sync(f.flags, nb, ++epoch, f.err);
+      coarse_rows<NR>(f.X1t, a.nP, a.nP, f.ug, nrhs, lds, f.lds_total, f.cg1);
+      flag_sync(f.flags, nb, ++epoch, f.err);
+    }
     for (int u = blockIdx.x; u < nunits; u += nb) {
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
       const int ng = np + nd;
-      if (np > 0) {
+      if (np > 0 && f.dist) {
+        for (int e = threadIdx.x; e < 2 * np * nrhs; e += kBlock) {
+          const int kind = e / (np * nrhs), b = (e / nrhs) % np, r = e % nrhs;
+          cor[kind][b][r] = ld_co(&f.cg1[(size_t)r * 2 * a.nP + (kind ? a.nP : 0) + a.pi_l2g[p0 + b]]);
+        }
+        __syncthreads();
+      } else if (np > 0) {
         for (int r = 0; r < nrhs; ++r) {
           for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
             double s1 = 0.0;

@@ -393,33 +393,74 @@ __global__ void k_coarse_assemble(int nP, const int* __restrict__ own_ptr, const
   }
 }
 
-// In-place lower Cholesky of an n x n column-major SPD matrix (one
-// workgroup).  err[0] |= 2 if a pivot is not positive.
-__global__ void __launch_bounds__(kBlock) k_cholesky(double* __restrict__ S, int n, unsigned* __restrict__ err) {
-  __shared__ double piv;
-  for (int j = 0; j < n; ++j) {
+// Blocked right-looking Cholesky (lower, column-major, in place) of the
+// coarse Schur complement: for each block column k0 of width at most kCB,
+// k_chol_diag factors the diagonal block in LDS, k_chol_panel solves the
+// rows below against it (one thread per row), and the trailing matrix is
+// updated by one GEMM (A22 -= L21 L21^T) on the host side.  Only the lower
+// triangle is meaningful afterwards.  err[0] |= 2 if a pivot is not positive.
+constexpr int kCB = 32;
+
+__global__ void __launch_bounds__(kBlock) k_chol_diag(double* __restrict__ S, int n, int k0, int nb,
+                                                      unsigned* __restrict__ err) {
+  __shared__ double A[kCB][kCB + 1];   // A[col][row]
+  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    const int r = e % nb, c = e / nb;
+    A[c][r] = S[(long long)(k0 + c) * n + k0 + r];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
     if (threadIdx.x == 0) {
-      double dj = S[(long long)j * n + j];
-      if (!(dj > 0.0)) {
+      double d = A[j][j];
+      if (!(d > 0.0)) {
         atomicOr(err, 2u);
-        dj = 1.0;
+        d = 1.0;
       }
-      dj = sqrt(dj);
-      S[(long long)j * n + j] = dj;
-      piv = dj;
+      A[j][j] = sqrt(d);
     }
     __syncthreads();
-    const double inv = 1.0 / piv;
-    for (int r = j + 1 + threadIdx.x; r < n; r += kBlock) S[(long long)j * n + r] *= inv;
+    const double inv = 1.0 / A[j][j];
+    for (int r = j + 1 + threadIdx.x; r < nb; r += kBlock) A[j][r] *= inv;
     __syncthreads();
-    const int m = n - j - 1;
-    const long long tot = (long long)m * m;
-    for (long long e = threadIdx.x; e < tot; e += kBlock) {
-      const int r = j + 1 + (int)(e % m), c = j + 1 + (int)(e / m);
-      if (r >= c) S[(long long)c * n + r] -= S[(long long)j * n + r] * S[(long long)j * n + c];
+    const int m = nb - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += kBlock) {
+      const int r = j + 1 + e % m, c = j + 1 + e / m;
+      if (r >= c) A[c][r] -= A[j][r] * A[j][c];
     }
     __syncthreads();
   }
+  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    const int r = e % nb, c = e / nb;
+    if (r >= c) S[(long long)(k0 + c) * n + k0 + r] = A[c][r];
+  }
+}
+
+// L21 = A21 L11^{-T} for the rows k0 + nb .. n-1 of block column k0
+__global__ void __launch_bounds__(kBlock) k_chol_panel(double* __restrict__ S, int n, int k0, int nb) {
+  __shared__ double L[kCB][kCB + 1];   // L[col][row] of the factored diagonal block
+  for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    const int r = e % nb, c = e / nb;
+    L[c][r] = S[(long long)(k0 + c) * n + k0 + r];
+  }
+  __syncthreads();
+  const int r = k0 + nb + blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n) return;
+  double x[kCB];
+#pragma unroll
+  for (int j = 0; j < kCB; ++j) x[j] = j < nb ? S[(long long)(k0 + j) * n + r] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kCB; ++j) {
+    if (j < nb) {
+      double v = x[j];
+#pragma unroll
+      for (int l = 0; l < kCB; ++l)
+        if (l < j) v -= x[l] * L[l][j];
+      x[j] = v / L[j][j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kCB; ++j)
+    if (j < nb) S[(long long)(k0 + j) * n + r] = x[j];
 }
 
 // Columns of S^{-1} from the Cholesky factor (lower, column-major):

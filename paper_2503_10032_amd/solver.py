@@ -35,7 +35,7 @@ class DDELMSolver:
                  extra_s: Sequence[float] = (), lo=(0.0, 0.0), hi=(1.0, 1.0), theta: float = 0.999,
                  coarse: int = 2, tol: float = 1e-8, maxit: int = 20000, max_nrhs: int = 1,
                  cg_mode: int = 0, precision: int = 0, refine_maxit: int = 10, refine_tol: float = 1e-9,
-                 inner_tol: float = 1e-6, device: str = "cuda:0"):
+                 inner_tol: float = 1e-3, device: str = "cuda:0"):
         if not torch.cuda.is_available():
             raise DDELMError("DDELM-NN needs a GPU (torch.cuda.is_available() is False)")
         self.lib = L.load()

@@ -48,6 +48,9 @@ def test_default_options_without_gpu(lib):
     o = _lib.Options()
     l.ddelm_default_options(ctypes.byref(o))
     assert o.theta == 0.999 and o.coarse == 2 and o.precision == 0 and o.max_nrhs == 1
+    # the defaults the header documents
+    assert (o.tol, o.maxit, o.cg_mode) == (1e-8, 20000, 0)
+    assert (o.refine_maxit, o.refine_tol, o.inner_tol) == (10, 1e-9, 1e-3)
 
 
 def test_setup_rejects_null_problem(lib):

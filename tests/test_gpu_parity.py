@@ -56,6 +56,7 @@ CASES = {
     "4x3": dict(nx=4, ny=3, M=48, n_int=7, p=9, a=2.0, seed=2),
     "strip_no_pi": dict(nx=3, ny=1, M=40, n_int=6, p=8, a=2.0, seed=3),
     "single": dict(nx=1, ny=1, M=40, n_int=8, p=9, a=2.0, seed=4),
+    "7x7": dict(nx=7, ny=7, M=24, n_int=4, p=5, a=1.5, seed=6),     # nP = 36: several coarse Cholesky blocks
 }
 
 
@@ -150,7 +151,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("name,theta,coarse", [
     ("small", 0.999, 2), ("small", 0.0, 2), ("small", 0.999, 1), ("small", 0.5, 2),
     ("3x3_uneven", 0.999, 2), ("4x3", 0.999, 2), ("4x3", 1.0, 2),
-    ("strip_no_pi", 0.999, 2), ("single", 0.999, 2), ("4x3", 0.0, 0),
+    ("strip_no_pi", 0.999, 2), ("single", 0.999, 2), ("4x3", 0.0, 0), ("7x7", 0.999, 2),
 ])
 @pytest.mark.parametrize("cg_mode", [1, 2])
 def test_solve_matches_oracle(name, theta, coarse, cg_mode):
@@ -204,6 +205,21 @@ def test_multi_rhs_matches_oracle():
         u_ref = O.evaluate(geo, c.W, c.b, refs[r]["c"], X)
         assert _rel(u[r], u_ref) < 1e-10
         assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < 1e-9
+
+
+@pytest.mark.parametrize("name,nrhs", [("4x3", 1), ("7x7", 1), ("3x3_uneven", 4)])
+def test_distributed_coarse_phases_match_oracle(name, nrhs, monkeypatch):
+    """The persistent CG with the coarse phases split over workgroups (the
+    form taken when nP * nrhs is large), forced on small problems."""
+    monkeypatch.setenv("DDELM_CG_COARSE", "1")
+    c = Case(**CASES[name], tol=1e-13, cg_mode=2, rhs="fourier" if nrhs > 1 else "sinsin", nrhs=nrhs)
+    g, geo, s, out, refs = _solve_both(c)
+    X = I.eval_grid(c.w)
+    u = g.evaluate(out["coef"], X).cpu().numpy()
+    for r in range(nrhs):
+        assert _rel(u[r], O.evaluate(geo, c.W, c.b, refs[r]["c"], X)) < 1e-10
+        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < 1e-9
+        assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < 1e-9
 
 
 def test_cg_modes_agree_and_runs_repeat_bitwise():
