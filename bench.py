@@ -25,6 +25,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the CG kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (KiB per dispatch), scaled by the same counters' reading of a plain
+# copy of known size (FETCH_SIZE 0.5, WRITE_SIZE 1.0 of the bytes moved).  Valid
+# only for the kernel sources they were taken with (sha256 of the three files
+# below) and for the workload named; otherwise the bench reports null.
+CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
+CG_TRAFFIC = {
+    ("medium", "fp64"): dict(fetch_kib=1472796.3, write_kib=49145.3, fetch_scale=0.5, write_scale=1.0,
+                             sha256="4238b657b599688407aca219433afaaf891b47c831ec43cc83b712df2c01a7c4"),
+}
+
 
 def cg_bytes_per_iteration(counts, M, n_pi, nrhs, elem=8):
     """Algorithmic HBM bytes of one CG iteration: every local interface
@@ -37,6 +48,23 @@ def cg_bytes_per_iteration(counts, M, n_pi, nrhs, elem=8):
     coarse = 8 * (4 * n_pi * n_pi + 2 * n_pi * n_pi)
     vecs = 8 * nrhs * int(np.sum(nD)) * 12
     return mats + coarse + vecs
+
+
+def cg_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in CG_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_10032_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cg_traffic_bytes(workload, precision):
+    """Measured HBM bytes per CG launch, or None when not measured for these sources."""
+    t = CG_TRAFFIC.get((workload, precision))
+    if t is None or t["sha256"] != cg_sources_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] / t["fetch_scale"] + t["write_kib"] / t["write_scale"])
 
 
 def cpu_baseline(w, W, b, xi, iters_gpu, budget_iters=10):
@@ -79,7 +107,22 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 5 times (the known-size kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                          "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (multi-GPU sharding is a "
               f"design note, not part of this build)", file=sys.stderr)
@@ -159,7 +202,7 @@ def main():
     roof = {
         "kernel": "k_cg_persistent (CG on eq. nn-mixed, one cooperative launch per solve)",
         "bound": "hbm", "achieved": bpi * it / (cg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "traffic": None,
+        "traffic": cg_traffic_bytes(w.name, args.precision),
     }
     roof["frac"] = roof["achieved"] / roof["peak"]
     res = {

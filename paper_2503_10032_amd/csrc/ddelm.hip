@@ -1261,6 +1261,8 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     c->use_nn = o.theta != 0.0 && o.coarse > 0;
     if (g.max_m > kBlock * 12) c->fail(DDELM_E_SHAPE, "local row count above 3072");
     if (g.max_nG > 4096) c->fail(DDELM_E_SHAPE, "too many interface points per subdomain");
+    for (int k = 0; k < g.n_dl; ++k)
+      if (g.dl_own_ptr[k + 1] - g.dl_own_ptr[k] > kMaxOwn) c->fail(DDELM_E_SHAPE, "Delta point with more than 4 owners");
     c->h_m.resize(N); c->h_nG.resize(N); c->h_nD.resize(N); c->h_nP.resize(N); c->h_nB.resize(N);
     c->h_offB.assign(N + 1, 0); c->h_offm.assign(N + 1, 0);
     std::vector<int> sizes(5 * (size_t)N);

@@ -35,6 +35,13 @@ namespace ddelm {
 
 constexpr int kFlagStride = 16;   // one flag per 64-byte line
 
+// Coherent loads of values written by other workgroups are issued in
+// batches of kLB elements before any of them is used: each such load goes to
+// memory, and a loop that consumed every value right after loading it would
+// pay one full round trip per element.
+constexpr int kLB = 8;
+constexpr int kMaxOwn = 4;   // owners of an interface point: 2 on an edge, 4 at a vertex
+
 // Coherent (agent-scope) loads and stores for every value that one workgroup
 // writes and another reads inside the kernel.  They bypass the per-XCD L2
 // copies, so no cache write-back or invalidation fences are needed; the
@@ -130,9 +137,17 @@ __device__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, co
   for (int g0 = 0; g0 < nrhs; g0 += G) {
     const int gn = min(G, nrhs - g0);
     if (row1 > row0) {
-      for (int e = threadIdx.x; e < gn * ncol; e += kBlock) {
-        const int g = e / ncol, c = e % ncol;
-        lds[e] = ld_co(&ug[(size_t)(g0 + g) * ld + c]);
+      const int n = gn * ncol;
+      for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
+        double v[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock;
+          v[u] = e < n ? ld_co(&ug[(size_t)(g0 + e / ncol) * ld + e % ncol]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u)
+          if (e0 + u * kBlock < n) lds[e0 + u * kBlock] = v[u];
       }
     }
     __syncthreads();
@@ -187,8 +202,9 @@ __device__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0
     __syncthreads();
     return;
   }
-  int Rp = ((R + 63) / 64) * 64;
-  if (Rp > kBlock) Rp = kBlock;     // R > 256: rows handled in passes
+  // rows per pass: 64, 128 or 256 so that no thread of the block idles for
+  // the whole pass (a 192-row pass would leave a quarter of them without work)
+  int Rp = R <= 64 ? 64 : (R <= 128 ? 128 : ((R > 192 && R <= 256) ? 256 : 64));
   const int nsplit = kBlock / Rp;
   for (int rb = 0; rb < R; rb += Rp) {
     const int t = threadIdx.x % Rp, j = threadIdx.x / Rp;
@@ -201,31 +217,32 @@ __device__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0
     if (row < R && j < nsplit) {
       const T* a0 = A0 + (long long)c0 * lda + r0 + row;
       const T* a1 = NM > 1 ? A1 + (long long)c0 * lda + r0 + row : nullptr;
-      int k = j;
-      for (; k + 3 * nsplit < K; k += 4 * nsplit) {
-        double v0[4], v1[4];
+      // batches of kU columns, the last one predicated: all loads of a batch
+      // are issued before its products, so each thread keeps kU * NM loads in
+      // flight and a row costs ceil(K / (kU * nsplit)) memory round trips.
+      // The matrix stream is latency bound, so with many right-hand sides
+      // (one wave per SIMD) the batch is deeper; with few, 16 columns
+      // measured faster.
+      constexpr int kU = NR >= 8 ? 32 : 16;
+      for (int k = j; k < K; k += kU * nsplit) {
+        double v0[kU], v1[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          v0[u] = (double)a0[(long long)(k + u * nsplit) * lda];
-          if (NM > 1) v1[u] = (double)a1[(long long)(k + u * nsplit) * lda];
+        for (int u = 0; u < kU; ++u) {
+          const int kk = k + u * nsplit;
+          v0[u] = kk < K ? (double)a0[(long long)kk * lda] : 0.0;
+          if (NM > 1) v1[u] = kk < K ? (double)a1[(long long)kk * lda] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kU; ++u) {
+          const int kk = k + u * nsplit;
+          if (kk < K) {
 #pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double xv = x[(k + u * nsplit) * NR + r];
-            acc[0][r] += v0[u] * xv;
-            if (NM > 1) acc[NM - 1][r] += v1[u] * xv;
+            for (int r = 0; r < NR; ++r) {
+              const double xv = x[kk * NR + r];
+              acc[0][r] += v0[u] * xv;
+              if (NM > 1) acc[NM - 1][r] += v1[u] * xv;
+            }
           }
-      }
-      for (; k < K; k += nsplit) {
-        const double v0 = (double)a0[(long long)k * lda];
-        const double v1 = NM > 1 ? (double)a1[(long long)k * lda] : 0.0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const double xv = x[k * NR + r];
-          acc[0][r] += v0 * xv;
-          if (NM > 1) acc[NM - 1][r] += v1 * xv;
         }
       }
     }
@@ -252,20 +269,42 @@ template <int NR>
 __device__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2g, int d0,
                           int nd, const double* A, const double* B, double ca, double cb, int sumD, int nrhs,
                           double* xs) {
-  for (int e = threadIdx.x; e < nd * NR; e += kBlock) {
-    const int k = e / NR, r = e % NR;
-    double v = 0.0;
-    if (r < nrhs) {
-      const int g = l2g[d0 + k];
-      double sa = 0.0, sb = 0.0;
-      for (int o = own_ptr[g]; o < own_ptr[g + 1]; ++o) {
-        const int sl = own_slot[o];
-        sa += ld_co(&A[(size_t)r * sumD + sl]);
-        if (B) sb += ld_co(&B[(size_t)r * sumD + sl]);
+  const int n = nd * NR;
+  for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
+    double va[kLB][kMaxOwn], vb[kLB][kMaxOwn];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+      int o0 = 0, cnt = 0;
+      if (e < n && r < nrhs) {
+        const int g = l2g[d0 + k];
+        o0 = own_ptr[g];
+        cnt = own_ptr[g + 1] - o0;
       }
-      v = B ? ca * sa + cb * sb : sa;
+#pragma unroll
+      for (int o = 0; o < kMaxOwn; ++o) {
+        va[u][o] = 0.0;
+        vb[u][o] = 0.0;
+        if (o < cnt) {
+          const size_t sl = (size_t)r * sumD + own_slot[o0 + o];
+          va[u][o] = ld_co(&A[sl]);
+          if (B) vb[u][o] = ld_co(&B[sl]);
+        }
+      }
     }
-    xs[e] = v;
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < n) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int o = 0; o < kMaxOwn; ++o) {
+          sa += va[u][o];
+          sb += vb[u][o];
+        }
+        xs[e] = B ? ca * sa + cb * sb : sa;
+      }
+    }
   }
 }
 
@@ -273,8 +312,10 @@ template <typename T, int NR>
 __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
   extern __shared__ double lds[];
   __shared__ double red[kWaves];
+  __shared__ double redv[kWaves * NR];
   __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR];
   __shared__ double cor[2][4][NR];          // per corner: (mu, e) or (nu, -D nu)
+  __shared__ double cms[2][4][NR];          // per corner: (mu, e) read back in F
   const OpArgs<T>& a = f.a;
   const unsigned nb = gridDim.x;
   const int nrhs = f.nrhs;
@@ -306,10 +347,21 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
   int it = 0;
   for (;; ++it) {
     // ---- reduce r.r, convergence test, beta (identical in every workgroup)
-    for (int r = 0; r < nrhs; ++r) {
-      double rr = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) rr += ld_co(&f.part[(size_t)(nrhs + r) * nb + k]);
-      rr = block_sum(rr, red);
+    double rrs[NR], rrt[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) rrs[r] = 0.0;
+    for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
+      double v[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r] = r < nrhs ? ld_co(&f.part[(size_t)(nrhs + r) * nb + k]) : 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) rrs[r] += v[r];
+    }
+    block_sum_vec<double, NR>(rrs, rrt, redv);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nrhs) continue;
+      const double rr = rrt[r];
       if (threadIdx.x == 0) {
         if (it == 0) {
           sc_bb[r] = rr; sc_rr[r] = rr; sc_done[r] = (rr == 0.0) ? 1.0 : 0.0; sc_it[r] = 0; sc_beta[r] = 0.0;
@@ -337,16 +389,31 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
       const int ng = np + nd;
-      for (int e = threadIdx.x; e < nd * NR; e += kBlock) {
-        const int k = e / NR, r = e % NR;
-        double v = 0.0;
-        if (r < nrhs) {
-          const int g = a.dl_l2g[d0 + k];
-          const size_t ge = (size_t)r * a.nD + g;
-          v = ld_co(&f.r[ge]) + sc_beta[r] * ld_co(&pp[ge]);
-          if (q == 0 && a.dl_own_slot[a.dl_own_ptr[g]] == d0 + k) st_co(&pc[ge], v);
+      for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLB * kBlock) {
+        double rv[kLB], pv[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+          rv[u] = 0.0;
+          pv[u] = 0.0;
+          if (e < nd * NR && r < nrhs) {
+            const size_t ge = (size_t)r * a.nD + a.dl_l2g[d0 + k];
+            rv[u] = ld_co(&f.r[ge]);
+            pv[u] = ld_co(&pp[ge]);
+          }
         }
-        xs[e] = v;
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+          if (e >= nd * NR) continue;
+          double v = 0.0;
+          if (r < nrhs) {
+            const int g = a.dl_l2g[d0 + k];
+            v = rv[u] + sc_beta[r] * pv[u];
+            if (q == 0 && a.dl_own_slot[a.dl_own_ptr[g]] == d0 + k) st_co(&pc[(size_t)r * a.nD + g], v);
+          }
+          xs[e] = v;
+        }
       }
       __syncthreads();
       int r0, r1;
@@ -430,12 +497,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       int r0, r1;
       slice_rows(nd, f.S, q, r0, r1);
       const T* L = a.Lm + a.offG[i];
-      for (int e = threadIdx.x; e < (r1 - r0) * nrhs; e += kBlock) {
-        const int tt = e / nrhs, r = e % nrhs;
-        const int row = r0 + tt;
-        double acc = ld_co(&a.l_loc[(size_t)r * a.sumD + d0 + row]);
-        for (int b = 0; b < np; ++b) acc -= (double)L[(long long)b * ng + np + row] * cor[0][b][r];
-        st_co(&a.lam_loc[(size_t)r * a.sumD + d0 + row], acc);
+      for (int e0 = threadIdx.x; e0 < (r1 - r0) * nrhs; e0 += kLB * kBlock) {
+        double lv[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock;
+          lv[u] = e < (r1 - r0) * nrhs ? ld_co(&a.l_loc[(size_t)(e % nrhs) * a.sumD + d0 + r0 + e / nrhs]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock;
+          if (e >= (r1 - r0) * nrhs) continue;
+          const int row = r0 + e / nrhs, r = e % nrhs;
+          double acc = lv[u];
+          for (int b = 0; b < np; ++b) acc -= (double)L[(long long)b * ng + np + row] * cor[0][b][r];
+          st_co(&a.lam_loc[(size_t)r * a.sumD + d0 + row], acc);
+        }
       }
       __syncthreads();
     }
@@ -544,57 +621,123 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
           __syncthreads();
         }
       }
+      // mu and e at the corners (from B) next to nu and -D nu (cor)
+      for (int e = threadIdx.x; e < 2 * np * nrhs; e += kBlock) {
+        const int kind = e / (np * nrhs), b = (e / nrhs) % np, r = e % nrhs;
+        cms[kind][b][r] = ld_co(&(kind ? f.e_slot : f.mu_slot)[(size_t)r * a.sumP + p0 + b]);
+      }
+      __syncthreads();
       int r0, r1;
       slice_rows(nd, f.S, q, r0, r1);
       const T* G = a.Gm + a.offG[i];
       const T* LT = a.LTm + a.offG[i];
-      for (int e = threadIdx.x; e < (r1 - r0) * nrhs; e += kBlock) {
-        const int tt = e / nrhs, r = e % nrhs;
-        const int row = r0 + tt;
-        double acc = ld_co(&a.s_loc[(size_t)r * a.sumD + d0 + row]) + ld_co(&a.t_loc[(size_t)r * a.sumD + d0 + row]);
-        for (int b = 0; b < np; ++b) {
-          const double mu = ld_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b]);
-          const double ee = ld_co(&f.e_slot[(size_t)r * a.sumP + p0 + b]);
-          acc -= (double)G[(long long)b * ng + np + row] * (mu + cor[0][b][r]);
-          acc += (double)LT[(long long)b * ng + np + row] * (ee + cor[1][b][r]);
+      for (int e0 = threadIdx.x; e0 < (r1 - r0) * nrhs; e0 += kLB * kBlock) {
+        double sv[kLB], tv[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock;
+          sv[u] = 0.0;
+          tv[u] = 0.0;
+          if (e < (r1 - r0) * nrhs) {
+            const size_t el = (size_t)(e % nrhs) * a.sumD + d0 + r0 + e / nrhs;
+            sv[u] = ld_co(&a.s_loc[el]);
+            tv[u] = ld_co(&a.t_loc[el]);
+          }
         }
-        st_co(&a.w_loc[(size_t)r * a.sumD + d0 + row], acc);
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int e = e0 + u * kBlock;
+          if (e >= (r1 - r0) * nrhs) continue;
+          const int row = r0 + e / nrhs, r = e % nrhs;
+          double acc = sv[u] + tv[u];
+          for (int b = 0; b < np; ++b) {
+            acc -= (double)G[(long long)b * ng + np + row] * (cms[0][b][r] + cor[0][b][r]);
+            acc += (double)LT[(long long)b * ng + np + row] * (cms[1][b][r] + cor[1][b][r]);
+          }
+          st_co(&a.w_loc[(size_t)r * a.sumD + d0 + row], acc);
+        }
       }
       __syncthreads();
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
 
-    // ---- G: w = sum of owners, partial p.w
-    for (int r = 0; r < nrhs; ++r) {
-      double acc = 0.0;
+    // ---- G: w = sum of owners, partial p.w (all right-hand sides of a point together)
+    {
+      double accs[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) accs[r] = 0.0;
       for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
-        double wv = 0.0;
-        for (int o = a.dl_own_ptr[g]; o < a.dl_own_ptr[g + 1]; ++o)
-          wv += ld_co(&a.w_loc[(size_t)r * a.sumD + a.dl_own_slot[o]]);
-        f.w[(size_t)r * a.nD + g] = wv;
-        acc += wv * ld_co(&pc[(size_t)r * a.nD + g]);
+        const int o0 = a.dl_own_ptr[g], cnt = a.dl_own_ptr[g + 1] - o0;
+        double wv[NR][kMaxOwn], pv[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+          for (int o = 0; o < kMaxOwn; ++o)
+            wv[r][o] = (r < nrhs && o < cnt) ? ld_co(&a.w_loc[(size_t)r * a.sumD + a.dl_own_slot[o0 + o]]) : 0.0;
+          pv[r] = r < nrhs ? ld_co(&pc[(size_t)r * a.nD + g]) : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r >= nrhs) continue;
+          double w = 0.0;
+#pragma unroll
+          for (int o = 0; o < kMaxOwn; ++o) w += wv[r][o];
+          f.w[(size_t)r * a.nD + g] = w;
+          accs[r] += w * pv[r];
+        }
       }
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], acc);
+      double tot[NR];
+      block_sum_vec<double, NR>(accs, tot, redv);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], tot[r]);
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
 
-    // ---- H: alpha, x and r updates, partial r.r
-    for (int r = 0; r < nrhs; ++r) {
-      double pw = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) pw += ld_co(&f.part[(size_t)r * nb + k]);
-      pw = block_sum(pw, red);
-      const double al = (sc_done[r] != 0.0 || pw == 0.0) ? 0.0 : sc_rr[r] / pw;
-      double acc = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
-        const size_t e = (size_t)r * a.nD + g;
-        f.x[e] += al * ld_co(&pc[e]);
-        const double rv = ld_co(&f.r[e]) - al * f.w[e];
-        st_co(&f.r[e], rv);
-        acc += rv * rv;
+    // ---- H: alpha, x and r updates, partial r.r (all right-hand sides of a point together)
+    {
+      double pws[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) pws[r] = 0.0;
+      for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
+        double v[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = r < nrhs ? ld_co(&f.part[(size_t)r * nb + k]) : 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pws[r] += v[r];
       }
-      acc = block_sum(acc, red);
-      if (threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], acc);
+      double pwt[NR];
+      block_sum_vec<double, NR>(pws, pwt, redv);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs && threadIdx.x == 0) sc_alpha[r] = (sc_done[r] != 0.0 || pwt[r] == 0.0) ? 0.0 : sc_rr[r] / pwt[r];
+      __syncthreads();
+      double accs[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) accs[r] = 0.0;
+      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
+        double pv[NR], rv[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          pv[r] = r < nrhs ? ld_co(&pc[(size_t)r * a.nD + g]) : 0.0;
+          rv[r] = r < nrhs ? ld_co(&f.r[(size_t)r * a.nD + g]) : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r >= nrhs) continue;
+          const size_t e = (size_t)r * a.nD + g;
+          const double al = sc_alpha[r];
+          f.x[e] += al * pv[r];
+          const double rn = rv[r] - al * f.w[e];
+          st_co(&f.r[e], rn);
+          accs[r] += rn * rn;
+        }
+      }
+      double tot[NR];
+      block_sum_vec<double, NR>(accs, tot, redv);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], tot[r]);
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
   }
