@@ -118,9 +118,11 @@ __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)
 constexpr double kRefineStall = 0.5;
 
 struct RowSetDev {
+  int lead = 0;
   DBuf<int> row0, ptr;
   DBuf<Term> terms;
   void upload(const RowSet& r, hipStream_t s) {
+    lead = r.lead;
     row0.upload(r.row0, s);
     ptr.upload(r.ptr, s);
     terms.upload(r.terms, s);
@@ -320,6 +322,7 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, c
                        const std::vector<int>& ld, int sub0, int nsub) {
   if (max_rows == 0 || nsub == 0) return;
   FeatArgs a;
+  a.lead = rs.lead; a.xint = c->x_int.p;
   a.row0 = rs.row0.p; a.ptr = rs.ptr.p; a.terms = rs.terms.p;
   a.W = c->W.p; a.bias = c->b.p; a.geom = c->geom.p;
   a.off = c->arena.put(off, c->stream); a.ld = c->arena.put(ld, c->stream); a.M = c->M; a.sub0 = sub0;
@@ -1480,9 +1483,13 @@ ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long
     if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
     if (nrhs < 1 || npts < 0 || !coef || (npts > 0 && (!x || !u))) c->fail(DDELM_E_ARG, "bad evaluate arguments");
     const Geometry& g = c->geo;
-    for (int r = 0; r < nrhs && npts > 0; ++r) {
-      k_evaluate<<<ceil_div(npts, kBlock), kBlock, 0, c->stream>>>(g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0],
-                                                                  g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, r);
+    if (npts > 0) {
+      if (nrhs == 1)
+        k_evaluate<1><<<dim3(ceil_div(npts, kBlock), 1), kBlock, 0, c->stream>>>(
+            g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, nrhs);
+      else
+        k_evaluate<8><<<dim3(ceil_div(npts, kBlock), ceil_div(nrhs, 8)), kBlock, 0, c->stream>>>(
+            g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, nrhs);
       HIPCHK(hipGetLastError());
     }
   });

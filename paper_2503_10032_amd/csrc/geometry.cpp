@@ -101,8 +101,21 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
 
   subs.assign(N, SubInfo());
   rowsK = RowSet(); rowsA = RowSet(); rowsKb = RowSet(); rowsAb = RowSet();
+  rowsK.lead = rowsKb.lead = n_int;   // interior rows come straight from x_int
+  {
+    const size_t side_rows = (size_t)N * (4 * (size_t)p + 4 * s_extra.size() + 8);
+    for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) {
+      r->ptr.reserve(side_rows + 1);
+      r->row0.reserve(N + 1);
+      r->terms.reserve(2 * side_rows);
+    }
+    rowsA.terms.reserve(side_rows + (size_t)N * 8 * p);
+  }
   for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) r->ptr.push_back(0);
 
+  std::vector<Term> ft, ct;   // terms of one corner flux row / one continuity row
+  ft.reserve(8 * (size_t)p);
+  ct.reserve(3);
   for (int iy = 0; iy < ny; ++iy) {
     for (int ix = 0; ix < nx; ++ix) {
       const int i = iy * nx + ix;
@@ -184,12 +197,6 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
       };
       // ---- rows
       for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) r->begin_sub();
-      for (int k = 0; k < n_int; ++k) {
-        Term t{x_int[((size_t)i * n_int + k) * 2], x_int[((size_t)i * n_int + k) * 2 + 1], 0, 0, 1.0,
-               OP_NEG_LAPLACE, 0};
-        rowsK.add_row({t});
-        rowsKb.add_row({t});
-      }
       for (int k = 0; k < sb.n_B; ++k) {
         Term t{sb.xB[2 * k], sb.xB[2 * k + 1], 0, 0, 1.0, OP_VALUE, 0};
         rowsK.add_row({t});
@@ -200,7 +207,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
         rowsK.add_row({t});
         rowsKb.add_row({t});
         // flux row at a corner
-        std::vector<Term> ft;
+        ft.clear();
         if (coarse == 2) {
           for (int sd = 0; sd < 4; ++sd) {
             if (sds[sd].on_boundary) continue;
@@ -226,7 +233,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
         if (g.side >= 0) { n[0] = kNormal[g.side][0]; n[1] = kNormal[g.side][1]; }
         else vertex_normal(g.vjx, g.vjy, n);
         // continuity row
-        std::vector<Term> ct{Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0}};
+        ct.assign(1, Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0});
         if (coarse == 2 && g.side >= 0) {
           const SideDesc& d = sds[g.side];
           const double sk = s[g.k];
@@ -258,38 +265,42 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
   }
   pi_loc2glob.assign(pi_off[N], 0);
   dl_loc2glob.assign(dl_off[N], 0);
-  std::vector<std::vector<int>> pown(n_pi), down(n_dl);
+  // owner lists in CSR form by counting: slots of a point in subdomain order
+  pi_own_ptr.assign(n_pi + 1, 0);
+  dl_own_ptr.assign(n_dl + 1, 0);
   x_pi.assign(2 * (size_t)n_pi, 0.0);
   x_dl.assign(2 * (size_t)n_dl, 0.0);
   for (int i = 0; i < N; ++i) {
     const SubInfo& sb = subs[i];
     for (int a = 0; a < sb.n_P; ++a) {
-      int g = sb.pi_glob[a];
+      const int g = sb.pi_glob[a];
       pi_loc2glob[pi_off[i] + a] = g;
-      if (pown[g].empty()) { x_pi[2 * g] = sb.xG[2 * a]; x_pi[2 * g + 1] = sb.xG[2 * a + 1]; }
-      pown[g].push_back(pi_off[i] + a);
+      if (pi_own_ptr[g + 1]++ == 0) { x_pi[2 * g] = sb.xG[2 * a]; x_pi[2 * g + 1] = sb.xG[2 * a + 1]; }
     }
     for (int a = 0; a < sb.n_D; ++a) {
-      int g = sb.dl_glob[a];
+      const int g = sb.dl_glob[a];
       dl_loc2glob[dl_off[i] + a] = g;
-      if (down[g].empty()) {
+      if (dl_own_ptr[g + 1]++ == 0) {
         x_dl[2 * g] = sb.xG[2 * (sb.n_P + a)];
         x_dl[2 * g + 1] = sb.xG[2 * (sb.n_P + a) + 1];
       }
-      down[g].push_back(dl_off[i] + a);
     }
   }
-  pi_own_ptr.assign(1, 0); pi_own_slot.clear();
   for (int g = 0; g < n_pi; ++g) {
-    if (pown[g].empty()) return "internal: Pi point without owner";
-    for (int sl : pown[g]) pi_own_slot.push_back(sl);
-    pi_own_ptr.push_back((int)pi_own_slot.size());
+    if (pi_own_ptr[g + 1] == 0) return "internal: Pi point without owner";
+    pi_own_ptr[g + 1] += pi_own_ptr[g];
   }
-  dl_own_ptr.assign(1, 0); dl_own_slot.clear();
   for (int g = 0; g < n_dl; ++g) {
-    if (down[g].size() < 2) return "internal: Delta point with fewer than two owners";
-    for (int sl : down[g]) dl_own_slot.push_back(sl);
-    dl_own_ptr.push_back((int)dl_own_slot.size());
+    if (dl_own_ptr[g + 1] < 2) return "internal: Delta point with fewer than two owners";
+    dl_own_ptr[g + 1] += dl_own_ptr[g];
+  }
+  pi_own_slot.assign(pi_own_ptr[n_pi], 0);
+  dl_own_slot.assign(dl_own_ptr[n_dl], 0);
+  std::vector<int> pcur(pi_own_ptr.begin(), pi_own_ptr.end() - 1), dcur(dl_own_ptr.begin(), dl_own_ptr.end() - 1);
+  for (int i = 0; i < N; ++i) {
+    const SubInfo& sb = subs[i];
+    for (int a = 0; a < sb.n_P; ++a) pi_own_slot[pcur[sb.pi_glob[a]]++] = pi_off[i] + a;
+    for (int a = 0; a < sb.n_D; ++a) dl_own_slot[dcur[sb.dl_glob[a]]++] = dl_off[i] + a;
   }
   return "";
 }

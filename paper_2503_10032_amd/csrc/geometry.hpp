@@ -37,10 +37,14 @@ struct SubInfo {
 };
 
 // Row descriptors of one family of local matrices, all subdomains
-// concatenated: row r of subdomain i has terms [ptr[row0_i + r], ptr[row0_i + r + 1]).
+// concatenated.  The first `lead` rows of every subdomain are its interior
+// collocation rows, -Laplace(phi) at the given interior points, which are not
+// stored as terms; row lead + r of subdomain i has terms
+// [ptr[row0_i + r], ptr[row0_i + r + 1]).
 struct RowSet {
-  std::vector<int> row0;        // [N+1] first row of each subdomain
-  std::vector<int> ptr;         // [rows+1]
+  int lead = 0;                 // implicit interior rows per subdomain
+  std::vector<int> row0;        // [N+1] first stored row of each subdomain
+  std::vector<int> ptr;         // [stored rows+1]
   std::vector<Term> terms;
   void begin_sub() { row0.push_back((int)ptr.size() - 1); }
   void add_row(std::initializer_list<Term> ts) {

@@ -377,12 +377,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
 }
 
 // ---------------------------------------------------------------- evaluation
-__global__ void k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0, double h1,
-                           const double* __restrict__ W, const double* __restrict__ bias,
-                           const double* __restrict__ coef, long long npts, const double* __restrict__ x,
-                           double* __restrict__ u, double* __restrict__ grad, int r) {
+// u[r][p] (and grad[r][p][:]) for the right-hand sides r0 .. r0+NRB-1 (< nrhs)
+// at point p = blockIdx.x * kBlock + threadIdx.x, r0 = blockIdx.y * NRB: one
+// tanh per (point, neuron) serves every right-hand side of the group.
+template <int NRB>
+__global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0,
+                                                     double h1, const double* __restrict__ W,
+                                                     const double* __restrict__ bias, const double* __restrict__ coef,
+                                                     long long npts, const double* __restrict__ x,
+                                                     double* __restrict__ u, double* __restrict__ grad, int nrhs) {
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (e >= npts) return;
+  const int r0 = blockIdx.y * NRB;
   const double px = x[2 * e], py = x[2 * e + 1];
   int ix = (int)ceil((px - lo0) / h0) - 1, iy = (int)ceil((py - lo1) / h1) - 1;
   ix = ix < 0 ? 0 : (ix > nx - 1 ? nx - 1 : ix);
@@ -391,20 +397,33 @@ __global__ void k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1,
   const double hx = 0.5 * h0, hy = 0.5 * h1;
   const double cx = lo0 + (ix + 0.5) * h0, cy = lo1 + (iy + 0.5) * h1;
   const double xi0 = (px - cx) / hx, xi1 = (py - cy) / hy;
-  const double* c = coef + ((size_t)r * N + i) * M;
-  double acc = 0.0, g0 = 0.0, g1 = 0.0;
+  double acc[NRB], g0[NRB], g1[NRB];
+#pragma unroll
+  for (int k = 0; k < NRB; ++k) acc[k] = g0[k] = g1[k] = 0.0;
   for (int j = 0; j < M; ++j) {
     const double w0 = W[((size_t)i * M + j) * 2], w1 = W[((size_t)i * M + j) * 2 + 1];
     const double t = tanh(w0 * xi0 + w1 * xi1 + bias[(size_t)i * M + j]);
-    acc += c[j] * t;
-    const double dt = c[j] * (1.0 - t * t);
-    g0 += dt * w0;
-    g1 += dt * w1;
+    const double dt = 1.0 - t * t;
+#pragma unroll
+    for (int k = 0; k < NRB; ++k) {
+      if (r0 + k < nrhs) {
+        const double c = coef[((size_t)(r0 + k) * N + i) * M + j];
+        acc[k] += c * t;
+        const double d = c * dt;
+        g0[k] += d * w0;
+        g1[k] += d * w1;
+      }
+    }
   }
-  u[(size_t)r * npts + e] = acc;
-  if (grad) {
-    grad[((size_t)r * npts + e) * 2] = g0 / hx;
-    grad[((size_t)r * npts + e) * 2 + 1] = g1 / hy;
+#pragma unroll
+  for (int k = 0; k < NRB; ++k) {
+    if (r0 + k >= nrhs) continue;
+    const int r = r0 + k;
+    u[(size_t)r * npts + e] = acc[k];
+    if (grad) {
+      grad[((size_t)r * npts + e) * 2] = g0[k] / hx;
+      grad[((size_t)r * npts + e) * 2 + 1] = g1[k] / hy;
+    }
   }
 }
 

@@ -15,8 +15,10 @@ namespace ddelm {
 //   flux       (1 - t^2) (w0 nx/hx + w1 ny/hy)
 // Output: column-major, element (r, j) at out[off[i] + j*ld[i] + r].
 struct FeatArgs {
-  const int* row0;       // [N+1]
-  const int* ptr;        // [rows+1]
+  int lead;              // implicit interior rows per subdomain (-Laplace at xint)
+  const double* xint;    // [N][lead][2]
+  const int* row0;       // [N+1] first stored row
+  const int* ptr;        // [stored rows+1]
   const Term* terms;
   const double* W;       // [N][M][2]
   const double* bias;    // [N][M]
@@ -32,15 +34,22 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   const int i = a.sub0 + blockIdx.z;
   const int r = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int nrows = a.row0[i + 1] - a.row0[i];
+  const int nrows = a.lead + a.row0[i + 1] - a.row0[i];
   if (r >= nrows || j >= a.M) return;
   const double cx = a.geom[4 * i], cy = a.geom[4 * i + 1], hx = a.geom[4 * i + 2], hy = a.geom[4 * i + 3];
   const double w0 = a.W[((size_t)i * a.M + j) * 2], w1 = a.W[((size_t)i * a.M + j) * 2 + 1];
   const double bj = a.bias[(size_t)i * a.M + j];
   const double gx = w0 / hx, gy = w1 / hy;
   const double lap = gx * gx + gy * gy;
-  const int row = a.row0[i] + r;
   double acc = 0.0;
+  if (r < a.lead) {            // interior row: -Laplace(phi) at the interior point
+    const double px = a.xint[((size_t)i * a.lead + r) * 2], py = a.xint[((size_t)i * a.lead + r) * 2 + 1];
+    const double t = tanh(w0 * ((px - cx) / hx) + w1 * ((py - cy) / hy) + bj);
+    const double v = 2.0 * t * (1.0 - t * t) * lap;
+    out[a.off[i] + (long long)j * a.ld[i] + r] = (T)v;
+    return;
+  }
+  const int row = a.row0[i] + r - a.lead;
   for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
     const Term tm = a.terms[q];
     const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;

@@ -140,7 +140,7 @@ def test_autograd_gradient_in_data_coefficients_matches_oracle():
     PhiI, PhiB = _basis(g, c)
     ap = I.adjoint_params(5)
     xo = I.observation_points(2000, seed=6)
-    u_obs = np.sin(np.pi * xo[:, 0]) * np.cos(np.pi * xo[:, 1])
+    u_obs = I.sinsin_u(xo)
     dev = torch.device("cuda:0")
     th = torch.tensor(ap.theta, device=dev, requires_grad=True)
     et = torch.tensor(ap.eta, device=dev, requires_grad=True)
@@ -205,7 +205,7 @@ def test_adjoint_workload_full_size_by_properties():
     tPB = torch.tensor(I.AdjointParams.g_basis(xB), device=dev)
     xo = I.observation_points(10000, seed=6)
     xt = torch.tensor(xo, device=dev)
-    ut = torch.tensor(np.sin(np.pi * xo[:, 0]) * np.cos(np.pi * xo[:, 1]), device=dev)
+    ut = torch.tensor(I.sinsin_u(xo), device=dev)
     ap = I.adjoint_params(5)
 
     def loss(th, et):

@@ -134,7 +134,7 @@ def test_gradient_in_data_coefficients_matches_one_solve_per_coefficient():
     s = O.DDELMNN(geo, W, b, theta=0.999)
     ap = I.adjoint_params(seed=5)
     xo = I.observation_points(300, seed=6)
-    u_obs = np.sin(np.pi * xo[:, 0]) * np.cos(np.pi * xo[:, 1])
+    u_obs = I.sinsin_u(xo)
     PhiI = [I.AdjointParams.f_basis(sb.x_I) for sb in geo.subs]
     PhiB = [I.AdjointParams.g_basis(sb.x_B) for sb in geo.subs]
 
