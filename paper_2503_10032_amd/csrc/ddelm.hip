@@ -132,7 +132,7 @@ struct RowSetDev {
 // Local factors and operators in the storage type T of the local solves.
 template <typename T>
 struct LocalBufs {
-  DBuf<T> qrA, tau, Tbuf;              // QR matrices (K_c^i | E_G, Kbar^i | E_flux), tau, block-reflector T
+  DBuf<T> qrA, tau, Tbuf, Tbig;        // QR matrices (K_c^i | E_G, Kbar^i | E_flux), tau, panel and block T
   DBuf<T> Am, CD;                      // A_m^i (n_G x M), Abar^i (n_D x M)
   DBuf<T> QG;                          // Q_G^T (M x n_G) per subdomain
   DBuf<T> Gm, Lm, LTm, Nm, NTm;        // local interface operators
@@ -166,7 +166,7 @@ struct ddelm_ctx_s {
   DBuf<QRDesc> qrdesc;
   std::vector<QRDesc> h_qrdesc;
   int max_ncols = 0;
-  int npanel = 0;
+  int npanel = 0, nblock = 0;
   DBuf<long long> qr_coff;
   DBuf<int> qr_ldc, qr_cn;
   std::vector<long long> h_offAm, h_offCD, h_offQG, h_offG, h_offN, h_offK;
@@ -637,19 +637,37 @@ void factor_impl(ddelm_ctx c) {
     }
   }
   c->mark(1);
-  // ---- blocked Householder QR of all matrices: 16-column panels, WY updates on MFMA
+  // ---- blocked Householder QR of all matrices: 16-column panels updating
+  //      their 64-column block, then one 64-wide block reflector per block
+  //      for the trailing matrix; all products on MFMA
   {
     c->npanel = ceil_div(M, kNB);
+    c->nblock = ceil_div(M, kBB);
     L.Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
-    for (int p = 0; p < c->npanel; ++p) {
-      const int k = p * kNB;
-      launch_qr_panel16<T>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, L.qrA.p, L.tau.p, L.Tbuf.p, k,
-                           p, c->npanel);
-      const int c0 = k + std::min(kNB, M - k);
-      const int ntile = ceil_div(c->max_ncols - c0, kUC);
+    L.Tbig.alloc((size_t)nmat * c->nblock * kBB * kBB);
+    const int nmat8 = ceil_div(nmat, 8) * 8;
+    for (int blk = 0; blk < c->nblock; ++blk) {
+      const int kb = blk * kBB, bw = std::min(kBB, M - kb);
+      const int* cnb = c->arena.put(std::vector<int>(nmat, kb + bw), s);
+      for (int k = kb; k < kb + bw; k += kNB) {
+        const int p = k / kNB;
+        launch_qr_panel16<T>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, L.qrA.p, L.tau.p,
+                             L.Tbuf.p, k, p, c->npanel);
+        const int c0 = k + std::min(kNB, M - k);
+        if (c0 < kb + bw) {
+          k_qr_wy<T><<<dim3(nmat, ceil_div(kb + bw - c0, kUC)), kBlock, 0, s>>>(
+              c->qrdesc.p, L.qrA.p, L.Tbuf.p, k, p, c->npanel, L.qrA.p, c->qr_coff.p, c->qr_ldc.p, cnb, c0, 1);
+          HIPCHK(hipGetLastError());
+        }
+      }
+      k_qr_tmerge<T><<<nmat, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, L.Tbig.p, kb, blk, c->npanel,
+                                             c->nblock);
+      HIPCHK(hipGetLastError());
+      const int c0 = kb + bw;
+      const int ntile = ceil_div(c->max_ncols - c0, kBC);
       if (ntile > 0) {
-        k_qr_wy<T><<<dim3(nmat, ntile), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, k, p, c->npanel, L.qrA.p,
-                                                        c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
+        k_qr_wy64<T><<<nmat8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntile,
+                                                      L.qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
         HIPCHK(hipGetLastError());
       }
     }
@@ -682,8 +700,11 @@ void factor_impl(ddelm_ctx c) {
       const int* dld = c->arena.put(ldx, s);
       const int* dxn = c->arena.put(xn, s);
       const size_t smt = (size_t)M * kTRSMC * sizeof(T);
-      if (smt > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_trsm<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smt));
-      k_trsm<T><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.qrA.p, dxo, dld, dxn, 0);
+      if (smt > 65536)
+        HIPCHK(hipFuncSetAttribute((const void*)k_trsm<T, kTRSMC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)smt));
+      k_trsm<T, kTRSMC><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.qrA.p, dxo,
+                                                                               dld, dxn, 0);
       HIPCHK(hipGetLastError());
     }
   }
@@ -847,10 +868,15 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   auto t0 = std::chrono::steady_clock::now();
   c->mark(5);
   // ---- Q^T f (block reflectors), projections, K^+ f, fluxes
-  for (int p = 0; p < c->npanel; ++p) {
-    k_qr_wy<T><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, p * kNB, p, c->npanel,
-                                                               L.F.p, c->f_off.p, c->f_ld.p, c->f_cn.p, 0, 1);
-    HIPCHK(hipGetLastError());
+  {
+    const int ntile = ceil_div(nrhs, kBC);
+    const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
+    for (int blk = 0; blk < c->nblock; ++blk) {
+      k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
+                                                                 c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
+                                                                 cnR, 0, 1);
+      HIPCHK(hipGetLastError());
+    }
   }
   k_rhs_proj<T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
                                                                    c->offQG_d.p, L.QG.p, c->offm_d.p, c->summ, L.F.p,
@@ -860,7 +886,7 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   {
     const size_t smt = (size_t)M * kTRSMC * sizeof(T);
     const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
-    k_trsm<T><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p,
+    k_trsm<T, kTRSMC><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p,
                                                                    cnM, 0);
     HIPCHK(hipGetLastError());
 
@@ -1064,14 +1090,16 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
                                           c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
   HIPCHK(hipGetLastError());
   const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
-  k_trsm<T><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, (size_t)M * kTRSMC * sizeof(T), s>>>(
+  k_trsm<T, kTRSMC><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, (size_t)M * kTRSMC * sizeof(T), s>>>(
       c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p, cnM, 1);
   k_adj_alpha<T><<<gl, kBlock, smG, s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offQG_d.p, L.QG.p,
                                          c->adj_pbar.p, sumG, c->offm_d.p, c->summ, L.F.p);
   HIPCHK(hipGetLastError());
-  for (int p = c->npanel - 1; p >= 0; --p) {
-    k_qr_wy<T><<<dim3(N, ceil_div(nrhs, kUC)), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, p * kNB, p, c->npanel,
-                                                               L.F.p, c->f_off.p, c->f_ld.p, cnM, 0, 0);
+  for (int blk = c->nblock - 1; blk >= 0; --blk) {
+    const int ntile = ceil_div(nrhs, kBC);
+    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
+                                                               c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
+                                                               cnM, 0, 0);
     HIPCHK(hipGetLastError());
   }
   k_adj_fout<T><<<gl, kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p, c->summ, L.F.p,

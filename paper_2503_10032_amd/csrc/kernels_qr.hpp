@@ -279,3 +279,250 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
 }
 
 }  // namespace ddelm
+
+namespace ddelm {
+
+// ---------------------------------------------------------------- 64-column blocks
+//
+// Four 16-column panels make one block.  Inside a block each panel's
+// reflector is applied only to the block's remaining columns; the four
+// panel T factors are then merged into the T of the whole block,
+//   Q1 Q2 = I - [V1 V2] [[T1, -T1 V1^T V2 T2], [0, T2]] [V1 V2]^T,
+// and the block reflector updates the trailing matrix once per 64 columns,
+// which streams it a quarter as often as panel-by-panel updates.
+constexpr int kBB = 64;    // block width
+constexpr int kBC = 64;    // columns of C per workgroup in the block update
+
+// T of block blk (columns kb .. kb+bw-1) from the panel T factors and V^T V.
+// One workgroup per matrix.  Tbig[b][blk] is 64 x 64 row-major, zero beyond bw.
+// The Gram matrix and the merge are formed in float64 whatever T is (a
+// float32 Gram summed over ~10^3 rows would add rounding that the
+// panel-by-panel application does not have).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                      const T* __restrict__ Tbuf, T* __restrict__ Tbig, int kb,
+                                                      int blk, int npanel, int nblock) {
+  const QRDesc d = desc[blockIdx.x];
+  if (kb >= d.nrefl) return;
+  const int bw = min(kBB, d.nrefl - kb);
+  const int npb = (bw + kNB - 1) / kNB;
+  __shared__ double Ts[kBB][kBB + 1];
+  __shared__ double Gs[kBB][kBB + 1];
+  __shared__ double Vc[64][kBB + 1];
+  const T* Am = A + d.off;
+  for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Ts[e / kBB][e % kBB] = 0.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < npb * kNB * kNB; e += kBlock) {
+    const int pp = e / (kNB * kNB), i = (e / kNB) % kNB, j = e % kNB;
+    const int p = kb / kNB + pp;
+    Ts[pp * kNB + i][pp * kNB + j] = (double)Tbuf[((long long)blockIdx.x * npanel + p) * kNB * kNB + i * kNB + j];
+  }
+  // G = V^T V over the rows of the block's reflectors on f64 MFMA: wave wv
+  // forms rows 16 wv .. 16 wv + 15 of G (4 tiles of 16 columns)
+  typedef Mfma<double>::v4 v4d;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4d{0, 0, 0, 0};
+  double vv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, kb + e % 64, e / 64) : 0.0;
+  }
+  for (int r0 = kb; r0 < d.m; r0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      Vc[e % 64][e / 64] = vv[u];
+    }
+    __syncthreads();
+    if (r0 + 64 < d.m) {       // next chunk's loads in flight during this chunk's products
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, r0 + 64 + e % 64, e / 64) : 0.0;
+      }
+    }
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+      const int rr = ks * 4 + (lane >> 4);
+      const double av = Vc[rr][16 * wv + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = Mfma<double>::mma(av, Vc[rr][16 * t + (lane & 15)], acc[t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Gs[16 * wv + Mfma<double>::drow(lane, v)][16 * t + (lane & 15)] = acc[t][v];
+  __syncthreads();
+  // merge: T(0:n0, n0:n0+16) = -T(0:n0, 0:n0) G(0:n0, n0:n0+16) T(n0:n0+16, n0:n0+16)
+  for (int q = 1; q < npb; ++q) {
+    const int n0 = q * kNB;
+    for (int e = threadIdx.x; e < n0 * kNB; e += kBlock) {
+      const int i = e / kNB, c = e % kNB;
+      double y = 0.0;
+      for (int l = i; l < n0; ++l) y += Ts[i][l] * Gs[l][n0 + c];
+      Vc[i][c] = y;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n0 * kNB; e += kBlock) {
+      const int i = e / kNB, c = e % kNB;
+      double z = 0.0;
+      for (int l = 0; l <= c; ++l) z += Vc[i][l] * Ts[n0 + l][n0 + c];
+      Ts[i][n0 + c] = -z;
+    }
+    __syncthreads();
+  }
+  T* Tout = Tbig + ((long long)blockIdx.x * nblock + blk) * kBB * kBB;
+  for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Tout[e] = (T)Ts[e / kBB][e % kBB];
+}
+
+// Apply the block reflector of block blk (columns kb .. kb+bw-1) of every
+// matrix to columns [c0, cn[b]) of C + coff[b] (leading dimension ldc[b]):
+// transT = 1 applies Q^T = I - V T^T V^T, transT = 0 applies Q = I - V T V^T.
+// 1-D grid over (matrix, 64-column tile), arranged so that all tiles of one
+// matrix land on the same XCD (workgroup id mod 8) and share its L2 for V.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                    const T* __restrict__ Tbig, int kb, int blk, int nblock,
+                                                    int nmat, int ntile, T* __restrict__ C,
+                                                    const long long* __restrict__ coff, const int* __restrict__ ldc,
+                                                    const int* __restrict__ cn, int c0, int transT) {
+  typedef typename Mfma<T>::v4 v4;
+  const int id = blockIdx.x;
+  const int b = (id % 8) + 8 * ((id / 8) / ntile);
+  const int tile = (id / 8) % ntile;
+  if (b >= nmat) return;
+  const QRDesc d = desc[b];
+  if (kb >= d.nrefl) return;
+  const int bw = min(kBB, d.nrefl - kb);
+  const int cbeg = c0 + tile * kBC;
+  const int ctot = cn[b];
+  if (cbeg >= ctot) return;
+  const int ncol = min(kBC, ctot - cbeg);
+  const int L = ldc[b];
+  const T* Am = A + d.off;
+  T* Cm = C + coff[b];
+  __shared__ T Vs[64][kBB + 1];      // V chunk, later T
+  __shared__ T Cs[64][kBC + 1];      // C chunk, later W
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // ---- W = V^T C: wave wv forms rows 16 wv .. 16 wv + 15 of W (4 tiles of 16 columns)
+  v4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4{0, 0, 0, 0};
+  T vv[16], cc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    const int row = kb + e % 64, c = e / 64;
+    vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+    cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+  }
+  for (int r0 = kb; r0 < d.m; r0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      Vs[e % 64][e / 64] = vv[u];
+      Cs[e % 64][e / 64] = cc[u];
+    }
+    __syncthreads();
+    if (r0 + 64 < d.m) {       // next chunk's loads in flight during this chunk's products
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        const int row = r0 + 64 + e % 64, c = e / 64;
+        vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+        cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+      }
+    }
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+      const int rr = ks * 4 + (lane >> 4);
+      const T av = Vs[rr][16 * wv + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mma(av, Cs[rr][16 * t + (lane & 15)], acc[t]);
+    }
+    __syncthreads();
+  }
+  // W into Cs, T into Vs
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * wv + Mfma<T>::drow(lane, v);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) Cs[i][16 * t + (lane & 15)] = acc[t][v];
+  }
+  const T* Tin = Tbig + ((long long)b * nblock + blk) * kBB * kBB;
+  for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Vs[e / kBB][e % kBB] = Tin[e];
+  __syncthreads();
+  // ---- W <- -T^T W (Q^T) or -T W (Q)
+  T wn[kBB * kBC / kBlock];
+#pragma unroll
+  for (int u = 0; u < kBB * kBC / kBlock; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    const int i = e / kBC, c = e % kBC;
+    T s = T(0);
+    if (transT) {
+      for (int ip = 0; ip <= i; ++ip) s += Vs[ip][i] * Cs[ip][c];
+    } else {
+      for (int ip = i; ip < kBB; ++ip) s += Vs[i][ip] * Cs[ip][c];
+    }
+    wn[u] = -s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kBB * kBC / kBlock; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    Cs[e / kBC][e % kBC] = wn[u];
+  }
+  __syncthreads();
+  // ---- C <- C + V W for 16-row blocks (rows along the lanes)
+  // loads of the next 16-row block are issued before the products of this one
+  T cn_[16], bn_[16];
+  auto load_rows = [&](int rb) {
+    const int row = rb + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * t + Mfma<T>::drow(lane, v);
+        cn_[4 * t + v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+      }
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int jj = ks * 4 + (lane >> 4);
+      bn_[ks] = jj < bw ? v_elem(Am, d.ld, d.m, kb, row, jj) : T(0);
+    }
+  };
+  int rb = kb + wv * 16;
+  if (rb < d.m) load_rows(rb);
+  for (; rb < d.m; rb += kWaves * 16) {
+    const int row = rb + (lane & 15);
+    v4 cacc[4];
+    T bv[16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cacc[t][v] = cn_[4 * t + v];
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) bv[ks] = bn_[ks];
+    if (rb + kWaves * 16 < d.m) load_rows(rb + kWaves * 16);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int jj = ks * 4 + (lane >> 4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cacc[t] = Mfma<T>::mma(Cs[jj][16 * t + (lane & 15)], bv[ks], cacc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * t + Mfma<T>::drow(lane, v);
+        if (row < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + row] = cacc[t][v];
+      }
+  }
+}
+
+}  // namespace ddelm

@@ -235,9 +235,10 @@ __global__ void __launch_bounds__(kBlock) k_qr_apply(const QRDesc* __restrict__ 
 // triangle R of matrix b (R at A + desc.off, leading dimension desc.ld,
 // n = desc.nrefl), X = n x nc columns at X + xoff[b], leading dimension
 // ldx[b].  Up to kTRSMC columns per workgroup, staged in LDS.
-constexpr int kTRSMC = 8;
+constexpr int kTRSMC = 8;    // right-hand-side columns per workgroup
+constexpr int kTRB = 16;     // rows per block of the substitution
 
-template <typename T>
+template <typename T, int kTRSMC>
 __global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                  T* __restrict__ X, const long long* __restrict__ xoff,
                                                  const int* __restrict__ ldx, const int* __restrict__ xn,
@@ -258,19 +259,60 @@ __global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc
     xs[e] = c < nc ? Xm[(long long)(cbeg + c) * L + r] : T(0);
   }
   __syncthreads();
-  for (int s = 0; s < n; ++s) {
-    const int k = trans ? s : (n - 1 - s);
-    if (threadIdx.x < kTRSMC) xs[k * kTRSMC + threadIdx.x] /= R[(long long)k * d.ld + k];
+  // Substitution by blocks of kTRB rows: the diagonal block (staged in LDS)
+  // is solved by kTRSMC threads of the first wave, one column each, then all
+  // threads update the rows not yet solved; three barriers per block instead
+  // of two per row.
+  __shared__ T Rd[kTRB][kTRB + 1];
+  const int nblk = (n + kTRB - 1) / kTRB;
+  for (int s = 0; s < nblk; ++s) {
+    const int bk = trans ? s : nblk - 1 - s;
+    const int r0 = bk * kTRB, r1 = min(n, r0 + kTRB);
+    for (int e = threadIdx.x; e < kTRB * kTRB; e += kBlock) {
+      const int i = e % kTRB, j = e / kTRB;             // Rd[i][j] = R(r0 + i, r0 + j)
+      Rd[i][j] = (r0 + i < r1 && r0 + j < r1) ? R[(long long)(r0 + j) * d.ld + r0 + i] : T(0);
+    }
     __syncthreads();
-    if (!trans) {
-      for (int e = threadIdx.x; e < k * kTRSMC; e += kBlock) {
-        const int r = e / kTRSMC, c = e % kTRSMC;
-        xs[e] -= R[(long long)k * d.ld + r] * xs[k * kTRSMC + c];
+    if (threadIdx.x < kTRSMC) {
+      const int c = threadIdx.x;
+      if (!trans) {
+        for (int k = r1 - 1; k >= r0; --k) {
+          T v = xs[k * kTRSMC + c];
+          for (int j = k + 1; j < r1; ++j) v -= Rd[k - r0][j - r0] * xs[j * kTRSMC + c];
+          xs[k * kTRSMC + c] = v / Rd[k - r0][k - r0];
+        }
+      } else {
+        for (int k = r0; k < r1; ++k) {
+          T v = xs[k * kTRSMC + c];
+          for (int j = r0; j < k; ++j) v -= Rd[j - r0][k - r0] * xs[j * kTRSMC + c];
+          xs[k * kTRSMC + c] = v / Rd[k - r0][k - r0];
+        }
       }
-    } else {
-      for (int e = (k + 1) * kTRSMC + threadIdx.x; e < n * kTRSMC; e += kBlock) {
+    }
+    __syncthreads();
+    if (!trans) {     // rows above the block: x_r -= R(r, j) x_j
+      for (int e = threadIdx.x; e < r0 * kTRSMC; e += kBlock) {
         const int r = e / kTRSMC, c = e % kTRSMC;
-        xs[e] -= R[(long long)r * d.ld + k] * xs[k * kTRSMC + c];
+        T rv[kTRB];
+#pragma unroll
+        for (int j = 0; j < kTRB; ++j) rv[j] = r0 + j < r1 ? R[(long long)(r0 + j) * d.ld + r] : T(0);
+        T acc = xs[e];
+#pragma unroll
+        for (int j = 0; j < kTRB; ++j)
+          if (r0 + j < r1) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];
+        xs[e] = acc;
+      }
+    } else {          // rows below the block: x_r -= R(j, r) x_j
+      for (int e = r1 * kTRSMC + threadIdx.x; e < n * kTRSMC; e += kBlock) {
+        const int r = e / kTRSMC, c = e % kTRSMC;
+        T rv[kTRB];
+#pragma unroll
+        for (int j = 0; j < kTRB; ++j) rv[j] = r0 + j < r1 ? R[(long long)r * d.ld + r0 + j] : T(0);
+        T acc = xs[e];
+#pragma unroll
+        for (int j = 0; j < kTRB; ++j)
+          if (r0 + j < r1) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];
+        xs[e] = acc;
       }
     }
     __syncthreads();
