@@ -143,6 +143,8 @@ struct LocalBufs {
 
 struct ddelm_ctx_s {
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;          // second stream of the QR look-ahead (created on first use)
+  std::vector<hipEvent_t> sync_ev;     // ordering events between the two streams
   ddelm_options opt;
   Geometry geo;
   int N = 0, M = 0, n_int = 0;
@@ -220,6 +222,25 @@ struct ddelm_ctx_s {
   ~ddelm_ctx_s() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : sync_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+  }
+  // event k of the cross-stream ordering pool (timing disabled)
+  hipEvent_t sev(size_t k) {
+    while (sync_ev.size() <= k) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      sync_ev.push_back(e);
+    }
+    return sync_ev[k];
+  }
+  hipStream_t side_stream() {
+    if (!side) HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    return side;
   }
 
   void fail(ddelm_status st, const std::string& m) { throw StatusError{st, m}; }
@@ -645,7 +666,20 @@ void factor_impl(ddelm_ctx c) {
     c->nblock = ceil_div(M, kBB);
     L.Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
     L.Tbig.alloc((size_t)nmat * c->nblock * kBB * kBB);
+    // Look-ahead: after block b is factored, its block reflector is applied
+    // first to the columns of block b+1 (on the main stream, which then
+    // factors block b+1) and to the columns beyond on a second stream, so
+    // the panels of block b+1 run beside the bulk of block b's update.
+    // Events: T[b] (block b factored, main), R[b] (block b's far update done,
+    // side).  The near update of block b waits for R[b-1], which updated the
+    // same columns before it; the two updates of one block touch disjoint
+    // columns and read only that block's reflectors and T factor.
     const int nmat8 = ceil_div(nmat, 8) * 8;
+    hipStream_t s2 = c->side_stream();
+    HIPCHK(hipEventRecord(c->sev(0), s));
+    HIPCHK(hipStreamWaitEvent(s2, c->sev(0), 0));
+    auto evT = [&](int b) { return c->sev(1 + 2 * (size_t)b); };
+    auto evR = [&](int b) { return c->sev(2 + 2 * (size_t)b); };
     for (int blk = 0; blk < c->nblock; ++blk) {
       const int kb = blk * kBB, bw = std::min(kBB, M - kb);
       const int* cnb = c->arena.put(std::vector<int>(nmat, kb + bw), s);
@@ -663,14 +697,30 @@ void factor_impl(ddelm_ctx c) {
       k_qr_tmerge<T><<<nmat, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, L.Tbig.p, kb, blk, c->npanel,
                                              c->nblock);
       HIPCHK(hipGetLastError());
-      const int c0 = kb + bw;
-      const int ntile = ceil_div(c->max_ncols - c0, kBC);
-      if (ntile > 0) {
-        k_qr_wy64<T><<<nmat8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntile,
-                                                      L.qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c0, 1);
+      HIPCHK(hipEventRecord(evT(blk), s));
+      const int c0 = kb + bw;                                    // first trailing column
+      const int c1 = std::min(c0 + kBB, M);                      // end of the next block
+      // near update: the next block's columns, on the main stream
+      if (c1 > c0) {
+        if (blk > 0) HIPCHK(hipStreamWaitEvent(s, evR(blk - 1), 0));
+        const int* cnn = c->arena.put(std::vector<int>(nmat, c1), s);
+        const int ntn = ceil_div(c1 - c0, kBC);
+        k_qr_wy64<T><<<nmat8 * ntn, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntn,
+                                                    L.qrA.p, c->qr_coff.p, c->qr_ldc.p, cnn, c0, 1);
         HIPCHK(hipGetLastError());
       }
+      // far update: every column after the next block (and the appended unit
+      // columns), on the side stream
+      const int ntf = ceil_div(c->max_ncols - c1, kBC);
+      HIPCHK(hipStreamWaitEvent(s2, evT(blk), 0));
+      if (ntf > 0) {
+        k_qr_wy64<T><<<nmat8 * ntf, kBlock, 0, s2>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntf,
+                                                     L.qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c1, 1);
+        HIPCHK(hipGetLastError());
+      }
+      HIPCHK(hipEventRecord(evR(blk), s2));
     }
+    HIPCHK(hipStreamWaitEvent(s, evR(c->nblock - 1), 0));
   }
   c->mark(2);
   // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T and Xbar = Rbar^{-1} Qbar_D^T in place
