@@ -44,6 +44,12 @@
  *   - Inputs are borrowed for the duration of the call; ddelm_setup copies
  *     what it keeps.  Outputs are written into caller-owned buffers.  The
  *     context owns its factors and workspaces until ddelm_destroy.
+ *   - Device memory of contexts comes from a pool private to the library
+ *     (one per device, stream-ordered on the context's stream); memory freed
+ *     by ddelm_destroy stays in the pool for the next context, and so do the
+ *     context's events, second stream and pinned staging buffer.
+ *     ddelm_release_cached_memory hands the idle part back.  Destroy a
+ *     context before the stream it was set up on.
  *   - Work is ordered on the stream given to ddelm_setup (a hipStream_t
  *     passed as void*; NULL = the default stream).  Calls that return
  *     statistics synchronise that stream.  A context is not thread-safe.
@@ -253,7 +259,16 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx ctx, int which, int sub, double* o
 ddelm_status ddelm_get_phase_times(ddelm_ctx ctx, double* ms);
 
 const char* ddelm_last_error(ddelm_ctx ctx);
+/* Synchronises the context's stream, then frees the context; its memory
+ * returns to the library's pool (see the conventions above).  NULL is a
+ * no-op. */
 void ddelm_destroy(ddelm_ctx ctx);
+
+/* Returns the library's idle device memory, events, streams and pinned
+ * staging buffers (those of destroyed contexts) to the runtime.  Memory of
+ * live contexts is not touched; allocations queued but not yet executed
+ * stay with the pool until their stream reaches them.  Thread-safe. */
+ddelm_status ddelm_release_cached_memory(void);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,7 @@ SIGNATURES = {
     "ddelm_get_phase_times": (ctypes.c_int, [ctypes.c_void_p, c_double_p]),
     "ddelm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "ddelm_destroy": (None, [ctypes.c_void_p]),
+    "ddelm_release_cached_memory": (ctypes.c_int, []),
 }
 
 _lib = None

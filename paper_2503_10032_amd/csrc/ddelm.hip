@@ -8,6 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -42,19 +45,156 @@ struct StatusError {
   std::string msg;
 };
 
+// ---- process-wide resources kept between contexts
+// Device memory freed by a destroyed context (whose stream has drained) is
+// kept in an idle list per device and handed to later allocations of a
+// similar size, so a context set up after another one of similar size
+// allocates nothing from the driver.  Memory freed while its context is
+// alive goes to that context's own list: only the same context reuses it,
+// and since all of a context's work is ordered on its stream (the side
+// stream of the QR joins it before anything after the QR is queued), a
+// block handed out again is only touched by work queued after every earlier
+// use.  Side streams, events and pinned staging buffers of destroyed
+// contexts are kept idle as well.  ddelm_release_cached_memory returns the
+// idle part to the runtime; nothing is released at exit.
+struct BlockList {
+  std::multimap<size_t, void*> free;          // capacity in bytes -> block
+  // smallest block of at least `bytes` that does not waste much of itself
+  void* take(size_t bytes, size_t& cap) {
+    auto it = free.lower_bound(bytes);
+    if (it == free.end() || it->first > 2 * bytes + (size_t(1) << 20)) return nullptr;
+    cap = it->first;
+    void* p = it->second;
+    free.erase(it);
+    return p;
+  }
+  void put(void* p, size_t cap) { free.emplace(cap, p); }
+};
+
+struct Resources {
+  std::mutex mu;
+  std::vector<BlockList> idle;                          // per device
+  std::vector<std::pair<int, hipStream_t>> streams;     // idle side streams (device, stream)
+  std::vector<std::pair<int, hipEvent_t>> events_t;     // idle events with timing
+  std::vector<std::pair<int, hipEvent_t>> events_n;     // idle events without timing
+  struct Staging { int dev; size_t cap; char* d; char* h; };
+  std::vector<Staging> staging;                         // idle descriptor arenas
+  BlockList& dev_list(int dev) {
+    if ((int)idle.size() <= dev) idle.resize(dev + 1);
+    return idle[dev];
+  }
+};
+Resources& res() {
+  static Resources* r = new Resources();
+  return *r;
+}
+
+hipEvent_t take_event(int dev, bool timing) {
+  {
+    Resources& R = res();
+    std::lock_guard<std::mutex> lk(R.mu);
+    auto& v = timing ? R.events_t : R.events_n;
+    for (size_t k = v.size(); k-- > 0;)
+      if (v[k].first == dev) {
+        hipEvent_t e = v[k].second;
+        v.erase(v.begin() + k);
+        return e;
+      }
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreateWithFlags(&e, timing ? hipEventDefault : hipEventDisableTiming));
+  return e;
+}
+void give_event(int dev, bool timing, hipEvent_t e) {
+  Resources& R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  (timing ? R.events_t : R.events_n).push_back({dev, e});
+}
+hipStream_t take_stream(int dev) {
+  {
+    Resources& R = res();
+    std::lock_guard<std::mutex> lk(R.mu);
+    for (size_t k = R.streams.size(); k-- > 0;)
+      if (R.streams[k].first == dev) {
+        hipStream_t st = R.streams[k].second;
+        R.streams.erase(R.streams.begin() + k);
+        return st;
+      }
+  }
+  hipStream_t st;
+  HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));   // default priority
+  return st;
+}
+
+// free list of the context whose API call is running on this thread
+struct CtxBlocks {
+  int dev = 0;
+  BlockList list;
+};
+thread_local CtxBlocks* tl_blocks = nullptr;
+struct BlocksScope {
+  CtxBlocks* prev;
+  explicit BlocksScope(CtxBlocks* b) : prev(tl_blocks) { tl_blocks = b; }
+  ~BlocksScope() { tl_blocks = prev; }
+};
+
+void release_idle_memory_locked(Resources& R) {
+  for (BlockList& l : R.idle) {
+    for (auto& kv : l.free) (void)hipFree(kv.second);
+    l.free.clear();
+  }
+}
+
+void* dev_alloc(size_t bytes, size_t& cap) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  bytes = (bytes + 255) & ~size_t(255);
+  if (tl_blocks && tl_blocks->dev == dev)
+    if (void* p = tl_blocks->list.take(bytes, cap)) return p;
+  Resources& R = res();
+  {
+    std::lock_guard<std::mutex> lk(R.mu);
+    if (void* p = R.dev_list(dev).take(bytes, cap)) return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(R.mu);
+      release_idle_memory_locked(R);
+    }
+    e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError{DDELM_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  cap = bytes;
+  return p;
+}
+
+void dev_free(void* p, size_t cap) {
+  if (!p) return;
+  if (tl_blocks) tl_blocks->list.put(p, cap);
+  else (void)hipFree(p);      // outside any context call: free for good (synchronises)
+}
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  size_t cap = 0;     // bytes of the block behind p
   void alloc(size_t count) {
     free();
     n = count;
     if (count == 0) return;
-    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
-    if (e != hipSuccess) {
+    try {
+      p = (T*)dev_alloc(count * sizeof(T), cap);
+    } catch (...) {
       p = nullptr;
       n = 0;
-      throw StatusError{DDELM_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+      throw;
     }
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
@@ -65,9 +205,10 @@ struct DBuf {
     if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s));
   }
   void free() {
-    if (p) (void)hipFree(p);
+    dev_free(p, cap);
     p = nullptr;
     n = 0;
+    cap = 0;
   }
   ~DBuf() { free(); }
 };
@@ -79,16 +220,42 @@ struct Arena {
   char* dev = nullptr;
   char* host = nullptr;
   size_t cap = 0, used = 0;
+  int device = 0;
   void ensure(size_t c) {
     if (c <= cap) return;
     release();
+    HIPCHK(hipGetDevice(&device));
+    {
+      // an idle arena of a destroyed context, if one is large enough
+      Resources& R = res();
+      std::lock_guard<std::mutex> lk(R.mu);
+      for (size_t k = 0; k < R.staging.size(); ++k) {
+        const Resources::Staging& a = R.staging[k];
+        if (a.dev == device && a.cap >= c) {
+          dev = a.d; host = a.h; cap = a.cap;
+          R.staging.erase(R.staging.begin() + k);
+          return;
+        }
+      }
+    }
     HIPCHK(hipMalloc((void**)&dev, c));
     HIPCHK(hipHostMalloc((void**)&host, c, hipHostMallocDefault));
     cap = c;
   }
+  // the copies out of the staging buffer may still be queued: free for good
   void release() {
     if (dev) (void)hipFree(dev);
     if (host) (void)hipHostFree(host);
+    dev = host = nullptr;
+    cap = used = 0;
+  }
+  // after the context's stream has drained: keep the buffers for the next context
+  void retire() {
+    if (dev) {
+      Resources& R = res();
+      std::lock_guard<std::mutex> lk(R.mu);
+      R.staging.push_back({device, cap, dev, host});
+    }
     dev = host = nullptr;
     cap = used = 0;
   }
@@ -143,6 +310,7 @@ struct LocalBufs {
 
 struct ddelm_ctx_s {
   hipStream_t stream = nullptr;
+  CtxBlocks* blocks = new CtxBlocks();   // device memory freed while the context lives
   hipStream_t side = nullptr;          // second stream of the QR look-ahead (created on first use)
   std::vector<hipEvent_t> sync_ev;     // ordering events between the two streams
   ddelm_options opt;
@@ -211,7 +379,7 @@ struct ddelm_ctx_s {
   hipEvent_t ev[10] = {};
   double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   void mark(int k) {
-    if (!ev[k]) HIPCHK(hipEventCreate(&ev[k]));
+    if (!ev[k]) ev[k] = take_event(device, true);
     HIPCHK(hipEventRecord(ev[k], stream));
   }
   double span(int a, int b) {
@@ -219,27 +387,30 @@ struct ddelm_ctx_s {
     HIPCHK(hipEventElapsedTime(&ms, ev[a], ev[b]));
     return (double)ms;
   }
+  // Called by ddelm_destroy once the context's stream has drained: the side
+  // stream is drained here, then the buffers' memory goes to the context's
+  // free list (member destructors; ddelm_destroy moves it to the idle list)
+  // and the staging arena, events and side stream to the idle lists.
   ~ddelm_ctx_s() {
     for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
+      if (e) give_event(device, true, e);
     for (auto& e : sync_ev)
-      if (e) (void)hipEventDestroy(e);
+      if (e) give_event(device, false, e);
     if (side) {
       (void)hipStreamSynchronize(side);
-      (void)hipStreamDestroy(side);
+      Resources& R = res();
+      std::lock_guard<std::mutex> lk(R.mu);
+      R.streams.push_back({device, side});
     }
+    arena.retire();
   }
   // event k of the cross-stream ordering pool (timing disabled)
   hipEvent_t sev(size_t k) {
-    while (sync_ev.size() <= k) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      sync_ev.push_back(e);
-    }
+    while (sync_ev.size() <= k) sync_ev.push_back(take_event(device, false));
     return sync_ev[k];
   }
   hipStream_t side_stream() {
-    if (!side) HIPCHK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (!side) side = take_stream(device);
     return side;
   }
 
@@ -255,6 +426,7 @@ namespace {
 
 template <typename F>
 ddelm_status run_guarded(ddelm_ctx c, F&& fn) {
+  BlocksScope scope(c ? c->blocks : nullptr);
   try {
     fn();
     return DDELM_OK;
@@ -1303,8 +1475,8 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
   if (!out || !prob) return DDELM_E_ARG;
   *out = nullptr;
   ddelm_ctx c = new ddelm_ctx_s();
+  c->stream = (hipStream_t)stream;
   ddelm_status st = run_guarded(c, [&]() {
-    c->stream = (hipStream_t)stream;
     if (opt) c->opt = *opt;
     else ddelm_default_options(&c->opt);
     const ddelm_options& o = c->opt;
@@ -1324,6 +1496,7 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     if (!prob->edge_s || !prob->x_int || !prob->W || !prob->b) c->fail(DDELM_E_ARG, "null array in problem");
     if (prob->n_extra < 0 || (prob->n_extra > 0 && !prob->extra_s)) c->fail(DDELM_E_ARG, "bad extra_s");
     HIPCHK(hipGetDevice(&c->device));
+    c->blocks->dev = c->device;
     HIPCHK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     const int N = prob->nx * prob->ny;
     if (prob->nx < 1 || prob->ny < 1 || (long long)prob->nx * prob->ny > (1 << 20))
@@ -1744,7 +1917,35 @@ void ddelm_destroy(ddelm_ctx c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  delete c;
+  CtxBlocks* blocks = c->blocks;
+  {
+    BlocksScope scope(blocks);     // the buffers' destructors put their memory on this list
+    delete c;                      // (drains the side stream first)
+  }
+  Resources& R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  BlockList& l = R.dev_list(blocks->dev);
+  for (auto& kv : blocks->list.free) l.put(kv.second, kv.first);
+  delete blocks;
+}
+
+ddelm_status ddelm_release_cached_memory(void) {
+  Resources& R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  ddelm_status st = DDELM_OK;
+  release_idle_memory_locked(R);
+  for (auto& e : R.events_t) (void)hipEventDestroy(e.second);
+  for (auto& e : R.events_n) (void)hipEventDestroy(e.second);
+  for (auto& x : R.streams) (void)hipStreamDestroy(x.second);
+  for (auto& a : R.staging) {
+    (void)hipFree(a.d);
+    (void)hipHostFree(a.h);
+  }
+  R.events_t.clear();
+  R.events_n.clear();
+  R.streams.clear();
+  R.staging.clear();
+  return st;
 }
 
 }  // extern "C"

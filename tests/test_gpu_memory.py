@@ -1,0 +1,96 @@
+"""Contexts share the library's device memory pool, events, side streams and
+staging buffers: memory freed by one destroyed context is handed to the next.
+These tests check that reuse changes no result: a context set up after
+others of different sizes (and after the idle memory has been released)
+returns the same numbers, two contexts alive at once on two streams give the
+same results as when run alone, and the results still match the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import ddelm_oracle as O
+from paper_2503_10032_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(nx, ny, M, n_int, p, seed):
+    w = I.Workload("pool", nx, ny, M, 2.0, seed, n_int, p, tol=1e-12)
+    W, b = I.hidden_params(w.N, M, 2, 2.0, seed)
+    return w, W, b, I.interior_points(w)
+
+
+def _run(case, stream=None):
+    torch = _torch()
+    from paper_2503_10032_amd import DDELMSolver
+    w, W, b, xi = case
+    ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.device(0)
+    with ctx:
+        s = DDELMSolver(w.nx, w.ny, w.M, W, b, xi, I.edge_params(w.p), I.extra_boundary_params(w), tol=1e-12)
+        s.factor()
+        xB = s.boundary_points().cpu().numpy()
+        out = s.solve(I.sinsin_f(xi)[None], I.sinsin_u(xB)[None])
+        X = I.eval_grid(w)
+        u = s.evaluate(out["coef"], X)[0]
+        res = (u.cpu().numpy(), out["mu_dl"][0].cpu().numpy(), out["stats"]["iters"])
+        s.close()
+    return res
+
+
+A = (3, 3, 48, 8, 10, 7)
+B = (5, 4, 96, 12, 14, 8)
+
+
+def test_results_unchanged_by_reused_memory():
+    first = _run(_case(*A))
+    _run(_case(*B))                 # a larger context frees its memory into the pool
+    again = _run(_case(*A))         # then a smaller one reuses it
+    from paper_2503_10032_amd import release_cached_memory
+    release_cached_memory()
+    fresh = _run(_case(*A))
+    for r in (again, fresh):
+        assert r[2] == first[2]
+        np.testing.assert_allclose(r[0], first[0], rtol=0, atol=1e-13 * np.abs(first[0]).max())
+        np.testing.assert_allclose(r[1], first[1], rtol=0, atol=1e-13 * np.abs(first[1]).max())
+    # and against the oracle
+    w, W, b, xi = _case(*A)
+    geo = O.Geometry2D(w.nx, w.ny, I.edge_params(w.p), I.extra_boundary_params(w), xi)
+    ref = O.DDELMNN(geo, W, b).solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-12)
+    u_ref = O.evaluate(geo, W, b, ref["c"], I.eval_grid(w))
+    assert np.linalg.norm(first[0] - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+
+
+def test_two_live_contexts_on_two_streams():
+    torch = _torch()
+    from paper_2503_10032_amd import DDELMSolver
+    alone = [_run(_case(*A)), _run(_case(*B))]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]          # default priority
+    solvers, outs = [], []
+    for case, st in zip((_case(*A), _case(*B)), streams):
+        w, W, b, xi = case
+        with torch.cuda.stream(st):
+            s = DDELMSolver(w.nx, w.ny, w.M, W, b, xi, I.edge_params(w.p), I.extra_boundary_params(w), tol=1e-12)
+        solvers.append((s, case, st))
+    for s, _, st in solvers:          # both factorisations queued before either solve
+        with torch.cuda.stream(st):
+            s.factor()
+    for s, case, st in solvers:
+        w, W, b, xi = case
+        with torch.cuda.stream(st):
+            xB = s.boundary_points().cpu().numpy()
+            out = s.solve(I.sinsin_f(xi)[None], I.sinsin_u(xB)[None])
+            u = s.evaluate(out["coef"], I.eval_grid(w))[0]
+            outs.append((u.cpu().numpy(), out["mu_dl"][0].cpu().numpy(), out["stats"]["iters"]))
+    for s, _, _ in solvers:
+        s.close()
+    for got, ref in zip(outs, alone):
+        assert got[2] == ref[2]
+        np.testing.assert_allclose(got[0], ref[0], rtol=0, atol=1e-13 * np.abs(ref[0]).max())
+        np.testing.assert_allclose(got[1], ref[1], rtol=0, atol=1e-13 * np.abs(ref[1]).max())
