@@ -288,11 +288,28 @@ struct RowSetDev {
   int lead = 0;
   DBuf<int> row0, ptr;
   DBuf<Term> terms;
+  // rows with more than kLongTerms terms: (subdomain, local row) pairs by
+  // subdomain; first[i] = first pair of subdomain i
+  std::vector<int> h_long, h_long_first;
+  DBuf<int> long_rows;
   void upload(const RowSet& r, hipStream_t s) {
     lead = r.lead;
     row0.upload(r.row0, s);
     ptr.upload(r.ptr, s);
     terms.upload(r.terms, s);
+    const int N = (int)r.row0.size() - 1;
+    h_long.clear();
+    h_long_first.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      h_long_first[i] = (int)h_long.size() / 2;
+      for (int row = r.row0[i]; row < r.row0[i + 1]; ++row)
+        if (r.ptr[row + 1] - r.ptr[row] > kLongTerms) {
+          h_long.push_back(i);
+          h_long.push_back(r.lead + row - r.row0[i]);
+        }
+    }
+    h_long_first[N] = (int)h_long.size() / 2;
+    long_rows.upload(h_long, s);
   }
 };
 
@@ -522,6 +539,11 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, c
   dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
   k_features<T><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
+  const int l0 = rs.h_long_first[sub0], l1 = rs.h_long_first[sub0 + nsub];
+  if (l1 > l0) {
+    k_features_long<T><<<dim3(l1 - l0, ceil_div(c->M, 4)), kBlock, 0, c->stream>>>(a, rs.long_rows.p + 2 * l0, out);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 template <typename T>

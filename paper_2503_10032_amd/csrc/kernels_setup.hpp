@@ -29,6 +29,11 @@ struct FeatArgs {
   int sub0;              // first subdomain of this launch
 };
 
+// Rows with more terms than this (the mean-flux rows at the corners, 2(p-1)
+// terms) are left to k_features_long, which spreads a row's terms over the
+// lanes of a wave instead of looping over them in one thread.
+constexpr int kLongTerms = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__ out) {
   const int i = a.sub0 + blockIdx.z;
@@ -50,6 +55,7 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
     return;
   }
   const int row = a.row0[i] + r - a.lead;
+  if (a.ptr[row + 1] - a.ptr[row] > kLongTerms) return;
   for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
     const Term tm = a.terms[q];
     const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
@@ -62,6 +68,36 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
     acc += tm.wgt * v;
   }
   out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;
+}
+
+// Rows with many terms: list[k] = (subdomain, local row) for k < nlong (all
+// in this launch's subdomains).  Block (k, column group): wave w takes column
+// j = 4 * blockIdx.y + w, its lanes the row's terms, then a wave sum.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_features_long(FeatArgs a, const int* __restrict__ list, T* __restrict__ out) {
+  const int i = list[2 * blockIdx.x], r = list[2 * blockIdx.x + 1];
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= a.M) return;
+  const double cx = a.geom[4 * i], cy = a.geom[4 * i + 1], hx = a.geom[4 * i + 2], hy = a.geom[4 * i + 3];
+  const double w0 = a.W[((size_t)i * a.M + j) * 2], w1 = a.W[((size_t)i * a.M + j) * 2 + 1];
+  const double bj = a.bias[(size_t)i * a.M + j];
+  const double gx = w0 / hx, gy = w1 / hy;
+  const double lap = gx * gx + gy * gy;
+  const int row = a.row0[i] + r - a.lead;
+  double acc = 0.0;
+  for (int q = a.ptr[row] + lane; q < a.ptr[row + 1]; q += 64) {
+    const Term tm = a.terms[q];
+    const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
+    const double t = tanh(z);
+    const double dt = 1.0 - t * t;
+    double v;
+    if (tm.op == OP_VALUE) v = t;
+    else if (tm.op == OP_NEG_LAPLACE) v = 2.0 * t * dt * lap;
+    else v = dt * (gx * tm.nx + gy * tm.ny);
+    acc += tm.wgt * v;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;
 }
 
 // ---------------------------------------------------------------- Householder QR
