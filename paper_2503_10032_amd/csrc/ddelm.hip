@@ -132,11 +132,26 @@ struct CtxBlocks {
   BlockList list;
 };
 thread_local CtxBlocks* tl_blocks = nullptr;
+thread_local hipStream_t tl_stream = nullptr;    // stream of the context whose call is running
 struct BlocksScope {
   CtxBlocks* prev;
   explicit BlocksScope(CtxBlocks* b) : prev(tl_blocks) { tl_blocks = b; }
   ~BlocksScope() { tl_blocks = prev; }
 };
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(tl_stream) { tl_stream = s; }
+  ~StreamScope() { tl_stream = prev; }
+};
+
+// Debugging aid: with DDELM_DEBUG_POISON=1 in the environment every device
+// block handed to a buffer is first filled with 0xFF bytes (a NaN in float
+// and double), so a kernel that reads memory nobody wrote shows up as
+// non-finite results instead of silently reading zeros or stale values.
+bool poison_enabled() {
+  const char* e = getenv("DDELM_DEBUG_POISON");
+  return e && e[0] == '1';
+}
 
 void release_idle_memory_locked(Resources& R) {
   for (BlockList& l : R.idle) {
@@ -191,6 +206,7 @@ struct DBuf {
     if (count == 0) return;
     try {
       p = (T*)dev_alloc(count * sizeof(T), cap);
+      if (poison_enabled()) HIPCHK(hipMemsetAsync(p, 0xFF, cap, tl_stream));
     } catch (...) {
       p = nullptr;
       n = 0;
@@ -444,6 +460,7 @@ namespace {
 template <typename F>
 ddelm_status run_guarded(ddelm_ctx c, F&& fn) {
   BlocksScope scope(c ? c->blocks : nullptr);
+  StreamScope sscope(c ? c->stream : nullptr);
   try {
     fn();
     return DDELM_OK;

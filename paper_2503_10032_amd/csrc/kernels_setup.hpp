@@ -295,60 +295,64 @@ __global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc
     xs[e] = c < nc ? Xm[(long long)(cbeg + c) * L + r] : T(0);
   }
   __syncthreads();
-  // Substitution by blocks of kTRB rows: the diagonal block (staged in LDS)
-  // is solved by kTRSMC threads of the first wave, one column each, then all
-  // threads update the rows not yet solved; three barriers per block instead
-  // of two per row.
+  // Substitution by blocks of kTRB rows.  The diagonal block is staged in
+  // LDS and solved by kTRSMC lanes of the first wave, one column each, with
+  // the block's unknowns in registers (fully unrolled, so the LDS reads of
+  // the block do not wait on each other).  Then every thread takes one row
+  // not yet solved: its kTRB entries of R are loaded in one batch and
+  // applied to all columns (the solved values are broadcast from LDS).
   __shared__ T Rd[kTRB][kTRB + 1];
   const int nblk = (n + kTRB - 1) / kTRB;
   for (int s = 0; s < nblk; ++s) {
     const int bk = trans ? s : nblk - 1 - s;
-    const int r0 = bk * kTRB, r1 = min(n, r0 + kTRB);
+    const int r0 = bk * kTRB, r1 = min(n, r0 + kTRB), nb = r1 - r0;
     for (int e = threadIdx.x; e < kTRB * kTRB; e += kBlock) {
       const int i = e % kTRB, j = e / kTRB;             // Rd[i][j] = R(r0 + i, r0 + j)
-      Rd[i][j] = (r0 + i < r1 && r0 + j < r1) ? R[(long long)(r0 + j) * d.ld + r0 + i] : T(0);
+      Rd[i][j] = (i < nb && j < nb) ? R[(long long)(r0 + j) * d.ld + r0 + i] : (i == j ? T(1) : T(0));
     }
     __syncthreads();
     if (threadIdx.x < kTRSMC) {
       const int c = threadIdx.x;
+      T x[kTRB];
+#pragma unroll
+      for (int k = 0; k < kTRB; ++k) x[k] = k < nb ? xs[(r0 + k) * kTRSMC + c] : T(0);
+      // rows past the end of R have a unit diagonal and zero coupling, so they stay 0
       if (!trans) {
-        for (int k = r1 - 1; k >= r0; --k) {
-          T v = xs[k * kTRSMC + c];
-          for (int j = k + 1; j < r1; ++j) v -= Rd[k - r0][j - r0] * xs[j * kTRSMC + c];
-          xs[k * kTRSMC + c] = v / Rd[k - r0][k - r0];
+#pragma unroll
+        for (int k = kTRB - 1; k >= 0; --k) {
+          T v = x[k];
+#pragma unroll
+          for (int j = k + 1; j < kTRB; ++j) v -= Rd[k][j] * x[j];
+          x[k] = v / Rd[k][k];
         }
       } else {
-        for (int k = r0; k < r1; ++k) {
-          T v = xs[k * kTRSMC + c];
-          for (int j = r0; j < k; ++j) v -= Rd[j - r0][k - r0] * xs[j * kTRSMC + c];
-          xs[k * kTRSMC + c] = v / Rd[k - r0][k - r0];
+#pragma unroll
+        for (int k = 0; k < kTRB; ++k) {
+          T v = x[k];
+#pragma unroll
+          for (int j = 0; j < k; ++j) v -= Rd[j][k] * x[j];
+          x[k] = v / Rd[k][k];
         }
       }
+#pragma unroll
+      for (int k = 0; k < kTRB; ++k)
+        if (k < nb) xs[(r0 + k) * kTRSMC + c] = x[k];
     }
     __syncthreads();
-    if (!trans) {     // rows above the block: x_r -= R(r, j) x_j
-      for (int e = threadIdx.x; e < r0 * kTRSMC; e += kBlock) {
-        const int r = e / kTRSMC, c = e % kTRSMC;
-        T rv[kTRB];
+    // rows still to solve: above the block (back substitution) or below it (forward)
+    const int u0 = trans ? r1 : 0, u1 = trans ? n : r0;
+    for (int r = u0 + threadIdx.x; r < u1; r += kBlock) {
+      T rv[kTRB];
 #pragma unroll
-        for (int j = 0; j < kTRB; ++j) rv[j] = r0 + j < r1 ? R[(long long)(r0 + j) * d.ld + r] : T(0);
-        T acc = xs[e];
+      for (int j = 0; j < kTRB; ++j)
+        rv[j] = j < nb ? (trans ? R[(long long)r * d.ld + r0 + j] : R[(long long)(r0 + j) * d.ld + r]) : T(0);
 #pragma unroll
-        for (int j = 0; j < kTRB; ++j)
-          if (r0 + j < r1) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];
-        xs[e] = acc;
-      }
-    } else {          // rows below the block: x_r -= R(j, r) x_j
-      for (int e = r1 * kTRSMC + threadIdx.x; e < n * kTRSMC; e += kBlock) {
-        const int r = e / kTRSMC, c = e % kTRSMC;
-        T rv[kTRB];
-#pragma unroll
-        for (int j = 0; j < kTRB; ++j) rv[j] = r0 + j < r1 ? R[(long long)r * d.ld + r0 + j] : T(0);
-        T acc = xs[e];
+      for (int c = 0; c < kTRSMC; ++c) {
+        T acc = xs[r * kTRSMC + c];
 #pragma unroll
         for (int j = 0; j < kTRB; ++j)
-          if (r0 + j < r1) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];
-        xs[e] = acc;
+          if (j < nb) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];   // rows past n are not in xs
+        xs[r * kTRSMC + c] = acc;
       }
     }
     __syncthreads();

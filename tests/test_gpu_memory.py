@@ -94,3 +94,32 @@ def test_two_live_contexts_on_two_streams():
         assert got[2] == ref[2]
         np.testing.assert_allclose(got[0], ref[0], rtol=0, atol=1e-13 * np.abs(ref[0]).max())
         np.testing.assert_allclose(got[1], ref[1], rtol=0, atol=1e-13 * np.abs(ref[1]).max())
+
+
+# With DDELM_DEBUG_POISON=1 every device block is filled with NaN bytes when
+# it is handed to a buffer, so a kernel that reads memory no kernel wrote (or
+# that multiplies stale on-chip values by zero) turns a result non-finite.
+# These reruns of parity tests cover the forward and adjoint paths in both
+# precisions, with matrix sizes that leave partial row and column blocks
+# (M = 90, 40, 48).
+import test_gpu_adjoint as _A       # noqa: E402  (sibling test modules)
+import test_gpu_parity as _P        # noqa: E402
+
+
+@pytest.mark.parametrize("name", ["3x3_uneven_M90", "4x3_M90"])
+def test_mixed_paths_read_only_written_memory(name, monkeypatch):
+    _torch()
+    monkeypatch.setenv("DDELM_DEBUG_POISON", "1")
+    _P.test_mixed_precision_matches_fp64_oracle(name)
+    _A.test_mixed_precision_adjoint_against_fp64_oracle(name)
+
+
+@pytest.mark.parametrize("name", ["3x3_uneven", "4x3", "7x7"])
+def test_fp64_paths_read_only_written_memory(name, monkeypatch):
+    _torch()
+    monkeypatch.setenv("DDELM_DEBUG_POISON", "1")
+    _P.test_solve_matches_oracle(name, 0.999, 2, 1)
+    if name != "7x7":
+        _P.test_factor_outputs(name)
+        _P.test_general_rhs_matches_oracle(name)
+        _A.test_adjoint_matches_oracle(name, 0.999, 2, 1)
