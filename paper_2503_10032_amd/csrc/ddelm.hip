@@ -1119,6 +1119,38 @@ void run_cg(ddelm_ctx c, int nrhs, double tol, CoreOut& res) {
   }
 }
 
+// Q^T or Q applied to the first nrhs columns of the local right-hand sides
+// of every K_c^i: for up to 4 columns one launch applies all blocks (columns
+// in LDS), otherwise one 64-column-tile launch per block.
+template <typename T, int NR>
+void launch_apply_narrow(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
+  LocalBufs<T>& L = c->lb<T>();
+  const size_t smem = (size_t)std::max(c->geo.max_m, 1) * NR * sizeof(T);
+  const void* fn = (const void*)k_qr_apply_narrow<T, NR>;
+  if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  k_qr_apply_narrow<T, NR><<<c->N, kBlock, smem, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, c->nblock, L.F.p, c->f_off.p,
+                                                      c->f_ld.p, nrhs, transT);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void apply_q_local(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
+  if (nrhs <= 1) return launch_apply_narrow<T, 1>(c, nrhs, transT, s);
+  if (nrhs <= 2) return launch_apply_narrow<T, 2>(c, nrhs, transT, s);
+  if (nrhs <= 4) return launch_apply_narrow<T, 4>(c, nrhs, transT, s);
+  LocalBufs<T>& L = c->lb<T>();
+  const int N = c->N;
+  const int ntile = ceil_div(nrhs, kBC);
+  const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
+  for (int q = 0; q < c->nblock; ++q) {
+    const int blk = transT ? q : c->nblock - 1 - q;
+    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
+                                                               c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
+                                                               cnR, 0, transT);
+    HIPCHK(hipGetLastError());
+  }
+}
+
 template <typename T>
 CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, const double* hP, const double* hD,
                    double tol, double* coef, int accumulate, double* mu_pi_out, double* mu_dl_out) {
@@ -1129,16 +1161,7 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   auto t0 = std::chrono::steady_clock::now();
   c->mark(5);
   // ---- Q^T f (block reflectors), projections, K^+ f, fluxes
-  {
-    const int ntile = ceil_div(nrhs, kBC);
-    const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
-    for (int blk = 0; blk < c->nblock; ++blk) {
-      k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
-                                                                 c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
-                                                                 cnR, 0, 1);
-      HIPCHK(hipGetLastError());
-    }
-  }
+  apply_q_local<T>(c, nrhs, 1, s);
   k_rhs_proj<T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
                                                                    c->offQG_d.p, L.QG.p, c->offm_d.p, c->summ, L.F.p,
                                                                    c->sumP, c->sumD, fGP, fGD, c->rho_loc.p,
@@ -1356,13 +1379,7 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
   k_adj_alpha<T><<<gl, kBlock, smG, s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offQG_d.p, L.QG.p,
                                          c->adj_pbar.p, sumG, c->offm_d.p, c->summ, L.F.p);
   HIPCHK(hipGetLastError());
-  for (int blk = c->nblock - 1; blk >= 0; --blk) {
-    const int ntile = ceil_div(nrhs, kBC);
-    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
-                                                               c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
-                                                               cnM, 0, 0);
-    HIPCHK(hipGetLastError());
-  }
+  apply_q_local<T>(c, nrhs, 0, s);
   k_adj_fout<T><<<gl, kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p, c->summ, L.F.p,
                                       c->adj_pbar.p, sumG, c->sumP, c->sumD, fbar, fbGP, fbGD);
   HIPCHK(hipGetLastError());

@@ -526,3 +526,124 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
 }
 
 }  // namespace ddelm
+
+namespace ddelm {
+
+// Q^T C (transT = 1, blocks in order) or Q C (transT = 0, blocks reversed)
+// for a few columns (ncols <= NR <= 4), one workgroup per matrix applying
+// every 64-reflector block in one launch.  The columns stay in LDS for the
+// whole launch; per block: W = V^T C (wave w takes reflectors 16w..16w+15,
+// lanes the rows), W <- -T^T W or -T W, then C += V W (threads take rows).
+template <typename T, int NR>
+__global__ void __launch_bounds__(kBlock) k_qr_apply_narrow(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                            const T* __restrict__ Tbig, int nblock, T* __restrict__ C,
+                                                            const long long* __restrict__ coff,
+                                                            const int* __restrict__ ldc, int ncols, int transT) {
+  extern __shared__ unsigned char smem_raw[];
+  T* cs = reinterpret_cast<T*>(smem_raw);          // [m][NR]
+  __shared__ T Ts[kBB][kBB + 1];
+  __shared__ T Ws[kBB][NR];
+  __shared__ T Wn[kBB][NR];
+  const QRDesc d = desc[blockIdx.x];
+  const int m = d.m, L = ldc[blockIdx.x];
+  T* Cm = C + coff[blockIdx.x];
+  const T* Am = A + d.off;
+  for (int e = threadIdx.x; e < m * NR; e += kBlock) {
+    const int c = e / m, r = e % m;
+    cs[r * NR + c] = c < ncols ? Cm[(long long)c * L + r] : T(0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = 0; q < nblock; ++q) {
+    const int blk = transT ? q : nblock - 1 - q;
+    const int kb = blk * kBB;
+    if (kb >= d.nrefl) continue;
+    const int bw = min(kBB, d.nrefl - kb);
+    const T* Tin = Tbig + ((long long)blockIdx.x * nblock + blk) * kBB * kBB;
+    for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Ts[e / kBB][e % kBB] = Tin[e];
+    // ---- W = V^T C
+    T acc[16][NR];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[jj][c] = T(0);
+    for (int r0 = kb; r0 < m; r0 += 128) {
+      T vv[2][16], cv[2][NR];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = r0 + u * 64 + lane;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          const int j = 16 * wv + jj;
+          vv[u][jj] = j < bw ? v_elem(Am, d.ld, m, kb, r, j) : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) cv[u][c] = r < m ? cs[r * NR + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[jj][c] += vv[u][jj] * cv[u][c];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const T v = wave_sum(acc[jj][c]);
+        if (lane == 0) Ws[16 * wv + jj][c] = v;
+      }
+    __syncthreads();
+    // ---- W <- -T^T W (Q^T) or -T W (Q)
+    for (int e = threadIdx.x; e < kBB * NR; e += kBlock) {
+      const int i = e / NR, c = e % NR;
+      T s = T(0);
+      if (transT) {
+        for (int ip = 0; ip <= i; ++ip) s += Ts[ip][i] * Ws[ip][c];
+      } else {
+        for (int ip = i; ip < kBB; ++ip) s += Ts[i][ip] * Ws[ip][c];
+      }
+      Wn[i][c] = -s;
+    }
+    __syncthreads();
+    // ---- C += V W, two rows per thread with their loads issued together
+    for (int r = kb + threadIdx.x; r < m; r += 2 * kBlock) {
+      const int r2 = r + kBlock;
+      T a[2][NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        a[0][c] = cs[r * NR + c];
+        a[1][c] = r2 < m ? cs[r2 * NR + c] : T(0);
+      }
+      for (int j0 = 0; j0 < bw; j0 += 16) {
+        T v0[16], v1[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          v0[jj] = j0 + jj < bw ? v_elem(Am, d.ld, m, kb, r, j0 + jj) : T(0);
+          v1[jj] = j0 + jj < bw ? v_elem(Am, d.ld, m, kb, r2, j0 + jj) : T(0);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) {
+            const T w = j0 + jj < bw ? Wn[j0 + jj][c] : T(0);
+            a[0][c] += v0[jj] * w;
+            a[1][c] += v1[jj] * w;
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        cs[r * NR + c] = a[0][c];
+        if (r2 < m) cs[r2 * NR + c] = a[1][c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < m * ncols; e += kBlock) {
+    const int c = e / m, r = e % m;
+    Cm[(long long)c * L + r] = cs[r * NR + c];
+  }
+}
+
+}  // namespace ddelm
