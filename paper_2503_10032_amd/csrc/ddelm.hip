@@ -393,6 +393,7 @@ struct ddelm_ctx_s {
   DBuf<int> f_ld, f_cn;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
+  DBuf<double> cg_r1, cg_s1;           // second r and s buffers of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
   int cg_blocks = 0, cg_slices = 0;
   // refinement workspaces (mixed precision)
@@ -603,7 +604,8 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   c->cg_c.alloc(C);
   c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
   const size_t V = (size_t)nrhs * std::max(c->nD, 1);
-  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b}) b->alloc(V);
+  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1})
+    b->alloc(V);
   c->mu_slot.alloc(P);
   c->e_slot.alloc(P);
   c->cg_part.alloc((size_t)2 * nrhs * 4096);
@@ -724,7 +726,8 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.nrhs = nrhs;
   f.tol = tol;
   f.maxit = c->opt.maxit;
-  f.x = c->cg_x.p; f.r = c->cg_r.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p; f.w = c->cg_w.p;
+  f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
+  f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
   f.err = c->flags.p;
   const int xs = std::max(g.max_nD, 1) * NR;
@@ -734,7 +737,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.lds_ys = xs;
   f.lds_part = xs + ys;
   f.lds_cu = xs + ys + part;
-  f.lds_total = xs + ys + part + cu;
+  f.lds_total = (xs + ys + part + cu + 1) & ~1;     // the int tables after it stay 16-byte aligned
   // distributed coarse phases when every unit gathering the whole coarse
   // right-hand side would cost more than the two extra synchronisations
   f.dist = (long long)c->nP * nrhs > 512 ? 1 : 0;
@@ -742,8 +745,16 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.X1t = c->X1t.p;
   f.ug = c->cg_u.p;
   f.cg1 = c->cg_c.p;
-  const size_t smem = sizeof(double) * (size_t)(xs + ys + part + cu);
-  if (smem > 160 * 1024) c->fail(DDELM_E_SHAPE, "CG workspace exceeds the LDS of one compute unit");
+  const size_t smem0 = sizeof(double) * (size_t)f.lds_total;
+  if (smem0 > 160 * 1024) c->fail(DDELM_E_SHAPE, "CG workspace exceeds the LDS of one compute unit");
+  // index tables (owner slots of the units' Delta points, of all Pi points)
+  int pi_owners = 0;
+  for (int k = 0; k < c->nP; ++k) pi_owners = std::max(pi_owners, g.pi_own_ptr[k + 1] - g.pi_own_ptr[k]);
+  const int tab_nd = std::max(g.max_nD, 1);
+  const int tab_pi = (!f.dist && pi_owners <= kMaxOwn) ? 1 : 0;
+  const size_t tab_bytes = sizeof(int) * ((size_t)kTabUnits * tab_nd * (1 + kMaxOwn) + (tab_pi ? (size_t)kMaxOwn * c->nP : 0));
+  const bool tab_fits = smem0 + tab_bytes <= 160 * 1024;
+  size_t smem = smem0 + (tab_fits ? tab_bytes : 0);
   const void* fn = (const void*)k_cg_fused<T, NR>;
   if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   int per_cu = 0;
@@ -752,6 +763,12 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   int nb = std::min(c->num_cu * std::min(per_cu, 2), c->N * S);
   if (const char* env = getenv("DDELM_CG_BLOCKS")) nb = std::max(1, std::min(nb, atoi(env)));
   nb = std::max(1, std::min(nb, 4096));
+  const int units_per_block = ceil_div(c->N * S, nb);
+  f.tab_units = (tab_fits && units_per_block <= kTabUnits) ? units_per_block : 0;
+  f.tab_nd = tab_nd;
+  f.tab_pi = f.tab_units ? tab_pi : 0;
+  if (const char* env = getenv("DDELM_CG_TABLES"))
+    if (atoi(env) == 0) f.tab_units = f.tab_pi = 0;
   f.flags = c->bar.p;
   HIPCHK(hipMemcpyAsync(f.r, c->cg_b.p, (size_t)nrhs * c->nD * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemsetAsync(c->bar.p, 0, (size_t)nb * kFlagStride * sizeof(unsigned), s));

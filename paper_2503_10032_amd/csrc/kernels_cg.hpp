@@ -5,13 +5,14 @@
 // many compute units.  Every unit handles all right-hand sides together, so
 // a matrix element read from memory serves nrhs products.
 //
-// Per iteration (theta != 0) the phases are separated by 8 grid-wide
-// synchronisations:
-//   A  p = r + beta p at the unit's Delta points; rows of [G; L](:, Delta) p
+// The iteration is the Chronopoulos-Gear form of CG (one operator
+// application and one fused reduction per step, see below).  Per pass
+// (theta != 0) the phases are separated by 7 grid-wide synchronisations:
+//   A  CG update at the unit's Delta points; rows of [G; L](:, Delta) r
 //   B  coarse solve at the subdomain's corners (mu_Pi, e), lam rows
 //   C  y = -N lambda rows               D  z = -N^T (P lambda) rows
-//   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, w rows
-//   G  w = sum of owners, partial p.w   H  alpha, x and r updates, partial r.r
+//   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, u rows
+//   G  u = A r as the sum of owners, partial (r, r) and (u, r)
 // With few coarse unknowns the coarse solves are done redundantly by every
 // unit for its own corners (rows of X1 against the full coarse right-hand
 // side), which removes synchronisations.  With many (nP * nrhs large) every
@@ -83,10 +84,12 @@ struct FusedArgs {
   double tol;
   int maxit;
   double* x;             // [nrhs][nD]
-  double* r;             // [nrhs][nD], holds b on entry
-  double* p0;            // [nrhs][nD] p buffers (alternate by iteration)
+  double* r;             // [nrhs][nD] r buffers (alternate by pass); r holds b on entry
+  double* r1;
+  double* p0;            // [nrhs][nD] p buffers (alternate by pass)
   double* p1;
-  double* w;             // [nrhs][nD]
+  double* s0;            // [nrhs][nD] s = A p buffers (alternate by pass)
+  double* s1;
   double* part;          // [2][nrhs][nb]
   double* mu_slot;       // [nrhs][sumP]  mu_Pi at the corner slots
   double* e_slot;        // [nrhs][sumP]
@@ -99,12 +102,27 @@ struct FusedArgs {
   const double* X1t;     // X1 transposed (row-major X1), for the distributed coarse rows
   double* ug;            // [nrhs][2 nP] gathered coarse right-hand side (distributed mode)
   double* cg1;           // [nrhs][2 nP] X1 times it (distributed mode)
+  // index tables in LDS (ints after the lds_total doubles): for each of the
+  // workgroup's units (at most tab_units; 0 = no tables) and each local Delta
+  // point, the global index (bit 30: this slot is the first owner) and the
+  // slots of its owners (-1 padded); for the coarse gathers of the redundant
+  // mode, the owner slots of every Pi point.
+  int tab_units, tab_nd, tab_pi;
 };
+
+constexpr int kTabUnits = 4;
+constexpr int kOwnerFlag = 1 << 30;
+
+// Owner slots of the Delta point k of the unit's table, as one 16-byte LDS read.
+__device__ __forceinline__ int4 tab_slots(const int* tslot, int k) {
+  return reinterpret_cast<const int4*>(tslot)[k];
+}
 
 // Distributed coarse gather: for the Pi points of this workgroup's share,
 // ug[r][p] = sum over owners of A, ug[r][nP + p] = sum over owners of B (B may be null).
 template <typename T>
-__device__ void coarse_gather(const OpArgs<T>& a, const double* A, const double* B, int nrhs, double* ug) {
+__device__ __forceinline__ void coarse_gather(const OpArgs<T>& a, const double* A, const double* B, int nrhs,
+                                              double* ug) {
   const unsigned nb = gridDim.x;
   const int chunk = (a.nP + (int)nb - 1) / (int)nb;
   const int p0 = blockIdx.x * chunk, p1 = min(a.nP, p0 + chunk);
@@ -126,8 +144,8 @@ __device__ void coarse_gather(const OpArgs<T>& a, const double* A, const double*
 // in LDS in groups; each wave holds a 512-column tile of one X1 row in
 // registers and applies it to the whole group.
 template <int NR>
-__device__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, const double* ug, int nrhs, double* lds,
-                            int lds_cap, double* out) {
+__device__ __forceinline__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, const double* ug,
+                                            int nrhs, double* lds, int lds_cap, double* out) {
   const unsigned nb = gridDim.x;
   const int ld = 2 * nP;
   const int chunk = (ld + (int)nb - 1) / (int)nb;
@@ -196,8 +214,8 @@ __device__ __forceinline__ void slice_rows(int n, int S, int q, int& r0, int& r1
 // are split into nsplit groups over k; partial sums meet in `part` (LDS,
 // kBlock * NM * NR doubles).
 template <typename T, int NR, int NM>
-__device__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K, const double* x, int nrhs,
-                        double* out, double* part) {
+__device__ __forceinline__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
+                                        const double* x, int nrhs, double* out, double* part) {
   if (R <= 0) {
     __syncthreads();
     return;
@@ -266,9 +284,9 @@ __device__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0
 // sum over owners of a local Delta vector, for all Delta points of subdomain i
 // into xs[k*NR + r] (LDS); optionally mixes two vectors (theta*A + (1-theta)*B)
 template <int NR>
-__device__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2g, int d0,
-                          int nd, const double* A, const double* B, double ca, double cb, int sumD, int nrhs,
-                          double* xs) {
+__device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2g, int d0, int nd,
+                                          const double* A, const double* B, double ca, double cb, int sumD, int nrhs,
+                                          double* xs) {
   const int n = nd * NR;
   for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
     double va[kLB][kMaxOwn], vb[kLB][kMaxOwn];
@@ -308,12 +326,52 @@ __device__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2
   }
 }
 
+// gather_dl with the owner slots read from the LDS table of the unit
+template <int NR>
+__device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const double* A, const double* B, double ca,
+                                              double cb, int sumD, int nrhs, double* xs) {
+  const int n = nd * NR;
+  for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
+    double va[kLB][kMaxOwn], vb[kLB][kMaxOwn];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+      int4 sl = make_int4(-1, -1, -1, -1);
+      if (e < n && r < nrhs) sl = tab_slots(tslot, k);
+      const int so[kMaxOwn] = {sl.x, sl.y, sl.z, sl.w};
+#pragma unroll
+      for (int o = 0; o < kMaxOwn; ++o) {
+        va[u][o] = 0.0;
+        vb[u][o] = 0.0;
+        if (so[o] >= 0) {
+          const size_t q = (size_t)r * sumD + so[o];
+          va[u][o] = ld_co(&A[q]);
+          if (B) vb[u][o] = ld_co(&B[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = e0 + u * kBlock;
+      if (e < n) {
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int o = 0; o < kMaxOwn; ++o) {
+          sa += va[u][o];
+          sb += vb[u][o];
+        }
+        xs[e] = B ? ca * sa + cb * sb : sa;
+      }
+    }
+  }
+}
+
 template <typename T, int NR>
 __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
   extern __shared__ double lds[];
   __shared__ double red[kWaves];
   __shared__ double redv[kWaves * NR];
-  __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR];
+  __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR], sc_gprev[NR];
   __shared__ double cor[2][4][NR];          // per corner: (mu, e) or (nu, -D nu)
   __shared__ double cms[2][4][NR];          // per corner: (mu, e) read back in F
   const OpArgs<T>& a = f.a;
@@ -327,97 +385,201 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
   double* part = lds + f.lds_part;
   double* cu = lds + f.lds_cu;
   unsigned epoch = 0;                        // flags are zeroed before every launch
-  double* pb[2] = {f.p0, f.p1};
+  int* tab = reinterpret_cast<int*>(lds + f.lds_total);
+  int* tg = tab;                                            // [tab_units][tab_nd]
+  int* tsl = tab + kTabUnits * f.tab_nd;                    // [tab_units][tab_nd][4], 16-byte aligned
+  int* tpi = tsl + 4 * kTabUnits * f.tab_nd;                // [nP][4] when tab_pi
+  if (f.tab_units) {
+    for (int t = 0; t < f.tab_units; ++t) {
+      const int u = blockIdx.x + t * (int)nb;
+      if (u >= nunits) break;
+      const int i = u / f.S, d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
+      for (int k = threadIdx.x; k < nd; k += kBlock) {
+        const int g = a.dl_l2g[d0 + k];
+        const int o0 = a.dl_own_ptr[g], cnt = a.dl_own_ptr[g + 1] - o0;
+        int sl[kMaxOwn];
+#pragma unroll
+        for (int o = 0; o < kMaxOwn; ++o) sl[o] = o < cnt ? a.dl_own_slot[o0 + o] : -1;
+        tg[t * f.tab_nd + k] = g | (sl[0] == d0 + k ? kOwnerFlag : 0);
+        reinterpret_cast<int4*>(tsl)[t * f.tab_nd + k] = make_int4(sl[0], sl[1], sl[2], sl[3]);
+      }
+    }
+    if (f.tab_pi) {
+      for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
+        const int o0 = a.pi_own_ptr[pq], cnt = a.pi_own_ptr[pq + 1] - o0;
+        int sl[kMaxOwn];
+#pragma unroll
+        for (int o = 0; o < kMaxOwn; ++o) sl[o] = o < cnt ? a.pi_own_slot[o0 + o] : -1;
+        reinterpret_cast<int4*>(tpi)[pq] = make_int4(sl[0], sl[1], sl[2], sl[3]);
+      }
+    }
+    __syncthreads();
+  }
 
-  // ---- prologue: x = 0, partial r.r
-  for (int r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
+  // Chronopoulos-Gear CG.  With u_k = A r_k, gamma_k = (r_k, r_k) and
+  // delta_k = (u_k, r_k):
+  //   beta_k  = gamma_k / gamma_{k-1}                      (beta_0 = 0)
+  //   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+  //   p_k = r_k + beta_k p_{k-1},   s_k = u_k + beta_k s_{k-1}   (s_k = A p_k)
+  //   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k
+  // (the same iterates as CG in exact arithmetic).  Pass `it` applies the
+  // operator to r_it.  Its phase A first forms p_{it-1}, s_{it-1}, x_it and
+  // r_it at the unit's Delta points from the reduction of the pass before:
+  // every unit computes its points' values, the first owner stores them, so
+  // the update needs no synchronisation of its own.  r, p and s alternate
+  // between two buffers by pass, so the other units still read a point's
+  // previous value in the same phase.
+  // ---- prologue: x = 0, p_{-1} = s_{-1} = 0 (r_0 = b is in rb[0])
+  for (int r = 0; r < nrhs; ++r)
     for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
       const size_t e = (size_t)r * a.nD + g;
-      const double rv = ld_co(&f.r[e]);
-      f.x[e] = 0.0;
+      st_co(&f.x[e], 0.0);      // x is updated by the owner unit's workgroup, so coherent stores throughout
       st_co(&f.p1[e], 0.0);
-      acc += rv * rv;
+      st_co(&f.s1[e], 0.0);
     }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], acc);
-  }
+  if (threadIdx.x == 0)
+    for (int r = 0; r < NR; ++r) {
+      sc_rr[r] = 0.0; sc_bb[r] = 0.0; sc_done[r] = 0.0; sc_it[r] = 0.0;
+      sc_beta[r] = 0.0; sc_alpha[r] = 0.0; sc_gprev[r] = 0.0;
+    }
   flag_sync(f.flags, nb, ++epoch, f.err);
 
   int it = 0;
   for (;; ++it) {
-    // ---- reduce r.r, convergence test, beta (identical in every workgroup)
-    double rrs[NR], rrt[NR];
+    if (it > 0) {
+      // ---- reduce gamma_{it-1}, delta_{it-1}; convergence test; alpha, beta (identical in every workgroup)
+      double gs[NR], ds[NR], gt[NR], dt[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) rrs[r] = 0.0;
-    for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
-      double v[NR];
+      for (int r = 0; r < NR; ++r) gs[r] = ds[r] = 0.0;
+      for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
+        double vg[NR], vd[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) v[r] = r < nrhs ? ld_co(&f.part[(size_t)(nrhs + r) * nb + k]) : 0.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) rrs[r] += v[r];
-    }
-    block_sum_vec<double, NR>(rrs, rrt, redv);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r >= nrhs) continue;
-      const double rr = rrt[r];
-      if (threadIdx.x == 0) {
-        if (it == 0) {
-          sc_bb[r] = rr; sc_rr[r] = rr; sc_done[r] = (rr == 0.0) ? 1.0 : 0.0; sc_it[r] = 0; sc_beta[r] = 0.0;
-        } else if (sc_done[r] == 0.0) {
-          sc_beta[r] = sc_rr[r] > 0.0 ? rr / sc_rr[r] : 0.0;
-          sc_rr[r] = rr;
-          sc_it[r] += 1.0;
-        } else {
-          sc_beta[r] = 0.0;
+        for (int r = 0; r < NR; ++r) {
+          vg[r] = r < nrhs ? ld_co(&f.part[(size_t)(nrhs + r) * nb + k]) : 0.0;
+          vd[r] = r < nrhs ? ld_co(&f.part[(size_t)r * nb + k]) : 0.0;
         }
-        if (sc_done[r] == 0.0 && (sqrt(sc_rr[r]) <= f.tol * sqrt(sc_bb[r]) || !(sc_rr[r] == sc_rr[r])))
-          sc_done[r] = 1.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          gs[r] += vg[r];
+          ds[r] += vd[r];
+        }
       }
+      block_sum_vec<double, NR>(gs, gt, redv);
+      block_sum_vec<double, NR>(ds, dt, redv);
+      if (threadIdx.x == 0) {
+        for (int r = 0; r < nrhs; ++r) {
+          const double gam = gt[r], del = dt[r];
+          if (sc_done[r] == 0.0) {
+            sc_rr[r] = gam;
+            if (it == 1) sc_bb[r] = gam;
+            if (gam == 0.0 || sqrt(gam) <= f.tol * sqrt(sc_bb[r]) || !(gam == gam)) sc_done[r] = 1.0;
+          }
+          if (sc_done[r] == 0.0 && it - 1 < f.maxit) {
+            const double beta = it == 1 ? 0.0 : gam / sc_gprev[r];
+            const double den = it == 1 ? del : del - beta * gam / sc_alpha[r];
+            sc_beta[r] = beta;
+            sc_alpha[r] = den != 0.0 ? gam / den : 0.0;
+            sc_gprev[r] = gam;
+            sc_it[r] += 1.0;
+          } else {
+            sc_beta[r] = 0.0;
+            sc_alpha[r] = 0.0;
+          }
+        }
+      }
+      __syncthreads();
+      bool all_done = true;
+      for (int r = 0; r < nrhs; ++r) all_done = all_done && sc_done[r] != 0.0;
+      if (all_done || it - 1 >= f.maxit) break;
     }
-    __syncthreads();
-    bool all_done = true;
-    for (int r = 0; r < nrhs; ++r) all_done = all_done && sc_done[r] != 0.0;
-    if (all_done || it >= f.maxit) break;
-    double* pc = pb[it & 1];          // p of this iteration
-    const double* pp = pb[(it + 1) & 1];
+    // (selects rather than indexed pointer arrays, which would live in scratch memory)
+    const bool odd = it & 1;
+    const double* r_old = odd ? f.r : f.r1;   // r_{it-1}
+    double* r_cur = odd ? f.r1 : f.r;         // r_it (r_0 = b when it == 0)
+    const double* p_old = odd ? f.p1 : f.p0;  // p_{it-2}
+    double* p_new = odd ? f.p0 : f.p1;        // p_{it-1}
+    const double* s_old = odd ? f.s1 : f.s0;
+    double* s_new = odd ? f.s0 : f.s1;
 
-    // ---- A: p at the unit's Delta points, rows of [G; L](:, Delta) p
-    for (int u = blockIdx.x; u < nunits; u += nb) {
+    // ---- A: CG update at the unit's Delta points, rows of [G; L](:, Delta) r_it
+    for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+      const bool use_tab = t < f.tab_units;
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
       const int ng = np + nd;
-      for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLB * kBlock) {
-        double rv[kLB], pv[kLB];
+      int r0, r1;
+      slice_rows(ng, f.S, q, r0, r1);
+      constexpr int kLA = NR >= 4 ? 4 : NR;   // elements per thread whose loads are issued together
+      for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLA * kBlock) {
+        double rv[kLA], pv[kLA], sv[kLA], wv[kLA][kMaxOwn];
+        int gg[kLA];
+        bool own[kLA];
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
-          rv[u] = 0.0;
-          pv[u] = 0.0;
+        for (int v = 0; v < kLA; ++v) {
+          const int e = e0 + v * kBlock, k = e / NR, r = e % NR;
+          rv[v] = pv[v] = sv[v] = 0.0;
+          gg[v] = 0;
+          own[v] = false;
+#pragma unroll
+          for (int o = 0; o < kMaxOwn; ++o) wv[v][o] = 0.0;
           if (e < nd * NR && r < nrhs) {
-            const size_t ge = (size_t)r * a.nD + a.dl_l2g[d0 + k];
-            rv[u] = ld_co(&f.r[ge]);
-            pv[u] = ld_co(&pp[ge]);
+            int so[kMaxOwn];
+            if (use_tab) {
+              const int tv = tg[t * f.tab_nd + k];
+              gg[v] = tv & ~kOwnerFlag;
+              own[v] = (tv & kOwnerFlag) != 0;
+              const int4 s4 = tab_slots(tsl + 4 * t * f.tab_nd, k);
+              so[0] = s4.x; so[1] = s4.y; so[2] = s4.z; so[3] = s4.w;
+            } else {
+              gg[v] = a.dl_l2g[d0 + k];
+              const int o0 = a.dl_own_ptr[gg[v]], cnt = a.dl_own_ptr[gg[v] + 1] - o0;
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) so[o] = o < cnt ? a.dl_own_slot[o0 + o] : -1;
+              own[v] = so[0] == d0 + k;
+            }
+            const size_t ge = (size_t)r * a.nD + gg[v];
+            if (it == 0) {
+              rv[v] = ld_co(&r_cur[ge]);
+            } else {
+              rv[v] = ld_co(&r_old[ge]);
+              pv[v] = ld_co(&p_old[ge]);
+              sv[v] = ld_co(&s_old[ge]);
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o)
+                if (so[o] >= 0) wv[v][o] = ld_co(&a.w_loc[(size_t)r * a.sumD + so[o]]);
+            }
           }
         }
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+        for (int v = 0; v < kLA; ++v) {
+          const int e = e0 + v * kBlock, r = e % NR;
           if (e >= nd * NR) continue;
-          double v = 0.0;
+          double x = 0.0;
           if (r < nrhs) {
-            const int g = a.dl_l2g[d0 + k];
-            v = rv[u] + sc_beta[r] * pv[u];
-            if (q == 0 && a.dl_own_slot[a.dl_own_ptr[g]] == d0 + k) st_co(&pc[(size_t)r * a.nD + g], v);
+            if (it == 0) {
+              x = rv[v];
+            } else {
+              double uu = 0.0;
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) uu += wv[v][o];
+              const double be = sc_beta[r], al = sc_alpha[r];
+              const double pn = rv[v] + be * pv[v];
+              const double sn = uu + be * sv[v];
+              x = rv[v] - al * sn;
+              if (q == 0 && own[v]) {
+                const size_t ge = (size_t)r * a.nD + gg[v];
+                st_co(&p_new[ge], pn);
+                st_co(&s_new[ge], sn);
+                st_co(&r_cur[ge], x);
+                st_co(&f.x[ge], ld_co(&f.x[ge]) + al * pn);
+              }
+            }
           }
-          xs[e] = v;
+          xs[e] = x;
         }
       }
       __syncthreads();
-      int r0, r1;
-      slice_rows(ng, f.S, q, r0, r1);
       mv_rows<T, NR, 2>(a.Gm + a.offG[i], a.Lm + a.offG[i], ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
       for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
         const int tt = e / NR, r = e % NR;
@@ -443,7 +605,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       coarse_rows<NR>(f.X1t, a.nP, 2 * a.nP, f.ug, nrhs, lds, f.lds_total, f.cg1);
       flag_sync(f.flags, nb, ++epoch, f.err);
     }
-    for (int u = blockIdx.x; u < nunits; u += nb) {
+    for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+      const bool use_tab = t < f.tab_units;
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
@@ -465,10 +628,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
         for (int r = 0; r < nrhs; ++r) {
           for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
             double s1 = 0.0, s2 = 0.0;
-            for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o) {
-              const int sl = a.pi_own_slot[o];
-              s1 += ld_co(&a.rho_loc[(size_t)r * a.sumP + sl]);
-              s2 += ld_co(&a.psi_loc[(size_t)r * a.sumP + sl]);
+            if (f.tab_pi) {
+              const int4 sl4 = reinterpret_cast<const int4*>(tpi)[pq];
+              const int so[kMaxOwn] = {sl4.x, sl4.y, sl4.z, sl4.w};
+              double v1[kMaxOwn], v2[kMaxOwn];
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) {
+                v1[o] = so[o] >= 0 ? ld_co(&a.rho_loc[(size_t)r * a.sumP + so[o]]) : 0.0;
+                v2[o] = so[o] >= 0 ? ld_co(&a.psi_loc[(size_t)r * a.sumP + so[o]]) : 0.0;
+              }
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) {
+                s1 += v1[o];
+                s2 += v2[o];
+              }
+            } else {
+              for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o) {
+                const int sl = a.pi_own_slot[o];
+                s1 += ld_co(&a.rho_loc[(size_t)r * a.sumP + sl]);
+                s2 += ld_co(&a.psi_loc[(size_t)r * a.sumP + sl]);
+              }
             }
             cu[pq] = s1;
             cu[a.nP + pq] = s2;
@@ -520,14 +699,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
 
     if (a.theta != 0.0) {
       // ---- C: y = -N lambda rows
-      for (int u = blockIdx.x; u < nunits; u += nb) {
+      for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+        const bool use_tab = t < f.tab_units;
         const int i = u / f.S, q = u % f.S;
         const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
-        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD,
-                      nrhs, xs);
-        __syncthreads();
         int r0, r1;
         slice_rows(nd, f.S, q, r0, r1);
+        if (use_tab) gather_dl_tab<NR>(tsl + 4 * t * f.tab_nd, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD, nrhs, xs);
+        else gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD,
+                           nrhs, xs);
+        __syncthreads();
         mv_rows<T, NR, 1>(a.Nm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
         for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
           const int tt = e / NR, r = e % NR;
@@ -537,14 +718,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       }
       flag_sync(f.flags, nb, ++epoch, f.err);
       // ---- D: z = -N^T (P lambda) rows
-      for (int u = blockIdx.x; u < nunits; u += nb) {
+      for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+        const bool use_tab = t < f.tab_units;
         const int i = u / f.S, q = u % f.S;
         const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
-        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.y_loc, nullptr, 1.0, 0.0, a.sumD,
-                      nrhs, xs);
-        __syncthreads();
         int r0, r1;
         slice_rows(nd, f.S, q, r0, r1);
+        if (use_tab) gather_dl_tab<NR>(tsl + 4 * t * f.tab_nd, nd, a.y_loc, nullptr, 1.0, 0.0, a.sumD, nrhs, xs);
+        else gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.y_loc, nullptr, 1.0, 0.0, a.sumD,
+                           nrhs, xs);
+        __syncthreads();
         mv_rows<T, NR, 1>(a.NTm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
         for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
           const int tt = e / NR, r = e % NR;
@@ -556,20 +739,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     }
 
     // ---- E: eta, rows of L^T(:, Delta) eta
-    for (int u = blockIdx.x; u < nunits; u += nb) {
+    for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+      const bool use_tab = t < f.tab_units;
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
       const int ng = np + nd;
-      if (a.theta != 0.0)
-        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.z_loc, a.lam_loc, a.theta,
-                      1.0 - a.theta, a.sumD, nrhs, xs);
-      else
-        gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, a.lam_loc, nullptr, 1.0, 0.0, a.sumD,
-                      nrhs, xs);
-      __syncthreads();
       int r0, r1;
       slice_rows(ng, f.S, q, r0, r1);
+      {
+        const double* zA = a.theta != 0.0 ? a.z_loc : a.lam_loc;
+        const double* zB = a.theta != 0.0 ? a.lam_loc : nullptr;
+        const double ca = a.theta != 0.0 ? a.theta : 1.0, cb = a.theta != 0.0 ? 1.0 - a.theta : 0.0;
+        if (use_tab) gather_dl_tab<NR>(tsl + 4 * t * f.tab_nd, nd, zA, zB, ca, cb, a.sumD, nrhs, xs);
+        else gather_dl<NR>(a.dl_own_ptr, a.dl_own_slot, a.dl_l2g, d0, nd, zA, zB, ca, cb, a.sumD, nrhs, xs);
+      }
+      __syncthreads();
       mv_rows<T, NR, 1>(a.LTm + a.offG[i], nullptr, ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
       for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
         const int tt = e / NR, r = e % NR;
@@ -589,7 +774,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       coarse_rows<NR>(f.X1t, a.nP, a.nP, f.ug, nrhs, lds, f.lds_total, f.cg1);
       flag_sync(f.flags, nb, ++epoch, f.err);
     }
-    for (int u = blockIdx.x; u < nunits; u += nb) {
+    for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
+      const bool use_tab = t < f.tab_units;
       const int i = u / f.S, q = u % f.S;
       const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
       const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
@@ -604,8 +790,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
         for (int r = 0; r < nrhs; ++r) {
           for (int pq = threadIdx.x; pq < a.nP; pq += kBlock) {
             double s1 = 0.0;
-            for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o)
-              s1 += ld_co(&a.nu_loc[(size_t)r * a.sumP + a.pi_own_slot[o]]);
+            if (f.tab_pi) {
+              const int4 sl4 = reinterpret_cast<const int4*>(tpi)[pq];
+              const int so[kMaxOwn] = {sl4.x, sl4.y, sl4.z, sl4.w};
+              double v1[kMaxOwn];
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) v1[o] = so[o] >= 0 ? ld_co(&a.nu_loc[(size_t)r * a.sumP + so[o]]) : 0.0;
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) s1 += v1[o];
+            } else {
+              for (int o = a.pi_own_ptr[pq]; o < a.pi_own_ptr[pq + 1]; ++o)
+                s1 += ld_co(&a.nu_loc[(size_t)r * a.sumP + a.pi_own_slot[o]]);
+            }
             cu[pq] = s1;
           }
           __syncthreads();
@@ -661,83 +857,40 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
 
-    // ---- G: w = sum of owners, partial p.w (all right-hand sides of a point together)
+    // ---- G: u_it = sum of owners; partial gamma_it = (r_it, r_it), delta_it = (u_it, r_it)
     {
-      double accs[NR];
+      double accg[NR], accd[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) accs[r] = 0.0;
+      for (int r = 0; r < NR; ++r) accg[r] = accd[r] = 0.0;
       for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
         const int o0 = a.dl_own_ptr[g], cnt = a.dl_own_ptr[g + 1] - o0;
-        double wv[NR][kMaxOwn], pv[NR];
+        double wv[NR][kMaxOwn], rv[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
 #pragma unroll
           for (int o = 0; o < kMaxOwn; ++o)
             wv[r][o] = (r < nrhs && o < cnt) ? ld_co(&a.w_loc[(size_t)r * a.sumD + a.dl_own_slot[o0 + o]]) : 0.0;
-          pv[r] = r < nrhs ? ld_co(&pc[(size_t)r * a.nD + g]) : 0.0;
+          rv[r] = r < nrhs ? ld_co(&r_cur[(size_t)r * a.nD + g]) : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r >= nrhs) continue;
-          double w = 0.0;
+          double uu = 0.0;
 #pragma unroll
-          for (int o = 0; o < kMaxOwn; ++o) w += wv[r][o];
-          f.w[(size_t)r * a.nD + g] = w;
-          accs[r] += w * pv[r];
+          for (int o = 0; o < kMaxOwn; ++o) uu += wv[r][o];
+          accg[r] += rv[r] * rv[r];
+          accd[r] += uu * rv[r];
         }
       }
-      double tot[NR];
-      block_sum_vec<double, NR>(accs, tot, redv);
+      double totg[NR], totd[NR];
+      block_sum_vec<double, NR>(accg, totg, redv);
+      block_sum_vec<double, NR>(accd, totd, redv);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], tot[r]);
-    }
-    flag_sync(f.flags, nb, ++epoch, f.err);
-
-    // ---- H: alpha, x and r updates, partial r.r (all right-hand sides of a point together)
-    {
-      double pws[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) pws[r] = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
-        double v[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = r < nrhs ? ld_co(&f.part[(size_t)r * nb + k]) : 0.0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) pws[r] += v[r];
-      }
-      double pwt[NR];
-      block_sum_vec<double, NR>(pws, pwt, redv);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) sc_alpha[r] = (sc_done[r] != 0.0 || pwt[r] == 0.0) ? 0.0 : sc_rr[r] / pwt[r];
-      __syncthreads();
-      double accs[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) accs[r] = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
-        double pv[NR], rv[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          pv[r] = r < nrhs ? ld_co(&pc[(size_t)r * a.nD + g]) : 0.0;
-          rv[r] = r < nrhs ? ld_co(&f.r[(size_t)r * a.nD + g]) : 0.0;
+        if (r < nrhs && threadIdx.x == 0) {
+          st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], totg[r]);
+          st_co(&f.part[(size_t)r * nb + blockIdx.x], totd[r]);
         }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (r >= nrhs) continue;
-          const size_t e = (size_t)r * a.nD + g;
-          const double al = sc_alpha[r];
-          f.x[e] += al * pv[r];
-          const double rn = rv[r] - al * f.w[e];
-          st_co(&f.r[e], rn);
-          accs[r] += rn * rn;
-        }
-      }
-      double tot[NR];
-      block_sum_vec<double, NR>(accs, tot, redv);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], tot[r]);
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
   }
