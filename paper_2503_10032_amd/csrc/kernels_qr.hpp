@@ -56,6 +56,79 @@ __device__ __forceinline__ T v_elem(const T* Am, int ld, int m, int k, int row, 
 constexpr int kPanelThreads = 512;
 constexpr int kPanelWaves = kPanelThreads / 64;
 
+// Column JJ of a panel (compile-time, so each column only touches the
+// columns it needs and picks its own column without selects).  One reduction
+// per column: with x the current column below the diagonal (rows r > j),
+// alpha = x_j and s = 1/(alpha - beta), v_j = [1; s x] and
+//   v_j . a_c = a_c[j] + s sum_{r>j} x_r a_c[r]        (c > JJ, applies H_j)
+//   v_c . v_j = v_c[j] + s sum_{r>j} x_r v_c[r]        (c < JJ, builds T)
+// so the squared norm of x (slot JJ) and the 15 sums share one reduction.
+template <typename T, int RPT, int JJ>
+__device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT][kNB], T* red, T* rowj,
+                                             T (&Ts)[kNB][kNB]) {
+  const int j = k + JJ;
+  T part[kNB];
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) part[c] = 0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kPanelThreads;
+    const T x = a[q][JJ];
+    if (r > j && r < d.m) {
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) part[c] += x * a[q][c];   // slot JJ: x . x
+    }
+    if (r == j) {
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) rowj[c] = a[q][c];
+    }
+  }
+  T w[kNB];
+  block_sum_vec_w<T, kNB, kPanelWaves>(part, w, red);
+  const T ss = w[JJ];
+  const T alpha = rowj[JJ];
+  T beta = alpha, tj = 0, scale = 0;
+  if (ss > T(0)) {
+    beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+    tj = (beta - alpha) / beta;
+    scale = T(1) / (alpha - beta);
+  }
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) w[c] = rowj[c] + scale * w[c];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = k + threadIdx.x + q * kPanelThreads;
+    if (r >= j && r < d.m) {
+      const T vj = (r == j) ? T(1) : a[q][JJ] * scale;
+      a[q][JJ] = (r == j) ? beta : vj;
+#pragma unroll
+      for (int c = JJ + 1; c < kNB; ++c) a[q][c] -= tj * w[c] * vj;
+    }
+  }
+  // T(0:JJ, JJ) = -tau_j T(0:JJ, 0:JJ) z, z_c = v_c . v_j = w_c (c < JJ); T(JJ, JJ) = tau_j
+  if (threadIdx.x < JJ) {      // thread i forms T(i, JJ)
+    const int i = threadIdx.x;
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < JJ; ++c)
+      if (c >= i) s += Ts[i][c] * w[c];
+    Ts[i][JJ] = -tj * s;
+  }
+  if (threadIdx.x == 0) Ts[JJ][JJ] = tj;
+  __syncthreads();
+}
+
+template <typename T, int RPT, int JJ>
+__device__ __forceinline__ void panel_columns(const QRDesc& d, int k, int ncol, T (&a)[RPT][kNB], T* red, T* rowj,
+                                              T (&Ts)[kNB][kNB]) {
+  if constexpr (JJ < kNB) {
+    if (JJ < ncol) {
+      panel_column<T, RPT, JJ>(d, k, a, red, rowj, Ts);
+      panel_columns<T, RPT, JJ + 1>(d, k, ncol, a, red, rowj, Ts);
+    }
+  }
+}
+
 template <typename T, int RPT>
 __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __restrict__ desc, T* __restrict__ A,
                                                               T* __restrict__ tau, T* __restrict__ Tbuf, int k,
@@ -75,77 +148,8 @@ __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __re
 #pragma unroll
     for (int c = 0; c < kNB; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
   }
-  // One reduction per column.  With x the current column below the diagonal
-  // (rows r > j), alpha = x_j and s = 1/(alpha - beta), v_j = [1; s x] and
-  //   v_j . a_c = a_c[j] + s sum_{r>j} x_r a_c[r]        (c > jj, applies H_j)
-  //   v_c . v_j = v_c[j] + s sum_{r>j} x_r v_c[r]        (c < jj, builds T)
-  // so the squared norm of x (slot jj) and the 15 sums share one reduction.
-  for (int jj = 0; jj < ncol; ++jj) {
-    const int j = k + jj;
-    T part[kNB];
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) part[c] = 0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kPanelThreads;
-      T x = T(0);
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) if (c == jj) x = a[q][c];
-      if (r > j && r < d.m) {
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) part[c] += x * a[q][c];   // slot jj: x . x
-      }
-      if (r == j) {
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) rowj[c] = a[q][c];
-      }
-    }
-    T w[kNB];
-    block_sum_vec_w<T, kNB, kPanelWaves>(part, w, red);
-    T ss = 0;
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) if (c == jj) ss = w[c];
-    T alpha = 0;
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) if (c == jj) alpha = rowj[c];
-    T beta = alpha, tj = 0, scale = 0;
-    if (ss > T(0)) {
-      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tj = (beta - alpha) / beta;
-      scale = T(1) / (alpha - beta);
-    }
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) w[c] = rowj[c] + scale * w[c];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kPanelThreads;
-      if (r >= j && r < d.m) {
-        T x = T(0);
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) if (c == jj) x = a[q][c];
-        const T vj = (r == j) ? T(1) : x * scale;
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) {
-          if (c == jj) a[q][c] = (r == j) ? beta : vj;
-          else if (c > jj) a[q][c] -= tj * w[c] * vj;
-        }
-      }
-    }
-    // T(0:jj, jj) = -tau_j T(0:jj, 0:jj) z, z_c = v_c . v_j = w_c (c < jj); T(jj, jj) = tau_j
-    if (threadIdx.x < jj) {      // thread i forms T(i, jj)
-      const int i = threadIdx.x;
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < kNB; ++c)
-        if (c >= i && c < jj) s += Ts[i][c] * w[c];
-      Ts[i][jj] = -tj * s;
-    }
-    if (threadIdx.x == 0) {
-      Ts[jj][jj] = tj;
-      tau[d.tau + j] = tj;
-    }
-    __syncthreads();
-  }
+  panel_columns<T, RPT, 0>(d, k, ncol, a, red, rowj, Ts);
+  if (threadIdx.x < ncol) tau[d.tau + k + threadIdx.x] = Ts[threadIdx.x][threadIdx.x];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = k + threadIdx.x + q * kPanelThreads;

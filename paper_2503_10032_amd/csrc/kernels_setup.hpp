@@ -115,156 +115,6 @@ struct QRDesc {
   int pad;
 };
 
-constexpr int kTW = 8;   // columns per register tile
-
-// Factor columns [k, k+kTW) of every matrix (rows k..m-1) with the panel
-// held in registers: row k + tid + q*kBlock, q < RPT.
-template <typename T, int RPT>
-__global__ void __launch_bounds__(kBlock) k_qr_panel(const QRDesc* __restrict__ desc, T* __restrict__ A,
-                                                     T* __restrict__ tau, int k) {
-  const QRDesc d = desc[blockIdx.x];
-  if (k >= d.nrefl) return;
-  __shared__ T red[kWaves * kTW];
-  __shared__ T bc[2];
-  T* Am = A + d.off;
-  const int ncol = min(kTW, d.nrefl - k);
-  T a[RPT][kTW];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kBlock;
-#pragma unroll
-    for (int c = 0; c < kTW; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
-  }
-  for (int jj = 0; jj < ncol; ++jj) {
-    const int j = k + jj;
-    // norm of the part below the diagonal, and the diagonal element
-    T ss = 0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kBlock;
-      T x = T(0);
-#pragma unroll
-      for (int c = 0; c < kTW; ++c) if (c == jj) x = a[q][c];
-      if (r > j && r < d.m) ss += x * x;
-      if (r == j) bc[0] = x;
-    }
-    ss = block_sum(ss, red);   // contains a barrier after bc[0] was written
-    const T alpha = bc[0];
-    T beta = alpha, tj = 0, scale = 0;
-    if (ss > T(0)) {
-      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tj = (beta - alpha) / beta;
-      scale = T(1) / (alpha - beta);
-    }
-    // form v_j in column jj, R diagonal
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kBlock;
-#pragma unroll
-      for (int c = 0; c < kTW; ++c) {
-        if (c == jj) {
-          if (r == j) a[q][c] = beta;
-          else if (r > j) a[q][c] *= scale;
-        }
-      }
-    }
-    if (threadIdx.x == 0) tau[d.tau + j] = tj;
-    // apply H_j to the panel columns right of jj
-    T part[kTW];
-#pragma unroll
-    for (int c = 0; c < kTW; ++c) part[c] = 0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kBlock;
-      if (r >= j && r < d.m) {
-        T v = T(1);
-#pragma unroll
-        for (int c = 0; c < kTW; ++c) if (c == jj && r > j) v = a[q][c];
-#pragma unroll
-        for (int c = 0; c < kTW; ++c) if (c > jj) part[c] += v * a[q][c];
-      }
-    }
-    T w[kTW];
-    block_sum_vec<T, kTW>(part, w, red);
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = k + threadIdx.x + q * kBlock;
-      if (r >= j && r < d.m) {
-        T v = T(1);
-#pragma unroll
-        for (int c = 0; c < kTW; ++c) if (c == jj && r > j) v = a[q][c];
-#pragma unroll
-        for (int c = 0; c < kTW; ++c) if (c > jj) a[q][c] -= tj * w[c] * v;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kBlock;
-#pragma unroll
-    for (int c = 0; c < kTW; ++c)
-      if (r < d.m && c < ncol) Am[(long long)(k + c) * d.ld + r] = a[q][c];
-  }
-}
-
-// Apply reflectors [j0, j1) of matrix b (stored in A) to a tile of kTW
-// columns of a target C: rows r0..m-1 with r0 = j0, columns
-// c0 + blockIdx.y*kTW + (0..kTW).  Target column c of matrix b is at
-// C + coff[b] + c*ldc[b].  reverse = 1 applies them from j1-1 down to j0
-// (multiplication by Q instead of Q^T).
-template <typename T, int RPT>
-__global__ void __launch_bounds__(kBlock) k_qr_apply(const QRDesc* __restrict__ desc, const T* __restrict__ A,
-                                                     const T* __restrict__ tau, int j0, int j1, T* __restrict__ C,
-                                                     const long long* __restrict__ coff, const int* __restrict__ ldc,
-                                                     const int* __restrict__ cn, int c0, int reverse) {
-  const QRDesc d = desc[blockIdx.x];
-  j1 = min(j1, d.nrefl);
-  if (j0 >= j1) return;
-  const int cbeg = c0 + blockIdx.y * kTW;
-  const int ctot = cn[blockIdx.x];
-  if (cbeg >= ctot) return;
-  const int ncol = min(kTW, ctot - cbeg);
-  __shared__ T red[kWaves * kTW];
-  const T* Am = A + d.off;
-  T* Cm = C + coff[blockIdx.x];
-  const int L = ldc[blockIdx.x];
-  T a[RPT][kTW];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = j0 + threadIdx.x + q * kBlock;
-#pragma unroll
-    for (int c = 0; c < kTW; ++c) a[q][c] = (r < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + r] : T(0);
-  }
-  for (int s = 0; s < j1 - j0; ++s) {
-    const int j = reverse ? (j1 - 1 - s) : (j0 + s);
-    const T tj = tau[d.tau + j];
-    T v[RPT];
-    T part[kTW];
-#pragma unroll
-    for (int c = 0; c < kTW; ++c) part[c] = 0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = j0 + threadIdx.x + q * kBlock;
-      v[q] = (r == j) ? T(1) : ((r > j && r < d.m) ? Am[(long long)j * d.ld + r] : T(0));
-#pragma unroll
-      for (int c = 0; c < kTW; ++c) part[c] += v[q] * a[q][c];
-    }
-    T w[kTW];
-    block_sum_vec<T, kTW>(part, w, red);
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int c = 0; c < kTW; ++c) a[q][c] -= tj * w[c] * v[q];
-  }
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = j0 + threadIdx.x + q * kBlock;
-#pragma unroll
-    for (int c = 0; c < kTW; ++c)
-      if (r < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + r] = a[q][c];
-  }
-}
-
 // ---------------------------------------------------------------- triangular solves
 //
 // X <- R^{-1} X (trans = 0) or R^{-T} X (trans = 1) for the n x n upper
@@ -437,19 +287,8 @@ __global__ void k_fill(double* __restrict__ p, long long n, double v) {
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
 }
 
-template <typename T>
-__global__ void k_fill_t(T* __restrict__ p, long long n, T v) {
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
-}
-
 // identity blocks: for each batch entry, add `v` on the diagonal of an n x n
 // block at off (column-major, ld = n)
-__global__ void k_add_diag(const long long* __restrict__ off, const int* __restrict__ n, double* __restrict__ P,
-                           double v) {
-  const int b = blockIdx.x;
-  for (int k = threadIdx.x; k < n[b]; k += kBlock) P[off[b] + (long long)k * n[b] + k] += v;
-}
-
 template <typename T>
 __global__ void k_add_diag_t(const long long* __restrict__ off, const int* __restrict__ n, T* __restrict__ P, T v) {
   const int b = blockIdx.x;
