@@ -63,10 +63,45 @@ constexpr int kPanelWaves = kPanelThreads / 64;
 //   v_j . a_c = a_c[j] + s sum_{r>j} x_r a_c[r]        (c > JJ, applies H_j)
 //   v_c . v_j = v_c[j] + s sum_{r>j} x_r v_c[r]        (c < JJ, builds T)
 // so the squared norm of x (slot JJ) and the 15 sums share one reduction.
+// Sum over the panel's workgroup of kNB values per thread with a single
+// barrier: wave sums through DPP, one LDS slot per wave, then every wave adds
+// the kPanelWaves partial sums itself (lanes 0..kNB-1) and broadcasts them
+// by readlane.  `red` holds kPanelWaves * kNB values; callers alternate two
+// buffers, so a wave that runs ahead cannot overwrite sums still being read.
+template <typename T>
+__device__ __forceinline__ void panel_sum(const T* v, T* out, T* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T w[kNB];
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) w[c] = wave_sum_dpp(v[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) red[wid * kNB + c] = w[c];
+  }
+  __syncthreads();
+  T s = 0;
+  if (lane < kNB) {
+#pragma unroll
+    for (int k = 0; k < kPanelWaves; ++k) s += red[k * kNB + lane];
+  }
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) {
+    if constexpr (sizeof(T) == 8) {
+      const int lo = __builtin_amdgcn_readlane(__double2loint(s), c);
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(s), c);
+      out[c] = __hiloint2double(hi, lo);
+    } else {
+      out[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s), c));
+    }
+  }
+}
+
 template <typename T, int RPT, int JJ>
-__device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT][kNB], T* red, T* rowj,
+__device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT][kNB], T* red2, T* rowj2,
                                              T (&Ts)[kNB][kNB]) {
   const int j = k + JJ;
+  T* red = red2 + (JJ & 1) * kPanelWaves * kNB;     // alternating buffers, see panel_sum
+  T* rowj = rowj2 + (JJ & 1) * kNB;
   T part[kNB];
 #pragma unroll
   for (int c = 0; c < kNB; ++c) part[c] = 0;
@@ -84,7 +119,7 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
     }
   }
   T w[kNB];
-  block_sum_vec_w<T, kNB, kPanelWaves>(part, w, red);
+  panel_sum<T>(part, w, red);
   const T ss = w[JJ];
   const T alpha = rowj[JJ];
   T beta = alpha, tj = 0, scale = 0;
@@ -114,8 +149,8 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
       if (c >= i) s += Ts[i][c] * w[c];
     Ts[i][JJ] = -tj * s;
   }
+  // (read by the next columns after their reduction's barrier)
   if (threadIdx.x == 0) Ts[JJ][JJ] = tj;
-  __syncthreads();
 }
 
 template <typename T, int RPT, int JJ>
@@ -135,8 +170,8 @@ __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __re
                                                               int panel, int npanel) {
   const QRDesc d = desc[blockIdx.x];
   if (k >= d.nrefl) return;
-  __shared__ T red[kPanelWaves * kNB + kNB];
-  __shared__ T rowj[kNB];
+  __shared__ T red[2 * kPanelWaves * kNB];
+  __shared__ T rowj[2 * kNB];
   __shared__ T Ts[kNB][kNB];
   T* Am = A + d.off;
   const int ncol = min(kNB, d.nrefl - k);
@@ -149,6 +184,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __re
     for (int c = 0; c < kNB; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
   }
   panel_columns<T, RPT, 0>(d, k, ncol, a, red, rowj, Ts);
+  __syncthreads();
   if (threadIdx.x < ncol) tau[d.tau + k + threadIdx.x] = Ts[threadIdx.x][threadIdx.x];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
