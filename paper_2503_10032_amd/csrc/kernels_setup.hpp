@@ -125,12 +125,12 @@ constexpr int kTRSMC = 8;    // right-hand-side columns per workgroup
 constexpr int kTRB = 16;     // rows per block of the substitution
 
 template <typename T, int kTRSMC>
-__global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+__global__ void __launch_bounds__(kBlock, 4) k_trsm(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                  T* __restrict__ X, const long long* __restrict__ xoff,
                                                  const int* __restrict__ ldx, const int* __restrict__ xn,
                                                  int trans) {
   extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);          // [n][kTRSMC]
+  T* xs = reinterpret_cast<T*>(smem_raw);          // [kTRSMC][n]: a column per RHS, rows along the lanes
   const QRDesc d = desc[blockIdx.x];
   const int n = d.nrefl;
   const int cbeg = blockIdx.y * kTRSMC;
@@ -140,75 +140,92 @@ __global__ void __launch_bounds__(kBlock) k_trsm(const QRDesc* __restrict__ desc
   const T* R = A + d.off;
   T* Xm = X + xoff[blockIdx.x];
   const int L = ldx[blockIdx.x];
-  for (int e = threadIdx.x; e < n * kTRSMC; e += kBlock) {
-    const int r = e / kTRSMC, c = e % kTRSMC;
-    xs[e] = c < nc ? Xm[(long long)(cbeg + c) * L + r] : T(0);
+  {
+    constexpr int kU = 8;      // loads issued together per thread
+    for (int e0 = threadIdx.x; e0 < n * kTRSMC; e0 += kU * kBlock) {
+      T v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * kBlock, c = e / n, r = e % n;
+        v[u] = (e < n * kTRSMC && c < nc) ? Xm[(long long)(cbeg + c) * L + r] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (e0 + u * kBlock < n * kTRSMC) xs[e0 + u * kBlock] = v[u];
+    }
   }
   __syncthreads();
   // Substitution by blocks of kTRB rows.  The diagonal block is staged in
-  // LDS and solved by kTRSMC lanes of the first wave, one column each, with
-  // the block's unknowns in registers (fully unrolled, so the LDS reads of
-  // the block do not wait on each other).  Then every thread takes one row
-  // not yet solved: its kTRB entries of R are loaded in one batch and
-  // applied to all columns (the solved values are broadcast from LDS).
+  // LDS with the reciprocals of its diagonal, and solved by kTRSMC lanes of
+  // the first wave, one column each, with the block's unknowns in registers
+  // and column by column (each solved unknown is removed from all remaining
+  // rows at once), so the dependent chain is one multiply and one
+  // multiply-add per row rather than a row-long sum and a division.  Then
+  // every thread takes one row not yet solved: its kTRB entries of R are
+  // loaded in one batch and applied to all columns (the solved values are
+  // broadcast from LDS).
   __shared__ T Rd[kTRB][kTRB + 1];
+  __shared__ T rinv[kTRB];
   const int nblk = (n + kTRB - 1) / kTRB;
   for (int s = 0; s < nblk; ++s) {
     const int bk = trans ? s : nblk - 1 - s;
     const int r0 = bk * kTRB, r1 = min(n, r0 + kTRB), nb = r1 - r0;
     for (int e = threadIdx.x; e < kTRB * kTRB; e += kBlock) {
       const int i = e % kTRB, j = e / kTRB;             // Rd[i][j] = R(r0 + i, r0 + j)
-      Rd[i][j] = (i < nb && j < nb) ? R[(long long)(r0 + j) * d.ld + r0 + i] : (i == j ? T(1) : T(0));
+      const T v = (i < nb && j < nb) ? R[(long long)(r0 + j) * d.ld + r0 + i] : (i == j ? T(1) : T(0));
+      Rd[i][j] = v;
+      if (i == j) rinv[i] = T(1) / v;
     }
     __syncthreads();
     if (threadIdx.x < kTRSMC) {
       const int c = threadIdx.x;
       T x[kTRB];
 #pragma unroll
-      for (int k = 0; k < kTRB; ++k) x[k] = k < nb ? xs[(r0 + k) * kTRSMC + c] : T(0);
+      for (int k = 0; k < kTRB; ++k) x[k] = k < nb ? xs[c * n + r0 + k] : T(0);
       // rows past the end of R have a unit diagonal and zero coupling, so they stay 0
       if (!trans) {
 #pragma unroll
         for (int k = kTRB - 1; k >= 0; --k) {
-          T v = x[k];
+          x[k] *= rinv[k];
 #pragma unroll
-          for (int j = k + 1; j < kTRB; ++j) v -= Rd[k][j] * x[j];
-          x[k] = v / Rd[k][k];
+          for (int j = 0; j < k; ++j) x[j] -= Rd[j][k] * x[k];
         }
       } else {
 #pragma unroll
         for (int k = 0; k < kTRB; ++k) {
-          T v = x[k];
+          x[k] *= rinv[k];
 #pragma unroll
-          for (int j = 0; j < k; ++j) v -= Rd[j][k] * x[j];
-          x[k] = v / Rd[k][k];
+          for (int j = k + 1; j < kTRB; ++j) x[j] -= Rd[k][j] * x[k];
         }
       }
 #pragma unroll
       for (int k = 0; k < kTRB; ++k)
-        if (k < nb) xs[(r0 + k) * kTRSMC + c] = x[k];
+        if (k < nb) xs[c * n + r0 + k] = x[k];
     }
     __syncthreads();
     // rows still to solve: above the block (back substitution) or below it (forward)
     const int u0 = trans ? r1 : 0, u1 = trans ? n : r0;
     for (int r = u0 + threadIdx.x; r < u1; r += kBlock) {
+      // one address per element, chosen before the load: two alternative
+      // loads into one register would make each wait for the previous one
+      const T* rp = trans ? R + (long long)r * d.ld + r0 : R + (long long)r0 * d.ld + r;
+      const long long rs = trans ? 1 : d.ld;
       T rv[kTRB];
 #pragma unroll
-      for (int j = 0; j < kTRB; ++j)
-        rv[j] = j < nb ? (trans ? R[(long long)r * d.ld + r0 + j] : R[(long long)(r0 + j) * d.ld + r]) : T(0);
+      for (int j = 0; j < kTRB; ++j) rv[j] = j < nb ? rp[j * rs] : T(0);
 #pragma unroll
       for (int c = 0; c < kTRSMC; ++c) {
-        T acc = xs[r * kTRSMC + c];
+        T acc = xs[c * n + r];
 #pragma unroll
         for (int j = 0; j < kTRB; ++j)
-          if (j < nb) acc -= rv[j] * xs[(r0 + j) * kTRSMC + c];   // rows past n are not in xs
-        xs[r * kTRSMC + c] = acc;
+          if (j < nb) acc -= rv[j] * xs[c * n + r0 + j];   // rows past n are not in xs
+        xs[c * n + r] = acc;
       }
     }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < n * kTRSMC; e += kBlock) {
-    const int r = e / kTRSMC, c = e % kTRSMC;
+    const int c = e / n, r = e % n;
     if (c < nc) Xm[(long long)(cbeg + c) * L + r] = xs[e];
   }
 }
