@@ -539,10 +539,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
               own[v] = so[0] == d0 + k;
             }
             const size_t ge = (size_t)r * a.nD + gg[v];
-            if (it == 0) {
-              rv[v] = ld_co(&r_cur[ge]);
-            } else {
-              rv[v] = ld_co(&r_old[ge]);
+            // (source chosen before the load: alternative loads into one register wait on each other)
+            rv[v] = ld_co(&(it == 0 ? r_cur : r_old)[ge]);
+            if (it != 0) {
               pv[v] = ld_co(&p_old[ge]);
               sv[v] = ld_co(&s_old[ge]);
 #pragma unroll

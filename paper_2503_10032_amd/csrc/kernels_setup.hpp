@@ -255,9 +255,9 @@ __global__ void __launch_bounds__(kBlock) k_gemm(const GemmDesc* __restrict__ de
     {
       const int rr = tx, kk = ty;
       const int r = blockIdx.x * 16 + rr, kx = k0 + kk;
-      double v = 0.0;
-      if (r < g.m && kx < g.k)
-        v = transA ? (double)A[g.a + (long long)r * g.lda + kx] : (double)A[g.a + (long long)kx * g.lda + r];
+      // the address is chosen before the load (two alternative loads would wait on each other)
+      const long long ia = transA ? g.a + (long long)r * g.lda + kx : g.a + (long long)kx * g.lda + r;
+      const double v = (r < g.m && kx < g.k) ? (double)A[ia] : 0.0;
       As[kk][rr] = v;
       const int cc = ty, kb = tx;
       const int cgl = blockIdx.y * 16 + cc, kbx = k0 + kb;
