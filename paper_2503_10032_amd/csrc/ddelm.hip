@@ -393,7 +393,7 @@ struct ddelm_ctx_s {
   DBuf<int> f_ld, f_cn;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
-  DBuf<double> cg_r1, cg_s1;           // second r and s buffers of the persistent CG
+  DBuf<double> cg_r1, cg_s1, cg_uv;    // second r and s buffers, u = A r of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
   int cg_blocks = 0, cg_slices = 0;
   // refinement workspaces (mixed precision)
@@ -604,7 +604,8 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   c->cg_c.alloc(C);
   c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
   const size_t V = (size_t)nrhs * std::max(c->nD, 1);
-  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1})
+  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1,
+                          &c->cg_uv})
     b->alloc(V);
   c->mu_slot.alloc(P);
   c->e_slot.alloc(P);
@@ -727,7 +728,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.tol = tol;
   f.maxit = c->opt.maxit;
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
-  f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p;
+  f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p; f.u = c->cg_uv.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
   f.err = c->flags.p;
   const int xs = std::max(g.max_nD, 1) * NR;

@@ -12,7 +12,7 @@
 //   B  coarse solve at the subdomain's corners (mu_Pi, e), lam rows
 //   C  y = -N lambda rows               D  z = -N^T (P lambda) rows
 //   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, u rows
-//   G  u = A r as the sum of owners, partial (r, r) and (u, r)
+//   G  u = A r as the sum of owners (stored), partial (r, r) and (u, r)
 // With few coarse unknowns the coarse solves are done redundantly by every
 // unit for its own corners (rows of X1 against the full coarse right-hand
 // side), which removes synchronisations.  With many (nP * nrhs large) every
@@ -90,6 +90,7 @@ struct FusedArgs {
   double* p1;
   double* s0;            // [nrhs][nD] s = A p buffers (alternate by pass)
   double* s1;
+  double* u;             // [nrhs][nD] u = A r of the pass (sum of owners, stored by the reduction phase)
   double* part;          // [2][nrhs][nb]
   double* mu_slot;       // [nrhs][sumP]  mu_Pi at the corner slots
   double* e_slot;        // [nrhs][sumP]
@@ -213,11 +214,64 @@ __device__ __forceinline__ void slice_rows(int n, int S, int q, int& r0, int& r1
 // matrices m < NM; results in out[(m*R + t)*NR + r] (LDS).  The 256 threads
 // are split into nsplit groups over k; partial sums meet in `part` (LDS,
 // kBlock * NM * NR doubles).
+// Many right-hand sides: the same products as a small GEMM on f64 MFMA,
+// Y (R x NR) = A (R x K) X (K x NR) in 16-row tiles (one per wave at a time,
+// NR <= 16 right-hand sides padded to the 16 MFMA columns), the matrix
+// streamed from memory as the A operand (lane l: row l & 15, column l >> 4
+// of each 16 x 4 step, so 16 consecutive rows of a column per load) and X
+// read from LDS as the B operand.  kMB steps (4 columns each) of loads are
+// issued before their products.  Float32 matrices are widened to float64.
+template <typename T, int NR, int NM>
+__device__ __forceinline__ void mv_rows_mfma(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
+                                             const double* x, double* out) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  constexpr int kMB = 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ntile = (R + 15) / 16;
+  for (int tile = wv; tile < ntile; tile += kWaves) {
+    v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int row = tile * 16 + lr;
+    const bool rok = row < R;
+    const T* a0 = A0 + (long long)c0 * lda + r0 + row;
+    const T* a1 = NM > 1 ? A1 + (long long)c0 * lda + r0 + row : nullptr;
+    for (int k0 = 0; k0 < K; k0 += 4 * kMB) {
+      double va[kMB], vb[kMB], xb[kMB];
+#pragma unroll
+      for (int u = 0; u < kMB; ++u) {
+        const int kk = k0 + 4 * u + lk;
+        va[u] = (rok && kk < K) ? (double)a0[(long long)kk * lda] : 0.0;
+        vb[u] = (NM > 1 && rok && kk < K) ? (double)a1[(long long)kk * lda] : 0.0;
+        xb[u] = (kk < K && lr < NR) ? x[kk * NR + lr] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kMB; ++u) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], xb[u], acc0, 0, 0, 0);
+        if (NM > 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[u], xb[u], acc1, 0, 0, 0);
+      }
+    }
+    // accumulator element v of lane l holds row (l >> 4) + 4 v, right-hand side l & 15
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int orow = tile * 16 + lk + 4 * v;
+      if (orow < R && lr < NR) {
+        out[orow * NR + lr] = acc0[v];
+        if (NM > 1) out[(R + orow) * NR + lr] = acc1[v];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int NR, int NM>
 __device__ __forceinline__ void mv_rows(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
                                         const double* x, int nrhs, double* out, double* part) {
   if (R <= 0) {
     __syncthreads();
+    return;
+  }
+  if constexpr (NR >= 8) {
+    mv_rows_mfma<T, NR, NM>(A0, A1, lda, r0, R, c0, K, x, out);
     return;
   }
   // rows per pass: 64, 128 or 256 so that no thread of the block idles for
@@ -512,31 +566,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       slice_rows(ng, f.S, q, r0, r1);
       constexpr int kLA = NR >= 4 ? 4 : NR;   // elements per thread whose loads are issued together
       for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLA * kBlock) {
-        double rv[kLA], pv[kLA], sv[kLA], wv[kLA][kMaxOwn];
+        double rv[kLA], pv[kLA], sv[kLA], uv[kLA];
         int gg[kLA];
         bool own[kLA];
 #pragma unroll
         for (int v = 0; v < kLA; ++v) {
           const int e = e0 + v * kBlock, k = e / NR, r = e % NR;
-          rv[v] = pv[v] = sv[v] = 0.0;
+          rv[v] = pv[v] = sv[v] = uv[v] = 0.0;
           gg[v] = 0;
           own[v] = false;
-#pragma unroll
-          for (int o = 0; o < kMaxOwn; ++o) wv[v][o] = 0.0;
           if (e < nd * NR && r < nrhs) {
-            int so[kMaxOwn];
             if (use_tab) {
               const int tv = tg[t * f.tab_nd + k];
               gg[v] = tv & ~kOwnerFlag;
               own[v] = (tv & kOwnerFlag) != 0;
-              const int4 s4 = tab_slots(tsl + 4 * t * f.tab_nd, k);
-              so[0] = s4.x; so[1] = s4.y; so[2] = s4.z; so[3] = s4.w;
             } else {
               gg[v] = a.dl_l2g[d0 + k];
-              const int o0 = a.dl_own_ptr[gg[v]], cnt = a.dl_own_ptr[gg[v] + 1] - o0;
-#pragma unroll
-              for (int o = 0; o < kMaxOwn; ++o) so[o] = o < cnt ? a.dl_own_slot[o0 + o] : -1;
-              own[v] = so[0] == d0 + k;
+              own[v] = a.dl_own_slot[a.dl_own_ptr[gg[v]]] == d0 + k;
             }
             const size_t ge = (size_t)r * a.nD + gg[v];
             // (source chosen before the load: alternative loads into one register wait on each other)
@@ -544,9 +590,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
             if (it != 0) {
               pv[v] = ld_co(&p_old[ge]);
               sv[v] = ld_co(&s_old[ge]);
-#pragma unroll
-              for (int o = 0; o < kMaxOwn; ++o)
-                if (so[o] >= 0) wv[v][o] = ld_co(&a.w_loc[(size_t)r * a.sumD + so[o]]);
+              uv[v] = ld_co(&f.u[ge]);
             }
           }
         }
@@ -559,9 +603,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
             if (it == 0) {
               x = rv[v];
             } else {
-              double uu = 0.0;
-#pragma unroll
-              for (int o = 0; o < kMaxOwn; ++o) uu += wv[v][o];
+              const double uu = uv[v];
               const double be = sc_beta[r], al = sc_alpha[r];
               const double pn = rv[v] + be * pv[v];
               const double sn = uu + be * sv[v];
@@ -877,6 +919,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
           double uu = 0.0;
 #pragma unroll
           for (int o = 0; o < kMaxOwn; ++o) uu += wv[r][o];
+          st_co(&f.u[(size_t)r * a.nD + g], uu);
           accg[r] += rv[r] * rv[r];
           accd[r] += uu * rv[r];
         }
