@@ -226,6 +226,7 @@ def main():
         "dominant_phase": dominant,
         "rel_l2_error_vs_exact": err,
         "roofline": roof,
+        "cg_launch": {k: out["stats"][k] for k in ("cg_blocks", "cg_slices", "cg_coarse_dist")},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, W, b, xi, I.eval_grid(w))

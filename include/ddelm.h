@@ -119,6 +119,9 @@ typedef struct {
   double ms_rhs;            /* wall time of the right-hand-side assembly */
   double ms_cg;             /* wall time of the CG loop(s) */
   double ms_recover;        /* wall time of recovery (and refinement residuals) */
+  int cg_blocks;            /* persistent CG: workgroups of the last launch (0 with cg_mode 1) */
+  int cg_slices;            /* persistent CG: row slices per subdomain (tuned, see ddelm_solve) */
+  int cg_coarse_dist;       /* persistent CG: 1 = coarse phases distributed over workgroups */
 } ddelm_stats;
 
 typedef struct {

@@ -42,6 +42,7 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int), ("refine_steps", ctypes.c_int), ("rel_res", ctypes.c_double),
         ("ms_rhs", ctypes.c_double), ("ms_cg", ctypes.c_double), ("ms_recover", ctypes.c_double),
+        ("cg_blocks", ctypes.c_int), ("cg_slices", ctypes.c_int), ("cg_coarse_dist", ctypes.c_int),
     ]
 
 

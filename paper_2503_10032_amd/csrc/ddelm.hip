@@ -10,6 +10,7 @@
 #include <cstring>
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -395,7 +396,7 @@ struct ddelm_ctx_s {
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
   DBuf<double> cg_r1, cg_s1, cg_uv;    // second r and s buffers, u = A r of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
-  int cg_blocks = 0, cg_slices = 0;
+  int cg_blocks = 0, cg_slices = 0, cg_dist = 0;   // launch shape of the last persistent CG
   // refinement workspaces (mixed precision)
   DBuf<double> F64, R64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
   DBuf<double> fGP0, fGD0, hP0, hD0;   // interface rows and flux rows of a general right-hand side
@@ -714,19 +715,24 @@ void cg_multilaunch(ddelm_ctx c, int nrhs, double tol) {
   }
 }
 
+// Launch configuration of the persistent CG: row slices per subdomain and
+// redundant or distributed coarse phases.
+struct CgConfig {
+  int S = 1;
+  int dist = 0;
+};
+
 template <typename T, int NR>
-void launch_fused(ddelm_ctx c, int nrhs, double tol) {
+void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int maxit) {
   hipStream_t s = c->stream;
   const Geometry& g = c->geo;
   FusedArgs<T> f;
   f.a = op_args<T>(c, nrhs);
-  int S = 1;
-  if (const char* env = getenv("DDELM_CG_SLICES")) S = std::max(1, std::min(8, atoi(env)));
-  else S = std::max(1, std::min(4, 128 / std::max(c->N, 1)));
+  const int S = cfg.S;
   f.S = S;
   f.nrhs = nrhs;
   f.tol = tol;
-  f.maxit = c->opt.maxit;
+  f.maxit = maxit;
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
   f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p; f.u = c->cg_uv.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
@@ -739,10 +745,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   f.lds_part = xs + ys;
   f.lds_cu = xs + ys + part;
   f.lds_total = (xs + ys + part + cu + 1) & ~1;     // the int tables after it stay 16-byte aligned
-  // distributed coarse phases when every unit gathering the whole coarse
-  // right-hand side would cost more than the two extra synchronisations
-  f.dist = (long long)c->nP * nrhs > 512 ? 1 : 0;
-  if (const char* env = getenv("DDELM_CG_COARSE")) f.dist = atoi(env) != 0 ? 1 : 0;
+  f.dist = cfg.dist;
   f.X1t = c->X1t.p;
   f.ug = c->cg_u.p;
   f.cg1 = c->cg_c.p;
@@ -777,15 +780,100 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol) {
   HIPCHK(hipLaunchCooperativeKernel(fn, dim3(nb), dim3(kBlock), args, smem, s));
   c->cg_blocks = nb;
   c->cg_slices = S;
+  c->cg_dist = f.dist;
+}
+
+// Autotuner of the CG launch.  The first solve of a problem shape in the
+// process times a few iterations of every candidate configuration on the
+// actual operator and right-hand side (tolerance 0, so each runs the same
+// number of iterations) and keeps the fastest; later solves of the same shape
+// reuse it.  Candidates: 1, 2 or 4 row slices per subdomain, and redundant or
+// distributed coarse phases where n_Pi * nrhs makes both plausible.
+// DDELM_CG_SLICES / DDELM_CG_COARSE fix a choice, DDELM_AUTOTUNE=0 turns the
+// tuner off (then a size heuristic decides).
+struct CgKey {
+  int tsize, nr, N, nP, nD, maxG, maxD, nrhs;
+  bool operator<(const CgKey& o) const {
+    return std::tie(tsize, nr, N, nP, nD, maxG, maxD, nrhs) <
+           std::tie(o.tsize, o.nr, o.N, o.nP, o.nD, o.maxG, o.maxD, o.nrhs);
+  }
+};
+std::map<CgKey, CgConfig>& cg_tuned() {
+  static std::map<CgKey, CgConfig>* m = new std::map<CgKey, CgConfig>();
+  return *m;
+}
+constexpr int kTuneIters = 8;
+
+template <typename T, int NR>
+CgConfig cg_choose(ddelm_ctx c, int nrhs) {
+  // heuristic: slices so that small problems still spread over the chip;
+  // distributed coarse phases when every unit gathering the whole coarse
+  // right-hand side would cost more than the extra synchronisations
+  CgConfig h;
+  h.S = std::max(1, std::min(4, 128 / std::max(c->N, 1)));
+  h.dist = (long long)c->nP * nrhs > 512 ? 1 : 0;
+  const char* es = getenv("DDELM_CG_SLICES");
+  const char* ed = getenv("DDELM_CG_COARSE");
+  const char* ea = getenv("DDELM_AUTOTUNE");
+  if (es) h.S = std::max(1, std::min(8, atoi(es)));
+  if (ed) h.dist = atoi(ed) != 0 ? 1 : 0;
+  if ((es && ed) || (ea && atoi(ea) == 0)) return h;
+  const CgKey key{(int)sizeof(T), NR, c->N, c->nP, c->nD, c->geo.max_nG, c->geo.max_nD, nrhs};
+  {
+    Resources& R = res();
+    std::lock_guard<std::mutex> lk(R.mu);
+    auto it = cg_tuned().find(key);
+    if (it != cg_tuned().end()) return it->second;
+  }
+  std::vector<CgConfig> cand;
+  for (int S : {1, 2, 4}) {
+    if (es && S != h.S) continue;
+    if ((long long)c->N * S > 8192) continue;
+    const long long np_r = (long long)c->nP * nrhs;
+    for (int d : {0, 1}) {
+      if (ed && d != h.dist) continue;
+      if (!ed && d != h.dist && (np_r < 64 || np_r > 8192)) continue;   // only the heuristic's choice is plausible
+      cand.push_back({S, d});
+    }
+  }
+  hipStream_t s = c->stream;
+  hipEvent_t t0 = take_event(c->device, true), t1 = take_event(c->device, true);
+  CgConfig best = h;
+  float best_ms = 1e30f;
+  launch_fused<T, NR>(c, nrhs, 0.0, cand.front(), kTuneIters);    // warm-up (code load, first touch)
+  for (const CgConfig& cf : cand) {
+    HIPCHK(hipEventRecord(t0, s));
+    launch_fused<T, NR>(c, nrhs, 0.0, cf, kTuneIters);
+    HIPCHK(hipEventRecord(t1, s));
+    HIPCHK(hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cf;
+    }
+  }
+  give_event(c->device, true, t0);
+  give_event(c->device, true, t1);
+  Resources& R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  cg_tuned()[key] = best;
+  return best;
+}
+
+template <typename T, int NR>
+void cg_run(ddelm_ctx c, int nrhs, double tol) {
+  const CgConfig cfg = cg_choose<T, NR>(c, nrhs);
+  launch_fused<T, NR>(c, nrhs, tol, cfg, c->opt.maxit);
 }
 
 template <typename T>
 void cg_persistent(ddelm_ctx c, int nrhs, double tol) {
-  if (nrhs <= 1) launch_fused<T, 1>(c, nrhs, tol);
-  else if (nrhs <= 2) launch_fused<T, 2>(c, nrhs, tol);
-  else if (nrhs <= 4) launch_fused<T, 4>(c, nrhs, tol);
-  else if (nrhs <= 8) launch_fused<T, 8>(c, nrhs, tol);
-  else if (nrhs <= 16) launch_fused<T, 16>(c, nrhs, tol);
+  if (nrhs <= 1) cg_run<T, 1>(c, nrhs, tol);
+  else if (nrhs <= 2) cg_run<T, 2>(c, nrhs, tol);
+  else if (nrhs <= 4) cg_run<T, 4>(c, nrhs, tol);
+  else if (nrhs <= 8) cg_run<T, 8>(c, nrhs, tol);
+  else if (nrhs <= 16) cg_run<T, 16>(c, nrhs, tol);
   else c->fail(DDELM_E_ARG, "the persistent CG handles at most 16 right-hand sides");
 }
 
@@ -1520,6 +1608,9 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
     }
     HIPCHK(hipStreamSynchronize(s));
   });
+  st.cg_blocks = c->cg_blocks;
+  st.cg_slices = c->cg_slices;
+  st.cg_coarse_dist = c->cg_dist;
   if (stats) *stats = st;
   if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
   return code;
@@ -1774,6 +1865,9 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
       HIPCHK(hipStreamSynchronize(s));
     }
   });
+  st.cg_blocks = c->cg_blocks;
+  st.cg_slices = c->cg_slices;
+  st.cg_coarse_dist = c->cg_dist;
   if (stats) *stats = st;
   if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
   return code;

@@ -175,7 +175,8 @@ class DDELMSolver:
                                                     _ptr(mu_pi) if self.n_pi else None,
                                                     _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)), "solve")
         stats = dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
-                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
+                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
+                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
         return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
 
     def solve_general(self, f_loc, h=None, want_mu: bool = True):
@@ -201,7 +202,8 @@ class DDELMSolver:
                 _ptr(mu_pi) if self.n_pi else None, _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)),
                 "solve_general")
         stats = dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
-                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
+                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
+                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
         return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
 
     def evaluate(self, coef: torch.Tensor, x, grad: bool = False):
@@ -220,7 +222,8 @@ class DDELMSolver:
     # ------------------------------------------------------------ adjoints
     def _stats(self, st, code):
         return dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
-                    ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK)
+                    ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
+                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
 
     def solve_adjoint(self, coef_bar):
         """Transpose of solve: coef_bar (nrhs, N, M) -> dict(f_I_bar (nrhs, N, n_int),

@@ -325,3 +325,39 @@ def test_mixed_precision_multi_rhs():
         ref = s.solve(f, tol=1e-13, maxit=20000)
         assert _rel(u[r], O.evaluate(geo, c.W, c.b, ref["c"], X)) < MIXED_TOL_MU
         assert _rel(out["mu_dl"][r].cpu().numpy(), ref["mu_dl"]) < MIXED_TOL_MU
+
+
+def test_cg_launch_autotuner_configurations_all_match_oracle(monkeypatch):
+    """The persistent CG's launch is tuned per problem shape (row slices per
+    subdomain, redundant or distributed coarse phases).  Every candidate the
+    tuner can pick solves the same system; the tuned choice is cached and
+    reported in the statistics."""
+    _torch()
+    c = Case(**CASES["4x3"], tol=1e-13)
+    geo, s = c.oracle()
+    ref = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-14, maxit=20000)
+    X = I.eval_grid(c.w)
+    u_ref = O.evaluate(geo, c.W, c.b, ref["c"], X)
+    for S in (1, 2, 4):
+        for dist in (0, 1):
+            monkeypatch.setenv("DDELM_CG_SLICES", str(S))
+            monkeypatch.setenv("DDELM_CG_COARSE", str(dist))
+            g = c.gpu().factor()
+            xB = g.boundary_points().cpu().numpy()
+            out = g.solve(I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None])
+            assert (out["stats"]["cg_slices"], out["stats"]["cg_coarse_dist"]) == (S, dist)
+            u = g.evaluate(out["coef"], X)[0].cpu().numpy()
+            assert _rel(u, u_ref) < 1e-10, (S, dist, _rel(u, u_ref))
+    monkeypatch.delenv("DDELM_CG_SLICES")
+    monkeypatch.delenv("DDELM_CG_COARSE")
+    picks = []
+    for _ in range(2):
+        g = c.gpu().factor()
+        xB = g.boundary_points().cpu().numpy()
+        out = g.solve(I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None])
+        st = out["stats"]
+        picks.append((st["cg_slices"], st["cg_coarse_dist"]))
+        assert st["cg_slices"] in (1, 2, 4) and st["cg_coarse_dist"] in (0, 1) and st["cg_blocks"] >= 1
+        u = g.evaluate(out["coef"], X)[0].cpu().numpy()
+        assert _rel(u, u_ref) < 1e-10
+    assert picks[0] == picks[1]          # cached for the shape
