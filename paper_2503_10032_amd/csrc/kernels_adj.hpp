@@ -15,6 +15,7 @@
 // S_theta and M are symmetric, so the transposed solve is one more CG with
 // the forward operator, and the M stage reuses the forward P kernels.
 #pragma once
+#include "tanh_fast.hpp"
 #include "kernels_rhs.hpp"
 
 namespace ddelm {
@@ -354,7 +355,7 @@ __global__ void __launch_bounds__(kBlock) k_eval_adj(int nx, int ny, int M, int 
       for (int q = 0; q < tot; ++q) {
         const long long pq = idx[q];
         const double xi0 = (x[2 * pq] - cx) / hx, xi1 = (x[2 * pq + 1] - cy) / hy;
-        const double t = tanh(w0 * xi0 + w1 * xi1 + bj);
+        const double t = tanh_fast(w0 * xi0 + w1 * xi1 + bj);
         acc += ubar[(size_t)r * npts + pq] * t;
         if (gbar) {
           const double dt = 1.0 - t * t;

@@ -2,6 +2,7 @@
 // evaluation kernels.  T is the storage type of the local factors (double,
 // or float in mixed precision); interface vectors are always double.
 #pragma once
+#include "tanh_fast.hpp"
 #include "kernels_qr.hpp"
 #include "kernels_solve.hpp"
 
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int 
   for (int k = 0; k < NRB; ++k) acc[k] = g0[k] = g1[k] = 0.0;
   for (int j = 0; j < M; ++j) {
     const double w0 = W[((size_t)i * M + j) * 2], w1 = W[((size_t)i * M + j) * 2 + 1];
-    const double t = tanh(w0 * xi0 + w1 * xi1 + bias[(size_t)i * M + j]);
+    const double t = tanh_fast(w0 * xi0 + w1 * xi1 + bias[(size_t)i * M + j]);
     const double dt = 1.0 - t * t;
 #pragma unroll
     for (int k = 0; k < NRB; ++k) {

@@ -1,6 +1,7 @@
 // Setup-time kernels: feature assembly, batched Householder QR, triangular
 // solves, small batched GEMMs, coarse assembly, Cholesky and inverse.
 #pragma once
+#include "tanh_fast.hpp"
 #include "geometry.hpp"
 #include "kernels_common.hpp"
 
@@ -49,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   double acc = 0.0;
   if (r < a.lead) {            // interior row: -Laplace(phi) at the interior point
     const double px = a.xint[((size_t)i * a.lead + r) * 2], py = a.xint[((size_t)i * a.lead + r) * 2 + 1];
-    const double t = tanh(w0 * ((px - cx) / hx) + w1 * ((py - cy) / hy) + bj);
+    const double t = tanh_fast(w0 * ((px - cx) / hx) + w1 * ((py - cy) / hy) + bj);
     const double v = 2.0 * t * (1.0 - t * t) * lap;
     out[a.off[i] + (long long)j * a.ld[i] + r] = (T)v;
     return;
@@ -59,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
     const Term tm = a.terms[q];
     const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
-    const double t = tanh(z);
+    const double t = tanh_fast(z);
     const double dt = 1.0 - t * t;
     double v;
     if (tm.op == OP_VALUE) v = t;
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(kBlock) k_features_long(FeatArgs a, const int*
   for (int q = a.ptr[row] + lane; q < a.ptr[row + 1]; q += 64) {
     const Term tm = a.terms[q];
     const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
-    const double t = tanh(z);
+    const double t = tanh_fast(z);
     const double dt = 1.0 - t * t;
     double v;
     if (tm.op == OP_VALUE) v = t;
