@@ -394,7 +394,7 @@ struct ddelm_ctx_s {
   DBuf<int> f_ld, f_cn;
   DBuf<double> s_loc, l_loc, rho_loc, psi_loc, lam_loc, y_loc, z_loc, t_loc, nu_loc, w_loc, c1, c2, pif;
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
-  DBuf<double> cg_r1, cg_s1, cg_uv;    // second r and s buffers, u = A r of the persistent CG
+  DBuf<double> cg_r1, cg_s1;    // second r and s buffers of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
   int cg_blocks = 0, cg_slices = 0, cg_dist = 0;   // launch shape of the last persistent CG
   // refinement workspaces (mixed precision)
@@ -605,12 +605,11 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   c->cg_c.alloc(C);
   c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
   const size_t V = (size_t)nrhs * std::max(c->nD, 1);
-  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1,
-                          &c->cg_uv})
+  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1})
     b->alloc(V);
   c->mu_slot.alloc(P);
   c->e_slot.alloc(P);
-  c->cg_part.alloc((size_t)2 * nrhs * 4096);
+  c->cg_part.alloc((size_t)3 * nrhs * 4096);
   c->cg_scal.alloc((size_t)nrhs * 8);
   for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc, &c->rho_loc,
                           &c->psi_loc, &c->nu_loc, &c->c1, &c->c2, &c->pif, &c->mu_slot, &c->e_slot})
@@ -734,7 +733,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int ma
   f.tol = tol;
   f.maxit = maxit;
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
-  f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p; f.u = c->cg_uv.p;
+  f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
   f.err = c->flags.p;
   const int xs = std::max(g.max_nD, 1) * NR;

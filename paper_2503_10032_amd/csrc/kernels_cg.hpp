@@ -7,12 +7,15 @@
 //
 // The iteration is the Chronopoulos-Gear form of CG (one operator
 // application and one fused reduction per step, see below).  Per pass
-// (theta != 0) the phases are separated by 7 grid-wide synchronisations:
-//   A  CG update at the unit's Delta points; rows of [G; L](:, Delta) r
+// (theta != 0) the phases are separated by 6 grid-wide synchronisations:
+//   A  CG update at the unit's Delta points (u = A r of the pass before as
+//      the sum of its owners' rows); rows of [G; L](:, Delta) r; partial (r, r)
 //   B  coarse solve at the subdomain's corners (mu_Pi, e), lam rows
 //   C  y = -N lambda rows               D  z = -N^T (P lambda) rows
-//   E  eta, rows of L^T(:, Delta) eta   F  coarse nu at the corners, u rows
-//   G  u = A r as the sum of owners (stored), partial (r, r) and (u, r)
+//   E  eta, rows of L^T(:, Delta) eta
+//   F  coarse nu at the corners, rows of u = A r; partial (u, r)
+// (u, r) needs no assembled u: it is the sum over subdomains of each
+// subdomain's rows of u times r at the same points.
 // With few coarse unknowns the coarse solves are done redundantly by every
 // unit for its own corners (rows of X1 against the full coarse right-hand
 // side), which removes synchronisations.  With many (nP * nrhs large) every
@@ -90,8 +93,7 @@ struct FusedArgs {
   double* p1;
   double* s0;            // [nrhs][nD] s = A p buffers (alternate by pass)
   double* s1;
-  double* u;             // [nrhs][nD] u = A r of the pass (sum of owners, stored by the reduction phase)
-  double* part;          // [2][nrhs][nb]
+  double* part;          // [3][nrhs][nb] workgroup partials: (u, r); (r, r) of even and of odd passes
   double* mu_slot;       // [nrhs][sumP]  mu_Pi at the corner slots
   double* e_slot;        // [nrhs][sumP]
   double* scal;          // [nrhs][8] out: rr, bb, -, -, -, done, iters, nonfinite
@@ -380,6 +382,26 @@ __device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slo
   }
 }
 
+// Sum over the workgroup of one value per thread, split by right-hand side:
+// out[c] is the sum over the threads with threadIdx.x % NV == c (NV divides
+// 64).  `red` must hold kWaves * NV values; every thread gets the results.
+template <int NV>
+__device__ __forceinline__ void block_sum_mod(double v, double* out, double* red) {
+#pragma unroll
+  for (int o = 32; o >= NV; o >>= 1) v += __shfl_xor(v, o, 64);   // lanes keep their residue mod NV
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane < NV) red[wid * NV + lane] = v;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double t = red[c];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t += red[w * NV + c];
+    out[c] = t;
+  }
+}
+
 // gather_dl with the owner slots read from the LDS table of the unit
 template <int NR>
 __device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const double* A, const double* B, double ca,
@@ -509,7 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
         double vg[NR], vd[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          vg[r] = r < nrhs ? ld_co(&f.part[(size_t)(nrhs + r) * nb + k]) : 0.0;
+          vg[r] = r < nrhs ? ld_co(&f.part[(size_t)((1 + ((it - 1) & 1)) * nrhs + r) * nb + k]) : 0.0;
           vd[r] = r < nrhs ? ld_co(&f.part[(size_t)r * nb + k]) : 0.0;
         }
 #pragma unroll
@@ -556,6 +578,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     double* s_new = odd ? f.s0 : f.s1;
 
     // ---- A: CG update at the unit's Delta points, rows of [G; L](:, Delta) r_it
+    // (every thread's elements belong to the right-hand side threadIdx.x % NR)
+    double gacc = 0.0;
     for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
       const bool use_tab = t < f.tab_units;
       const int i = u / f.S, q = u % f.S;
@@ -566,23 +590,31 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       slice_rows(ng, f.S, q, r0, r1);
       constexpr int kLA = NR >= 4 ? 4 : NR;   // elements per thread whose loads are issued together
       for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLA * kBlock) {
-        double rv[kLA], pv[kLA], sv[kLA], uv[kLA];
+        double rv[kLA], pv[kLA], sv[kLA], wv[kLA][kMaxOwn];
         int gg[kLA];
         bool own[kLA];
 #pragma unroll
         for (int v = 0; v < kLA; ++v) {
           const int e = e0 + v * kBlock, k = e / NR, r = e % NR;
-          rv[v] = pv[v] = sv[v] = uv[v] = 0.0;
+          rv[v] = pv[v] = sv[v] = 0.0;
+#pragma unroll
+          for (int o = 0; o < kMaxOwn; ++o) wv[v][o] = 0.0;
           gg[v] = 0;
           own[v] = false;
           if (e < nd * NR && r < nrhs) {
+            int so[kMaxOwn];
             if (use_tab) {
               const int tv = tg[t * f.tab_nd + k];
               gg[v] = tv & ~kOwnerFlag;
               own[v] = (tv & kOwnerFlag) != 0;
+              const int4 sl = tab_slots(tsl + 4 * t * f.tab_nd, k);
+              so[0] = sl.x; so[1] = sl.y; so[2] = sl.z; so[3] = sl.w;
             } else {
               gg[v] = a.dl_l2g[d0 + k];
-              own[v] = a.dl_own_slot[a.dl_own_ptr[gg[v]]] == d0 + k;
+              const int o0 = a.dl_own_ptr[gg[v]], cnt = a.dl_own_ptr[gg[v] + 1] - o0;
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) so[o] = o < cnt ? a.dl_own_slot[o0 + o] : -1;
+              own[v] = so[0] == d0 + k;
             }
             const size_t ge = (size_t)r * a.nD + gg[v];
             // (source chosen before the load: alternative loads into one register wait on each other)
@@ -590,7 +622,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
             if (it != 0) {
               pv[v] = ld_co(&p_old[ge]);
               sv[v] = ld_co(&s_old[ge]);
-              uv[v] = ld_co(&f.u[ge]);
+              // u_{it-1} at the point: the owners' rows from phase F of the pass before
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o)
+                if (so[o] >= 0) wv[v][o] = ld_co(&a.w_loc[(size_t)r * a.sumD + so[o]]);
             }
           }
         }
@@ -603,7 +638,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
             if (it == 0) {
               x = rv[v];
             } else {
-              const double uu = uv[v];
+              double uu = 0.0;
+#pragma unroll
+              for (int o = 0; o < kMaxOwn; ++o) uu += wv[v][o];
               const double be = sc_beta[r], al = sc_alpha[r];
               const double pn = rv[v] + be * pv[v];
               const double sn = uu + be * sv[v];
@@ -616,6 +653,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
                 st_co(&f.x[ge], ld_co(&f.x[ge]) + al * pn);
               }
             }
+            if (q == 0 && own[v]) gacc += x * x;
           }
           xs[e] = x;
         }
@@ -636,6 +674,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
         }
       }
       __syncthreads();
+    }
+    {
+      double tot[NR];
+      block_sum_mod<NR>(gacc, tot, redv);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)((1 + (it & 1)) * nrhs + r) * nb + blockIdx.x], tot[r]);
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
 
@@ -808,7 +853,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
 
-    // ---- F: coarse nu at the corners, w rows
+    // ---- F: coarse nu at the corners, rows of u = A r_it; partial (u, r_it)
+    double dacc = 0.0;    // right-hand side threadIdx.x % NR
     if (f.dist) {
       coarse_gather(a, a.nu_loc, (const double*)nullptr, nrhs, f.ug);
       flag_sync(f.flags, nb, ++epoch, f.err);
@@ -868,74 +914,50 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       slice_rows(nd, f.S, q, r0, r1);
       const T* G = a.Gm + a.offG[i];
       const T* LT = a.LTm + a.offG[i];
-      for (int e0 = threadIdx.x; e0 < (r1 - r0) * nrhs; e0 += kLB * kBlock) {
-        double sv[kLB], tv[kLB];
+      const int nrow = (r1 - r0) * NR;
+      for (int e0 = threadIdx.x; e0 < nrow; e0 += kLB * kBlock) {
+        double sv[kLB], tv[kLB], rc[kLB];
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock;
+          const int e = e0 + u * kBlock, r = e % NR;
           sv[u] = 0.0;
           tv[u] = 0.0;
-          if (e < (r1 - r0) * nrhs) {
-            const size_t el = (size_t)(e % nrhs) * a.sumD + d0 + r0 + e / nrhs;
+          rc[u] = 0.0;
+          if (e < nrow && r < nrhs) {
+            const int k = r0 + e / NR;
+            const size_t el = (size_t)r * a.sumD + d0 + k;
+            const int g = use_tab ? tg[t * f.tab_nd + k] & ~kOwnerFlag : a.dl_l2g[d0 + k];
             sv[u] = ld_co(&a.s_loc[el]);
             tv[u] = ld_co(&a.t_loc[el]);
+            rc[u] = ld_co(&r_cur[(size_t)r * a.nD + g]);
           }
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock;
-          if (e >= (r1 - r0) * nrhs) continue;
-          const int row = r0 + e / nrhs, r = e % nrhs;
+          const int e = e0 + u * kBlock, r = e % NR;
+          if (e >= nrow || r >= nrhs) continue;
+          const int row = r0 + e / NR;
           double acc = sv[u] + tv[u];
           for (int b = 0; b < np; ++b) {
             acc -= (double)G[(long long)b * ng + np + row] * (cms[0][b][r] + cor[0][b][r]);
             acc += (double)LT[(long long)b * ng + np + row] * (cms[1][b][r] + cor[1][b][r]);
           }
           st_co(&a.w_loc[(size_t)r * a.sumD + d0 + row], acc);
+          dacc += acc * rc[u];
         }
       }
       __syncthreads();
     }
-    flag_sync(f.flags, nb, ++epoch, f.err);
-
-    // ---- G: u_it = sum of owners; partial gamma_it = (r_it, r_it), delta_it = (u_it, r_it)
     {
-      double accg[NR], accd[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) accg[r] = accd[r] = 0.0;
-      for (int g = blockIdx.x * kBlock + threadIdx.x; g < a.nD; g += nb * kBlock) {
-        const int o0 = a.dl_own_ptr[g], cnt = a.dl_own_ptr[g + 1] - o0;
-        double wv[NR][kMaxOwn], rv[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-#pragma unroll
-          for (int o = 0; o < kMaxOwn; ++o)
-            wv[r][o] = (r < nrhs && o < cnt) ? ld_co(&a.w_loc[(size_t)r * a.sumD + a.dl_own_slot[o0 + o]]) : 0.0;
-          rv[r] = r < nrhs ? ld_co(&r_cur[(size_t)r * a.nD + g]) : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (r >= nrhs) continue;
-          double uu = 0.0;
-#pragma unroll
-          for (int o = 0; o < kMaxOwn; ++o) uu += wv[r][o];
-          st_co(&f.u[(size_t)r * a.nD + g], uu);
-          accg[r] += rv[r] * rv[r];
-          accd[r] += uu * rv[r];
-        }
-      }
-      double totg[NR], totd[NR];
-      block_sum_vec<double, NR>(accg, totg, redv);
-      block_sum_vec<double, NR>(accd, totd, redv);
+      double tot[NR];
+      block_sum_mod<NR>(dacc, tot, redv);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) {
-          st_co(&f.part[(size_t)(nrhs + r) * nb + blockIdx.x], totg[r]);
-          st_co(&f.part[(size_t)r * nb + blockIdx.x], totd[r]);
-        }
+        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], tot[r]);
     }
     flag_sync(f.flags, nb, ++epoch, f.err);
   }
+
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (int r = 0; r < nrhs; ++r) {
       double* sc = f.scal + (size_t)r * 8;
