@@ -196,6 +196,11 @@ void dev_free(void* p, size_t cap) {
   else (void)hipFree(p);      // outside any context call: free for good (synchronises)
 }
 
+// Host-to-device copy through the pinned staging buffer of the running call's
+// context (asynchronous, the host does not wait); false when there is none
+// or it is full, and the caller copies from pageable memory instead.
+bool stage_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
@@ -216,7 +221,8 @@ struct DBuf {
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     alloc(h.size());
-    if (!h.empty()) HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (h.empty() || stage_upload(p, h.data(), h.size() * sizeof(T), s)) return;
+    HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   }
   void zero(hipStream_t s) {
     if (n) HIPCHK(hipMemsetAsync(p, 0, n * sizeof(T), s));
@@ -291,8 +297,29 @@ struct Arena {
   }
   template <typename T>
   T* put(const std::vector<T>& v, hipStream_t s) { return put(v.data(), v.size(), s); }
+  // copy `bytes` from src to the device address dst through the pinned buffer
+  bool stage(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const size_t off = (used + 255) & ~size_t(255);
+    if (!host || off + bytes > cap) return false;
+    std::memcpy(host + off, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, host + off, bytes, hipMemcpyHostToDevice, s));
+    used = off + bytes;
+    return true;
+  }
   ~Arena() { release(); }
 };
+
+// Pinned staging of table uploads for the context whose call is running
+// (reset with the descriptor arena, after the stream has drained).
+thread_local Arena* tl_upload = nullptr;
+struct UploadScope {
+  Arena* prev;
+  explicit UploadScope(Arena* a) : prev(tl_upload) { tl_upload = a; }
+  ~UploadScope() { tl_upload = prev; }
+};
+bool stage_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  return tl_upload && tl_upload->stage(dst, src, bytes, s);
+}
 
 __host__ __device__ inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
@@ -385,6 +412,7 @@ struct ddelm_ctx_s {
   // coarse (always float64)
   DBuf<double> Spi, Sfac, Sinv, Dpp, Gs, Zm, Ztm, Wm, X1, X1t;
   DBuf<unsigned> flags;                // [0] barrier expired (1) / Cholesky (2)
+  DBuf<unsigned> chk;                  // setup: lowest subdomain with an interior point outside it
   // indexing on device
   DBuf<int> pi_off, dl_off, pi_l2g, dl_l2g, pi_own_ptr, pi_own_slot, dl_own_ptr, dl_own_slot, pi_slot_sub;
   DBuf<int> nG_dev;
@@ -409,6 +437,7 @@ struct ddelm_ctx_s {
   DBuf<unsigned> bar;
   DBuf<int> sizes_dev;                 // per subdomain M, n_I, n_B, m, n_G
   Arena arena;
+  Arena upload;     // pinned staging of table uploads (its device half is unused)
   DBuf<long long> offm_d, offB_d, offQG_d, offAm_d;
   // phase timing (HIP events on the stream)
   hipEvent_t ev[10] = {};
@@ -438,6 +467,7 @@ struct ddelm_ctx_s {
       R.streams.push_back({device, side});
     }
     arena.retire();
+    upload.retire();
   }
   // event k of the cross-stream ordering pool (timing disabled)
   hipEvent_t sev(size_t k) {
@@ -463,6 +493,7 @@ template <typename F>
 ddelm_status run_guarded(ddelm_ctx c, F&& fn) {
   BlocksScope scope(c ? c->blocks : nullptr);
   StreamScope sscope(c ? c->stream : nullptr);
+  UploadScope uscope(c ? &c->upload : nullptr);
   try {
     fn();
     return DDELM_OK;
@@ -1515,6 +1546,7 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
     alloc_adjoint_workspace(c, nrhs);
     HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
+    c->upload.reset();
     c->phase_ms[4] = c->phase_ms[5] = c->phase_ms[6] = 0.0;
     auto acc = [&](const CoreOut& o) {
       st.iters += o.iters;
@@ -1667,11 +1699,8 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
       c->fail(DDELM_E_SHAPE, "nx, ny out of range");
     if (prob->n_int < 1) c->fail(DDELM_E_SHAPE, "n_int must be >= 1");
     c->N = N; c->M = prob->M; c->n_int = prob->n_int;
-    std::vector<double> xint((size_t)N * prob->n_int * 2);
-    HIPCHK(hipMemcpyAsync(xint.data(), prob->x_int, xint.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
     std::string e = c->geo.build(prob->nx, prob->ny, prob->lo, prob->hi, prob->p, prob->edge_s, prob->n_extra,
-                                 prob->extra_s, prob->n_int, xint, o.coarse);
+                                 prob->extra_s, prob->n_int, o.coarse);
     if (!e.empty()) c->fail(DDELM_E_SHAPE, e);
     Geometry& g = c->geo;
     c->nP = g.n_pi; c->nD = g.n_dl;
@@ -1695,18 +1724,39 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     }
     c->summ = c->h_offm[N];
     hipStream_t s = c->stream;
+    {
+      // pinned staging for the table uploads below (the host does not wait for them)
+      size_t need = (size_t)1 << 20;
+      for (const RowSet* r : {&g.rowsK, &g.rowsA, &g.rowsKb, &g.rowsAb})
+        need += sizeof(int) * (r->row0.size() + 3 * r->ptr.size()) + sizeof(Term) * r->terms.size();
+      need += sizeof(double) * 8 * (size_t)N +
+              sizeof(int) * (16 * (size_t)N + g.pi_loc2glob.size() + g.dl_loc2glob.size() + g.pi_own_slot.size() +
+                             g.dl_own_slot.size() + g.pi_own_ptr.size() + g.dl_own_ptr.size() + (size_t)c->sumP);
+      c->upload.ensure(need);
+    }
     // problem copies
     c->W.alloc((size_t)N * c->M * 2);
     HIPCHK(hipMemcpyAsync(c->W.p, prob->W, c->W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     c->b.alloc((size_t)N * c->M);
     HIPCHK(hipMemcpyAsync(c->b.p, prob->b, c->b.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    c->x_int.upload(xint, s);
-    std::vector<double> geom(4 * (size_t)N);
+    c->x_int.alloc((size_t)N * prob->n_int * 2);
+    HIPCHK(hipMemcpyAsync(c->x_int.p, prob->x_int, c->x_int.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<double> geom(8 * (size_t)N);   // centre and half widths, then the closed boxes
     for (int i = 0; i < N; ++i) {
       geom[4 * i] = g.subs[i].cx; geom[4 * i + 1] = g.subs[i].cy;
       geom[4 * i + 2] = g.subs[i].hx; geom[4 * i + 3] = g.subs[i].hy;
+      g.box(i, &geom[4 * ((size_t)N + i)]);
     }
     c->geom.upload(geom, s);
+    // interior points inside their subdomains, checked on the device (read back at the end of setup)
+    c->chk.alloc(1);
+    HIPCHK(hipMemsetAsync(c->chk.p, 0xFF, sizeof(unsigned), s));
+    {
+      const long long npt = (long long)N * prob->n_int;
+      const unsigned nblk = (unsigned)std::min<long long>(ceil_div(npt, (long long)kBlock), 1024);
+      k_check_interior<<<nblk, kBlock, 0, s>>>(c->x_int.p, c->geom.p + 4 * (size_t)N, N, prob->n_int, c->chk.p);
+      HIPCHK(hipGetLastError());
+    }
     c->rsK.upload(g.rowsK, s); c->rsA.upload(g.rowsA, s); c->rsKb.upload(g.rowsKb, s); c->rsAb.upload(g.rowsAb, s);
     c->sizes_dev.upload(sizes, s);
     c->pi_off.upload(g.pi_off, s); c->dl_off.upload(g.dl_off, s);
@@ -1728,7 +1778,11 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     c->flags.zero(s);
     c->bar.alloc((size_t)4096 * kFlagStride);
     c->bar.zero(s);
+    unsigned first_bad = 0;
+    HIPCHK(hipMemcpyAsync(&first_bad, c->chk.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (first_bad != 0xFFFFFFFFu)
+      c->fail(DDELM_E_SHAPE, "interior point outside its subdomain (subdomain " + std::to_string(first_bad) + ")");
   });
   if (st != DDELM_OK) {
     // keep the context only to report the error through ddelm_last_error
@@ -1745,6 +1799,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
     if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->arena.reset();
+    c->upload.reset();
     c->factored = false;
     if (c->mixed) factor_impl<float>(c);
     else factor_impl<double>(c);
@@ -1772,6 +1827,7 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
     alloc_solve_workspace(c, nrhs);
     HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
+    c->upload.reset();
     c->phase_ms[4] = c->phase_ms[5] = c->phase_ms[6] = 0.0;
     auto acc = [&](const CoreOut& o) {
       st.iters += o.iters;
@@ -2048,6 +2104,7 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
     hipStream_t s = c->stream;
     HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
+    c->upload.reset();
     if (which <= 3) {
       DBuf<double> tmp;
       tmp.alloc((size_t)R * C);

@@ -34,8 +34,7 @@ struct SideDesc {
 }  // namespace
 
 std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* hi_, int p_,
-                            const double* edge_s, int n_extra, const double* extra_s, int n_int,
-                            const std::vector<double>& x_int, int coarse_) {
+                            const double* edge_s, int n_extra, const double* extra_s, int n_int, int coarse_) {
   nx = nx_; ny = ny_; N = nx * ny; p = p_; coarse = coarse_;
   if (nx < 1 || ny < 1) return "nx, ny must be >= 1";
   if ((long long)nx * ny > (1 << 20)) return "too many subdomains";
@@ -126,12 +125,6 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
       sb.hx = 0.5 * h[0];
       sb.hy = 0.5 * h[1];
       sb.n_I = n_int;
-      // interior points must lie in the closed subdomain box
-      for (int k = 0; k < n_int; ++k) {
-        double x = x_int[((size_t)i * n_int + k) * 2], y = x_int[((size_t)i * n_int + k) * 2 + 1];
-        if (x < vx(ix) || x > vx(ix + 1) || y < vy(iy) || y > vy(iy + 1))
-          return "interior point outside its subdomain (subdomain " + std::to_string(i) + ")";
-      }
       SideDesc sds[4];
       for (int sd = 0; sd < 4; ++sd) sds[sd] = side_desc(ix, iy, sd);
       // ---- boundary points

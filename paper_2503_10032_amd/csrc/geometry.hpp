@@ -77,8 +77,13 @@ struct Geometry {
 
   // Returns an empty string on success, else an error message.
   std::string build(int nx, int ny, const double* lo, const double* hi, int p, const double* edge_s,
-                    int n_extra, const double* extra_s, int n_int, const std::vector<double>& x_int,
-                    int coarse);
+                    int n_extra, const double* extra_s, int n_int, int coarse);
+  // closed box [x0, x1] x [y0, y1] of subdomain i (the lattice lines, as the rows use them)
+  void box(int i, double* b) const {
+    const int ix = i % nx, iy = i / nx;
+    b[0] = lo[0] + ix * h[0]; b[1] = lo[0] + (ix + 1) * h[0];
+    b[2] = lo[1] + iy * h[1]; b[3] = lo[1] + (iy + 1) * h[1];
+  }
 };
 
 }  // namespace ddelm

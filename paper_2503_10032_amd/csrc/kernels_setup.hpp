@@ -301,6 +301,21 @@ __global__ void __launch_bounds__(kBlock) k_copy2d(const CopyDesc* __restrict__ 
   }
 }
 
+// Interior points must lie in the closed box of their subdomain
+// (box[4 i .. 4 i + 3] = x0, x1, y0, y1); *first_bad becomes the lowest
+// subdomain index with a point outside (or a NaN coordinate).  It starts at
+// 0xffffffff.
+__global__ void k_check_interior(const double* __restrict__ x, const double* __restrict__ box, int N, int n_int,
+                                 unsigned* __restrict__ first_bad) {
+  const long long n = (long long)N * n_int;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const int i = (int)(e / n_int);
+    const double px = x[2 * e], py = x[2 * e + 1];
+    const double* b = box + 4 * (size_t)i;
+    if (!(px >= b[0] && px <= b[1] && py >= b[2] && py <= b[3])) atomicMin(first_bad, (unsigned)i);
+  }
+}
+
 __global__ void k_fill(double* __restrict__ p, long long n, double v) {
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
 }

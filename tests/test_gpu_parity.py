@@ -242,6 +242,23 @@ def test_solve_before_factor_is_a_state_error():
         g.solve(np.zeros((1, c.w.N, c.xi.shape[1])), np.zeros((1, g.sizes.sum_nB)))
 
 
+def test_interior_point_outside_its_subdomain_is_a_shape_error():
+    from paper_2503_10032_amd import DDELMSolver
+    from paper_2503_10032_amd.solver import DDELMError
+    c = Case(**CASES["4x3"])
+    w = c.w
+    ok = c.xi.copy()
+    ok[2, 0] = (0.5, 0.0)                 # the lower-left corner of subdomain 2's closed box
+    ok[6, 1] = (0.75, 2.0 / 3.0)          # the upper-right corner of subdomain 6's
+    _torch()
+    DDELMSolver(w.nx, w.ny, w.M, c.W, c.b, ok, c.s, c.se).close()
+    bad = c.xi.copy()
+    bad[9, 3] = (np.nan, 0.5)
+    bad[5, 2] = c.xi[0, 0]                # a point of subdomain 0 given to subdomain 5
+    with pytest.raises(DDELMError, match=r"SHAPE.*outside its subdomain \(subdomain 5\)"):
+        DDELMSolver(w.nx, w.ny, w.M, c.W, c.b, bad, c.s, c.se)
+
+
 def test_noconvergence_is_reported():
     c = Case(**CASES["small"], tol=1e-13)
     g = c.gpu(maxit=2).factor()
