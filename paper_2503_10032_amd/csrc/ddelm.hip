@@ -532,8 +532,8 @@ void gemm_batch(ddelm_ctx c, const std::vector<GemmDesc>& h, const T* A, const T
   for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
   if (mm == 0 || nn == 0) return;
   const GemmDesc* d = c->arena.put(h, c->stream);
-  dim3 grid(ceil_div(mm, 16), ceil_div(nn, 16), (unsigned)h.size());
-  k_gemm<T, T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  dim3 grid(ceil_div(mm, kGT), ceil_div(nn, kGT), (unsigned)h.size());
+  k_gemm_mfma<T, T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
   HIPCHK(hipGetLastError());
 }
 
@@ -546,8 +546,8 @@ void gemm_batch_mixed(ddelm_ctx c, const std::vector<GemmDesc>& h, const TA* A, 
   for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
   if (mm == 0 || nn == 0) return;
   const GemmDesc* d = c->arena.put(h, c->stream);
-  dim3 grid(ceil_div(mm, 16), ceil_div(nn, 16), (unsigned)h.size());
-  k_gemm<TA, TB, TC><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  dim3 grid(ceil_div(mm, kGT), ceil_div(nn, kGT), (unsigned)h.size());
+  k_gemm_mfma<TA, TB, TC><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
   HIPCHK(hipGetLastError());
 }
 

@@ -569,6 +569,71 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
 
 namespace ddelm {
 
+// Batched C = alpha op(A) B + beta C on f64 MFMA (operands of any storage
+// type are widened to double).  One workgroup per 32 x 32 tile of C (each
+// wave a 16 x 16 quarter), k in chunks of 32 staged through LDS, the next
+// chunk's loads issued before the current chunk's products.
+constexpr int kGT = 32;
+template <typename TA, typename TB, typename TC>
+__global__ void __launch_bounds__(kBlock) k_gemm_mfma(const GemmDesc* __restrict__ desc, const TA* __restrict__ A,
+                                                      const TB* __restrict__ B, TC* __restrict__ C, int transA,
+                                                      double alpha, double beta) {
+  typedef Mfma<double>::v4 v4;
+  const GemmDesc g = desc[blockIdx.z];
+  const int row0 = blockIdx.x * kGT, col0 = blockIdx.y * kGT;
+  if (row0 >= g.m || col0 >= g.n) return;
+  __shared__ double As[kGT][kGT + 1];   // As[k][row]
+  __shared__ double Bs[kGT][kGT + 1];   // Bs[col][k]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = wv & 1, wc = wv >> 1;
+  constexpr int kPer = kGT * kGT / kBlock;   // elements of each operand per thread and chunk
+  double av[kPer], bv[kPer];
+  // element u of this thread: A along rows (transA = 0) or along k (transA = 1), B along k
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int lo = e % kGT, hi = e / kGT;
+      const int r = transA ? hi : lo, kk = transA ? lo : hi;
+      const int rg = row0 + r, kg = k0 + kk;
+      const long long ia = transA ? g.a + (long long)rg * g.lda + kg : g.a + (long long)kg * g.lda + rg;
+      av[u] = (rg < g.m && kg < g.k) ? (double)A[ia] : 0.0;
+      const int cg = col0 + hi, kb = k0 + lo;
+      bv[u] = (cg < g.n && kb < g.k) ? (double)B[g.b + (long long)cg * g.ldb + kb] : 0.0;
+    }
+  };
+  v4 acc = v4{0, 0, 0, 0};
+  load(0);
+  for (int k0 = 0; k0 < g.k; k0 += kGT) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int lo = e % kGT, hi = e / kGT;
+      if (transA) As[lo][hi] = av[u];
+      else As[hi][lo] = av[u];
+      Bs[hi][lo] = bv[u];
+    }
+    __syncthreads();
+    if (k0 + kGT < g.k) load(k0 + kGT);
+#pragma unroll
+    for (int ks = 0; ks < kGT / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      acc = Mfma<double>::mma(As[kk][16 * wr + (lane & 15)], Bs[16 * wc + (lane & 15)][kk], acc);
+    }
+    __syncthreads();
+  }
+  const int col = col0 + 16 * wc + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = row0 + 16 * wr + Mfma<double>::drow(lane, v);
+    if (row < g.m && col < g.n) {
+      TC* cp = C + g.c + (long long)col * g.ldc + row;
+      const double prev = beta != 0.0 ? (double)*cp : 0.0;
+      *cp = (TC)(alpha * acc[v] + beta * prev);
+    }
+  }
+}
+
 // Q^T C (transT = 1, blocks in order) or Q C (transT = 0, blocks reversed)
 // for a few columns (ncols <= NR <= 4), one workgroup per matrix applying
 // every 64-reflector block in one launch.  The columns stay in LDS for the

@@ -234,47 +234,13 @@ __global__ void __launch_bounds__(kBlock, 4) k_trsm(const QRDesc* __restrict__ d
 // ---------------------------------------------------------------- batched GEMM
 //
 // C = alpha * op(A) * B + beta * C, all column-major; op(A) = A (m x k) or
-// A^T (A stored k x m).  16 x 16 output tile per workgroup.
+// A^T (A stored k x m).  The kernel (k_gemm_mfma) is with the other MFMA
+// kernels.
 struct GemmDesc {
   long long a, b, c;     // element offsets
   int lda, ldb, ldc;
   int m, n, k;
 };
-
-template <typename TA, typename TB, typename TC>
-__global__ void __launch_bounds__(kBlock) k_gemm(const GemmDesc* __restrict__ desc, const TA* __restrict__ A,
-                                                 const TB* __restrict__ B, TC* __restrict__ C, int transA,
-                                                 double alpha, double beta) {
-  const GemmDesc g = desc[blockIdx.z];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int row = blockIdx.x * 16 + tx, col = blockIdx.y * 16 + ty;
-  if (blockIdx.x * 16 >= g.m || blockIdx.y * 16 >= g.n) return;
-  __shared__ double As[16][17], Bs[16][17];
-  double acc = 0.0;
-  for (int k0 = 0; k0 < g.k; k0 += 16) {
-    // As[kk][rr] = op(A)[row0 + rr][k0 + kk]
-    {
-      const int rr = tx, kk = ty;
-      const int r = blockIdx.x * 16 + rr, kx = k0 + kk;
-      // the address is chosen before the load (two alternative loads would wait on each other)
-      const long long ia = transA ? g.a + (long long)r * g.lda + kx : g.a + (long long)kx * g.lda + r;
-      const double v = (r < g.m && kx < g.k) ? (double)A[ia] : 0.0;
-      As[kk][rr] = v;
-      const int cc = ty, kb = tx;
-      const int cgl = blockIdx.y * 16 + cc, kbx = k0 + kb;
-      Bs[cc][kb] = (cgl < g.n && kbx < g.k) ? (double)B[g.b + (long long)cgl * g.ldb + kbx] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc += As[kk][tx] * Bs[ty][kk];
-    __syncthreads();
-  }
-  if (row < g.m && col < g.n) {
-    TC* cp = C + g.c + (long long)col * g.ldc + row;
-    const double prev = beta != 0.0 ? (double)*cp : 0.0;
-    *cp = (TC)(alpha * acc + beta * prev);
-  }
-}
 
 // ---------------------------------------------------------------- small helpers
 
