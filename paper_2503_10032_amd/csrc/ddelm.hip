@@ -1264,7 +1264,7 @@ void launch_apply_narrow(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
   const size_t smem = (size_t)std::max(c->geo.max_m, 1) * NR * sizeof(T);
   const void* fn = (const void*)k_qr_apply_narrow<T, NR>;
   if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  k_qr_apply_narrow<T, NR><<<c->N, kBlock, smem, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, c->nblock, L.F.p, c->f_off.p,
+  k_qr_apply_narrow<T, NR><<<c->N, an_threads(NR), smem, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, c->nblock, L.F.p, c->f_off.p,
                                                       c->f_ld.p, nrhs, transT);
   HIPCHK(hipGetLastError());
 }

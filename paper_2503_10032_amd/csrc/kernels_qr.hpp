@@ -635,51 +635,57 @@ __global__ void __launch_bounds__(kBlock) k_gemm_mfma(const GemmDesc* __restrict
 }
 
 // Q^T C (transT = 1, blocks in order) or Q C (transT = 0, blocks reversed)
-// for a few columns (ncols <= NR <= 4), one workgroup per matrix applying
-// every 64-reflector block in one launch.  The columns stay in LDS for the
-// whole launch; per block: W = V^T C (wave w takes reflectors 16w..16w+15,
-// lanes the rows), W <- -T^T W or -T W, then C += V W (threads take rows).
+// for a few columns (ncols <= NR <= 4), one workgroup of an_threads(NR)
+// threads per matrix applying every 64-reflector block in one launch.  The
+// columns stay in LDS for the whole launch; per block: W = V^T C (wave w
+// takes reflectors 16 (w % 4) .. + 15 and the 128-row chunks w / 4 modulo
+// the number of row groups, lanes the rows; the groups' sums are added in
+// LDS), W <- -T^T W or -T W, then C += V W (threads take rows).  Two row
+// groups (512 threads) where the registers allow it.
+__host__ __device__ constexpr int an_threads(int nr) { return nr <= 2 ? 512 : 256; }
 template <typename T, int NR>
-__global__ void __launch_bounds__(kBlock) k_qr_apply_narrow(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+__global__ void __launch_bounds__(an_threads(NR)) k_qr_apply_narrow(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                             const T* __restrict__ Tbig, int nblock, T* __restrict__ C,
                                                             const long long* __restrict__ coff,
                                                             const int* __restrict__ ldc, int ncols, int transT) {
   extern __shared__ unsigned char smem_raw[];
   T* cs = reinterpret_cast<T*>(smem_raw);          // [m][NR]
   __shared__ T Ts[kBB][kBB + 1];
-  __shared__ T Ws[kBB][NR];
+  constexpr int kAN = an_threads(NR), kRG = kAN / 256;   // threads, row groups
+  __shared__ T Ws[kRG][kBB][NR];
   __shared__ T Wn[kBB][NR];
   const QRDesc d = desc[blockIdx.x];
   const int m = d.m, L = ldc[blockIdx.x];
   T* Cm = C + coff[blockIdx.x];
   const T* Am = A + d.off;
-  for (int e = threadIdx.x; e < m * NR; e += kBlock) {
+  for (int e = threadIdx.x; e < m * NR; e += kAN) {
     const int c = e / m, r = e % m;
     cs[r * NR + c] = c < ncols ? Cm[(long long)c * L + r] : T(0);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wg = wv & 3, wh = wv >> 2;      // reflector group, row half
   for (int q = 0; q < nblock; ++q) {
     const int blk = transT ? q : nblock - 1 - q;
     const int kb = blk * kBB;
     if (kb >= d.nrefl) continue;
     const int bw = min(kBB, d.nrefl - kb);
     const T* Tin = Tbig + ((long long)blockIdx.x * nblock + blk) * kBB * kBB;
-    for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Ts[e / kBB][e % kBB] = Tin[e];
+    for (int e = threadIdx.x; e < kBB * kBB; e += kAN) Ts[e / kBB][e % kBB] = Tin[e];
     // ---- W = V^T C
     T acc[16][NR];
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj)
 #pragma unroll
       for (int c = 0; c < NR; ++c) acc[jj][c] = T(0);
-    for (int r0 = kb; r0 < m; r0 += 128) {
+    for (int r0 = kb + 128 * wh; r0 < m; r0 += 128 * kRG) {
       T vv[2][16], cv[2][NR];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int r = r0 + u * 64 + lane;
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
-          const int j = 16 * wv + jj;
+          const int j = 16 * wg + jj;
           vv[u][jj] = j < bw ? v_elem(Am, d.ld, m, kb, r, j) : T(0);
         }
 #pragma unroll
@@ -697,24 +703,34 @@ __global__ void __launch_bounds__(kBlock) k_qr_apply_narrow(const QRDesc* __rest
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
         const T v = wave_sum(acc[jj][c]);
-        if (lane == 0) Ws[16 * wv + jj][c] = v;
+        if (lane == 0) Ws[wh][16 * wg + jj][c] = v;
       }
     __syncthreads();
     // ---- W <- -T^T W (Q^T) or -T W (Q)
-    for (int e = threadIdx.x; e < kBB * NR; e += kBlock) {
+    for (int e = threadIdx.x; e < kBB * NR; e += kAN) {
       const int i = e / NR, c = e % NR;
       T s = T(0);
       if (transT) {
-        for (int ip = 0; ip <= i; ++ip) s += Ts[ip][i] * Ws[ip][c];
+        for (int ip = 0; ip <= i; ++ip) {
+          T w = Ws[0][ip][c];
+#pragma unroll
+          for (int h = 1; h < kRG; ++h) w += Ws[h][ip][c];
+          s += Ts[ip][i] * w;
+        }
       } else {
-        for (int ip = i; ip < kBB; ++ip) s += Ts[i][ip] * Ws[ip][c];
+        for (int ip = i; ip < kBB; ++ip) {
+          T w = Ws[0][ip][c];
+#pragma unroll
+          for (int h = 1; h < kRG; ++h) w += Ws[h][ip][c];
+          s += Ts[i][ip] * w;
+        }
       }
       Wn[i][c] = -s;
     }
     __syncthreads();
     // ---- C += V W, two rows per thread with their loads issued together
-    for (int r = kb + threadIdx.x; r < m; r += 2 * kBlock) {
-      const int r2 = r + kBlock;
+    for (int r = kb + threadIdx.x; r < m; r += 2 * kAN) {
+      const int r2 = r + kAN;
       T a[2][NR];
 #pragma unroll
       for (int c = 0; c < NR; ++c) {
@@ -745,7 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_apply_narrow(const QRDesc* __rest
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < m * ncols; e += kBlock) {
+  for (int e = threadIdx.x; e < m * ncols; e += kAN) {
     const int c = e / m, r = e % m;
     Cm[(long long)c * L + r] = cs[r * NR + c];
   }
