@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # below) and for the workload named; otherwise the bench reports null.
 CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
 CG_TRAFFIC = {
-    ("medium", "fp64"): dict(fetch_kib=1496939.8, write_kib=53942.4, fetch_scale=0.5, write_scale=1.0,
+    ("medium", "fp64"): dict(fetch_kib=1413423.4, write_kib=48890.3, fetch_scale=0.5, write_scale=1.0,
                              sha256="4f27056924380908c7303b5a7351e053a1b28039660cf289e6fd9d9db253026b"),
 }
 
