@@ -227,11 +227,12 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const T* Tin = Tbuf + ((long long)blockIdx.x * npanel + panel) * kNB * kNB;
   for (int e = threadIdx.x; e < kNB * kNB; e += kBlock) Ts[e / kNB][e % kNB] = Tin[e];
-  // ---- W = V^T C over rows k..m-1, 64-row chunks staged in LDS
+  // ---- W = V^T C over rows k..m-1, 64-row chunks staged in LDS; the next
+  //      chunk's loads (4 V and 8 C elements per thread) are in flight during
+  //      this chunk's products
   v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  for (int r0 = k; r0 < d.m; r0 += 64) {
-    // all loads of the chunk first (4 V and 8 C elements per thread), then the LDS stores
-    T vv[4], cc[8];
+  T vv[4], cc[8];
+  auto load_chunk = [&](int r0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -243,6 +244,9 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       const int c = e / 64, row = r0 + e % 64;
       cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
     }
+  };
+  load_chunk(k);
+  for (int r0 = k; r0 < d.m; r0 += 64) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -254,6 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       Cs[e % 64][e / 64] = cc[u];
     }
     __syncthreads();
+    if (r0 + 64 < d.m) load_chunk(r0 + 64);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int rr = wv * 16 + ks * 4 + (lane >> 4);
@@ -287,20 +292,34 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
     Wp[1][i][c] = -s;
   }
   __syncthreads();
-  // ---- C^T <- C^T + Wn^T V^T for 16-row blocks (rows along the lanes)
-  for (int rb = k + wv * 16; rb < d.m; rb += kWaves * 16) {
+  // ---- C^T <- C^T + Wn^T V^T for 16-row blocks (rows along the lanes); the
+  //      next block's loads are issued before this block's products
+  T cn_[8], bn_[4];
+  auto load_rows = [&](int rb) {
+    const int row = rb + (lane & 15);
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = cg * 16 + Mfma<T>::drow(lane, v);
+        cn_[4 * cg + v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+      }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) bn_[ks] = v_elem(Am, d.ld, d.m, k, row, ks * 4 + (lane >> 4));
+  };
+  int rb = k + wv * 16;
+  if (rb < d.m) load_rows(rb);
+  for (; rb < d.m; rb += kWaves * 16) {
     const int row = rb + (lane & 15);
     v4 acc[2];
     T bv[4];
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = cg * 16 + Mfma<T>::drow(lane, v);
-        acc[cg][v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
-      }
+      for (int v = 0; v < 4; ++v) acc[cg][v] = cn_[4 * cg + v];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) bv[ks] = v_elem(Am, d.ld, d.m, k, row, ks * 4 + (lane >> 4));
+    for (int ks = 0; ks < 4; ++ks) bv[ks] = bn_[ks];
+    if (rb + kWaves * 16 < d.m) load_rows(rb + kWaves * 16);
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
