@@ -138,7 +138,11 @@ typedef struct {
 void ddelm_default_options(ddelm_options* opt);
 
 /* Validate, build the interface indexing on the host and allocate the
- * context.  Errors: DDELM_E_ARG, DDELM_E_SHAPE, DDELM_E_NOMEM, DDELM_E_HIP. */
+ * context.  Errors: DDELM_E_ARG, DDELM_E_SHAPE (also for an interior point
+ * outside the closed box of its subdomain, or with a NaN coordinate; checked
+ * on the device, the message names the lowest such subdomain),
+ * DDELM_E_NOMEM, DDELM_E_HIP.  Returns after the context's stream has
+ * drained. */
 ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob,
                          const ddelm_options* opt, void* stream);
 
