@@ -933,8 +933,15 @@ void factor_impl(ddelm_ctx c) {
   }
   L.qrA.alloc(off);
   L.tau.alloc(toff);
-  L.qrA.zero(s);
   c->qrdesc.upload(c->h_qrdesc, s);
+  {
+    long long most = 0;
+    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * (d.ncols - d.nrefl));
+    if (most > 0) {
+      k_zero_appended<T><<<dim3(std::min(ceil_div(most, kBlock), 64), nmat), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p);
+      HIPCHK(hipGetLastError());
+    }
+  }
   {
     std::vector<long long> coff(nmat);
     std::vector<int> ldc(nmat), cn(nmat);

@@ -116,6 +116,17 @@ struct QRDesc {
   int pad;
 };
 
+// Zero the columns after the factored ones (the appended unit columns) of
+// every matrix; the factored columns are written in full by the feature
+// assembly.  blockIdx.y = matrix.
+template <typename T>
+__global__ void k_zero_appended(const QRDesc* __restrict__ desc, T* __restrict__ A) {
+  const QRDesc d = desc[blockIdx.y];
+  const long long beg = d.off + (long long)d.ld * d.nrefl, n = (long long)d.ld * (d.ncols - d.nrefl);
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock)
+    A[beg + e] = T(0);
+}
+
 // ---------------------------------------------------------------- triangular solves
 //
 // X <- R^{-1} X (trans = 0) or R^{-T} X (trans = 1) for the n x n upper
