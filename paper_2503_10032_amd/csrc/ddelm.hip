@@ -236,6 +236,33 @@ struct DBuf {
   ~DBuf() { free(); }
 };
 
+// Several buffers cleared by one kernel launch instead of one fill each.
+struct ZeroBatch {
+  std::vector<std::pair<unsigned*, long long>> v;
+  template <typename T>
+  ZeroBatch& add(DBuf<T>& b) {
+    static_assert(sizeof(T) % 4 == 0, "cleared as 32-bit words");
+    if (b.n) v.push_back({reinterpret_cast<unsigned*>(b.p), (long long)(b.n * sizeof(T) / 4)});
+    return *this;
+  }
+  void launch(hipStream_t s) {
+    for (size_t k0 = 0; k0 < v.size(); k0 += kZeroMax) {
+      ZeroList z{};
+      long long most = 0;
+      const int cnt = (int)std::min(v.size() - k0, (size_t)kZeroMax);
+      for (int k = 0; k < cnt; ++k) {
+        z.p[k] = v[k0 + k].first;
+        z.n[k] = v[k0 + k].second;
+        most = std::max(most, z.n[k]);
+      }
+      const unsigned gx = (unsigned)std::max<long long>(1, std::min<long long>((most + kBlock - 1) / kBlock, 256));
+      k_zero_many<<<dim3(gx, cnt), kBlock, 0, s>>>(z);
+      HIPCHK(hipGetLastError());
+    }
+    v.clear();
+  }
+};
+
 // Device copies of small per-call descriptor arrays: one device buffer and one
 // pinned host staging buffer, filled by a bump pointer and reset at the start
 // of every API call (the previous call has drained the stream).
@@ -642,14 +669,15 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   c->e_slot.alloc(P);
   c->cg_part.alloc((size_t)3 * nrhs * 4096);
   c->cg_scal.alloc((size_t)nrhs * 8);
+  ZeroBatch zb;
   for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc, &c->rho_loc,
                           &c->psi_loc, &c->nu_loc, &c->c1, &c->c2, &c->pif, &c->mu_slot, &c->e_slot})
-    b->zero(s);
+    zb.add(*b);
   c->fGP.alloc(P); c->fGD.alloc(D);
   c->fGP0.alloc(P); c->fGD0.alloc(D);
   c->hP0.alloc((size_t)nrhs * std::max(c->nP, 1));
   c->hD0.alloc(V);
-  for (DBuf<double>* b : {&c->fGP, &c->fGD, &c->fGP0, &c->fGD0, &c->hP0, &c->hD0}) b->zero(s);
+  for (DBuf<double>* b : {&c->fGP, &c->fGD, &c->fGP0, &c->fGD0, &c->hP0, &c->hD0}) zb.add(*b);
   if (c->mixed) {
     c->F64.alloc((size_t)nrhs * c->summ);
     c->R64.alloc((size_t)nrhs * c->summ);
@@ -661,8 +689,9 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
     c->dmup.alloc((size_t)nrhs * std::max(c->nP, 1));
     c->dmud.alloc(V);
     c->nrm_part.alloc((size_t)nrhs * 2 * 256);
-    for (DBuf<double>* b : {&c->fGP, &c->aP, &c->fGD, &c->aD, &c->hPb, &c->hDb, &c->dmup, &c->dmud}) b->zero(s);
+    for (DBuf<double>* b : {&c->fGP, &c->aP, &c->fGD, &c->aD, &c->hPb, &c->hDb, &c->dmup, &c->dmud}) zb.add(*b);
   }
+  zb.launch(s);
   std::vector<long long> foff(c->N);
   std::vector<int> fld(c->N, (int)c->summ), fcn(c->N, nrhs);
   for (int i = 0; i < c->N; ++i) foff[i] = c->h_offm[i];
@@ -1123,7 +1152,7 @@ void factor_impl(ddelm_ctx c) {
     const size_t nGt = std::max(c->h_offG[N], 1ll), nNt = std::max(c->h_offN[N], 1ll);
     L.Gm.alloc(nGt); L.Lm.alloc(nGt); L.LTm.alloc(nGt);
     L.Nm.alloc(nNt); L.NTm.alloc(nNt);
-    L.Gm.zero(s); L.Lm.zero(s); L.LTm.zero(s); L.Nm.zero(s); L.NTm.zero(s);
+    ZeroBatch().add(L.Gm).add(L.Lm).add(L.LTm).add(L.Nm).add(L.NTm).launch(s);
     c->offG.upload(std::vector<long long>(c->h_offG.begin(), c->h_offG.end() - 1), s);
     c->offN.upload(std::vector<long long>(c->h_offN.begin(), c->h_offN.end() - 1), s);
     std::vector<GemmDesc> gG, gL, gN;

@@ -293,6 +293,18 @@ __global__ void k_check_interior(const double* __restrict__ x, const double* __r
   }
 }
 
+// Zero several buffers in one launch: blockIdx.y = buffer, n in 32-bit words.
+constexpr int kZeroMax = 24;
+struct ZeroList {
+  unsigned* p[kZeroMax];
+  long long n[kZeroMax];
+};
+__global__ void k_zero_many(ZeroList z) {
+  unsigned* __restrict__ p = z.p[blockIdx.y];
+  const long long n = z.n[blockIdx.y];
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = 0u;
+}
+
 __global__ void k_fill(double* __restrict__ p, long long n, double v) {
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
 }
