@@ -1063,9 +1063,17 @@ void factor_impl(ddelm_ctx c) {
     HIPCHK(hipStreamWaitEvent(s2, c->sev(0), 0));
     auto evT = [&](int b) { return c->sev(1 + 2 * (size_t)b); };
     auto evR = [&](int b) { return c->sev(2 + 2 * (size_t)b); };
+    // column ends of every block (cnb) and of every near update (cnn), one upload
+    std::vector<int> cn_all((size_t)2 * c->nblock * nmat);
     for (int blk = 0; blk < c->nblock; ++blk) {
       const int kb = blk * kBB, bw = std::min(kBB, M - kb);
-      const int* cnb = c->arena.put(std::vector<int>(nmat, kb + bw), s);
+      std::fill_n(cn_all.begin() + (size_t)2 * blk * nmat, nmat, kb + bw);
+      std::fill_n(cn_all.begin() + (size_t)(2 * blk + 1) * nmat, nmat, std::min(kb + bw + kBB, M));
+    }
+    const int* cn_dev = c->arena.put(cn_all, s);
+    for (int blk = 0; blk < c->nblock; ++blk) {
+      const int kb = blk * kBB, bw = std::min(kBB, M - kb);
+      const int* cnb = cn_dev + (size_t)2 * blk * nmat;
       for (int k = kb; k < kb + bw; k += kNB) {
         const int p = k / kNB;
         launch_qr_panel16<T>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, L.qrA.p, L.tau.p,
@@ -1086,7 +1094,7 @@ void factor_impl(ddelm_ctx c) {
       // near update: the next block's columns, on the main stream
       if (c1 > c0) {
         if (blk > 0) HIPCHK(hipStreamWaitEvent(s, evR(blk - 1), 0));
-        const int* cnn = c->arena.put(std::vector<int>(nmat, c1), s);
+        const int* cnn = cn_dev + (size_t)(2 * blk + 1) * nmat;   // = c1
         const int ntn = ceil_div(c1 - c0, kBC);
         k_qr_wy64<T><<<nmat8 * ntn, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntn,
                                                     L.qrA.p, c->qr_coff.p, c->qr_ldc.p, cnn, c0, 1);
