@@ -2002,12 +2002,21 @@ ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long
     if (nrhs < 1 || npts < 0 || !coef || (npts > 0 && (!x || !u))) c->fail(DDELM_E_ARG, "bad evaluate arguments");
     const Geometry& g = c->geo;
     if (npts > 0) {
-      if (nrhs == 1)
-        k_evaluate<1><<<dim3(ceil_div(npts, kBlock), 1), kBlock, 0, c->stream>>>(
+      // right-hand sides per thread: all of them up to 16 (one tanh per point and neuron), else groups of 16
+      auto launch = [&](auto nrb, auto with_grad) {
+        constexpr int NRB = decltype(nrb)::value;
+        constexpr bool GRAD = decltype(with_grad)::value;
+        k_evaluate<NRB, GRAD><<<dim3(ceil_div(npts, kBlock), ceil_div(nrhs, NRB)), kBlock, 0, c->stream>>>(
             g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, nrhs);
-      else
-        k_evaluate<8><<<dim3(ceil_div(npts, kBlock), ceil_div(nrhs, 8)), kBlock, 0, c->stream>>>(
-            g.nx, g.ny, c->M, c->N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p, coef, npts, x, u, grad, nrhs);
+      };
+      using One = std::integral_constant<int, 1>;
+      using Eight = std::integral_constant<int, 8>;
+      using Sixteen = std::integral_constant<int, 16>;
+      using Yes = std::true_type;
+      using No = std::false_type;
+      if (nrhs == 1) grad ? launch(One(), Yes()) : launch(One(), No());
+      else if (nrhs <= 8) grad ? launch(Eight(), Yes()) : launch(Eight(), No());
+      else grad ? launch(Sixteen(), Yes()) : launch(Sixteen(), No());
       HIPCHK(hipGetLastError());
     }
   });

@@ -380,8 +380,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
 // ---------------------------------------------------------------- evaluation
 // u[r][p] (and grad[r][p][:]) for the right-hand sides r0 .. r0+NRB-1 (< nrhs)
 // at point p = blockIdx.x * kBlock + threadIdx.x, r0 = blockIdx.y * NRB: one
-// tanh per (point, neuron) serves every right-hand side of the group.
-template <int NRB>
+// tanh per (point, neuron) serves every right-hand side of the group.  GRAD:
+// the gradient is wanted (otherwise it is not accumulated).
+template <int NRB, bool GRAD>
 __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int N, double lo0, double lo1, double h0,
                                                      double h1, const double* __restrict__ W,
                                                      const double* __restrict__ bias, const double* __restrict__ coef,
@@ -410,9 +411,11 @@ __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int 
       if (r0 + k < nrhs) {
         const double c = coef[((size_t)(r0 + k) * N + i) * M + j];
         acc[k] += c * t;
-        const double d = c * dt;
-        g0[k] += d * w0;
-        g1[k] += d * w1;
+        if (GRAD) {
+          const double d = c * dt;
+          g0[k] += d * w0;
+          g1[k] += d * w1;
+        }
       }
     }
   }
@@ -421,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int 
     if (r0 + k >= nrhs) continue;
     const int r = r0 + k;
     u[(size_t)r * npts + e] = acc[k];
-    if (grad) {
+    if (GRAD) {
       grad[((size_t)r * npts + e) * 2] = g0[k] / hx;
       grad[((size_t)r * npts + e) * 2 + 1] = g1[k] / hy;
     }

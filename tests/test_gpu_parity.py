@@ -196,8 +196,10 @@ def test_general_rhs_matches_oracle(name):
             assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < 1e-9
 
 
-def test_multi_rhs_matches_oracle():
-    c = Case(nx=3, ny=3, M=40, n_int=6, p=8, a=2.0, seed=5, extra=True, tol=1e-12, rhs="fourier", nrhs=4)
+@pytest.mark.parametrize("nrhs", [4, 12])
+def test_multi_rhs_matches_oracle(nrhs):
+    # 12 right-hand sides: the CG with MFMA local products and the evaluation with 16 per thread
+    c = Case(nx=3, ny=3, M=40, n_int=6, p=8, a=2.0, seed=5, extra=True, tol=1e-12, rhs="fourier", nrhs=nrhs)
     g, geo, s, out, refs = _solve_both(c)
     X = I.eval_grid(c.w)
     u = g.evaluate(out["coef"], X).cpu().numpy()
