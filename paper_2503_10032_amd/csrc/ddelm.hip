@@ -24,6 +24,7 @@
 #include "kernels_qr.hpp"
 #include "kernels_rhs.hpp"
 #include "kernels_adj.hpp"
+#include "kernel_entries.hpp"
 
 using namespace ddelm;
 
@@ -543,7 +544,7 @@ template <typename T>
 void launch_qr_panel16(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
                        int npanel) {
   switch (rpt) {
-#define CASE(R) case R: k_qr_panel16<T, R><<<grid, kPanelThreads, 0, s>>>(d, A, tau, Tb, k, panel, npanel); break;
+#define CASE(R) case R: launch_qr_panel16_rpt<T, R>(grid, s, d, A, tau, Tb, k, panel, npanel); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
     default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
@@ -818,7 +819,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int ma
   const size_t tab_bytes = sizeof(int) * ((size_t)kTabUnits * tab_nd * (1 + kMaxOwn) + (tab_pi ? (size_t)kMaxOwn * c->nP : 0));
   const bool tab_fits = smem0 + tab_bytes <= 160 * 1024;
   size_t smem = smem0 + (tab_fits ? tab_bytes : 0);
-  const void* fn = (const void*)k_cg_fused<T, NR>;
+  const void* fn = cg_fused_kernel<T, NR>();
   if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   int per_cu = 0;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, smem));

@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_copy2d(const CopyDesc* __restrict__ 
   }
 }
 
+#ifndef DDELM_KERNEL_SUBSET   // plain kernels: defined once, in the unit that launches them
 // Interior points must lie in the closed box of their subdomain
 // (box[4 i .. 4 i + 3] = x0, x1, y0, y1); *first_bad becomes the lowest
 // subdomain index with a point outside (or a NaN coordinate).  It starts at
@@ -293,12 +294,15 @@ __global__ void k_check_interior(const double* __restrict__ x, const double* __r
   }
 }
 
+#endif
+
 // Zero several buffers in one launch: blockIdx.y = buffer, n in 32-bit words.
 constexpr int kZeroMax = 24;
 struct ZeroList {
   unsigned* p[kZeroMax];
   long long n[kZeroMax];
 };
+#ifndef DDELM_KERNEL_SUBSET   // plain kernels: defined once, in the unit that launches them
 __global__ void k_zero_many(ZeroList z) {
   unsigned* __restrict__ p = z.p[blockIdx.y];
   const long long n = z.n[blockIdx.y];
@@ -308,6 +312,7 @@ __global__ void k_zero_many(ZeroList z) {
 __global__ void k_fill(double* __restrict__ p, long long n, double v) {
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) p[e] = v;
 }
+#endif
 
 // identity blocks: for each batch entry, add `v` on the diagonal of an n x n
 // block at off (column-major, ld = n)
@@ -353,6 +358,7 @@ __global__ void k_coarse_assemble(int nP, const int* __restrict__ own_ptr, const
 // triangle is meaningful afterwards.  err[0] |= 2 if a pivot is not positive.
 constexpr int kCB = 32;
 
+#ifndef DDELM_KERNEL_SUBSET   // plain kernels: defined once, in the unit that launches them
 __global__ void __launch_bounds__(kBlock) k_chol_diag(double* __restrict__ S, int n, int k0, int nb,
                                                       unsigned* __restrict__ err) {
   __shared__ double A[kCB][kCB + 1];   // A[col][row]
@@ -450,5 +456,6 @@ __global__ void __launch_bounds__(kBlock) k_chol_inverse(const double* __restric
     if (c0 + c < n) Sinv[(long long)(c0 + c) * n + r] = x[e];
   }
 }
+#endif
 
 }  // namespace ddelm
