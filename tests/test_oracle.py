@@ -213,16 +213,18 @@ def test_manufactured_error_falls_with_neurons():
 
 
 def test_neumann_neumann_cuts_iterations():
-    """theta = 0.999 needs several times fewer CG iterations than theta = 0
-    (the paper's ablation trend)."""
-    w = I.Workload("t", 4, 4, 96, 2.0, 0, 12, 12)
+    """theta = 0.999 needs at least 3x fewer CG iterations than theta = 0 on a
+    4x4 partition with the paper's manufactured solution (table nn-mixed:
+    DDELM-CS against DDELM-NN, ratios 4-10 at its much finer resolution; the
+    ratio grows with the local resolution, about 3.6 at M = 192 here)."""
+    w = I.Workload("t", 4, 4, 192, 2.0, 0, 18, 18)
     W, b = I.hidden_params(w.N, w.M, 2, w.a, w.seed)
     geo = O.Geometry2D(4, 4, I.edge_params(w.p), [], I.interior_points(w))
     f = O.local_rhs(geo, I.sinsin_f, I.sinsin_u)
     it = {}
     for th in (0.0, 0.999):
         it[th] = O.DDELMNN(geo, W, b, theta=th).solve(f, tol=1e-10)["iters"]
-    assert it[0.999] * 2 < it[0.0]
+    assert it[0.999] * 3 <= it[0.0], it
 
 
 def test_small_workload_counts():
