@@ -105,7 +105,10 @@ class Geometry2D:
 
     coarse: 0 = no coarse space (vanilla DDELM), K and plain A;
             1 = corners as Pi, K and plain A;
-            2 = corners as Pi, K_c and A_m (the paper's default).
+            2 = corners as Pi, K_c and A_m (the paper's default);
+            3 = corners as Pi, K_c and plain A;
+            4 = corners as Pi, K and A_m
+    (3 and 4 are the remaining cells of the ablation of sec. 4.2, table chov).
     """
 
     def __init__(self, nx, ny, s_edge, s_extra, x_int, lo=(0.0, 0.0), hi=(1.0, 1.0), coarse=2):
@@ -220,7 +223,7 @@ class Geometry2D:
         # corner and falls linearly (in s) to 0 at the other end of each of this
         # subdomain's interface edges through that corner.
         T = np.eye(nG)
-        if self.coarse == 2:
+        if self.coarse in (2, 3):
             for a, t in enumerate(dls):
                 info = t[2]
                 if info[0] != "e":
@@ -238,7 +241,7 @@ class Geometry2D:
             c = t[2]
             terms = []
             incident = [sd for sd in iface_sides if sd[1] == c or sd[2] == c]
-            if self.coarse == 2:
+            if self.coarse in (2, 4):
                 # mean flux over each incident edge, excluding the opposite end
                 for side, v0, v1, e, f in incident:
                     n = np.array(NORMAL[side])
@@ -574,9 +577,10 @@ class DDELMNN:
 
     def solve(self, f, h=None, tol=1e-10, maxit=10000, x0=None):
         b, d_pi = self.rhs(f, h)
-        mu_dl, it, relres = cg(self.S_theta, b, tol, maxit, x0)
+        info = {}
+        mu_dl, it, relres = cg(self.S_theta, b, tol, maxit, x0, info=info)
         cs, mu_pi = self.recover(f, d_pi, mu_dl)
-        return dict(c=cs, mu_pi=mu_pi, mu_dl=mu_dl, iters=it, relres=relres, b=b)
+        return dict(c=cs, mu_pi=mu_pi, mu_dl=mu_dl, iters=it, relres=relres, b=b, kappa=info.get("kappa", 1.0))
 
     # ---------------- adjoint (transpose) of solve, derived from its equations
     def adjoint(self, cbar, mubar_pi=None, mubar_dl=None, tol=1e-12, maxit=10000, direct=False):
@@ -621,8 +625,14 @@ class DDELMNN:
         return fbar, (ft_bot, q), it
 
 
-def cg(apply, b, tol, maxit, x0=None):
-    """Plain conjugate gradients; stops when ||r_k|| <= tol ||b||."""
+def cg(apply, b, tol, maxit, x0=None, info=None):
+    """Plain conjugate gradients; stops when ||r_k|| <= tol ||b||.
+
+    If `info` is a dict, info["kappa"] receives the condition-number estimate
+    of the operator from the CG coefficients: CG is the Lanczos process, whose
+    tridiagonal matrix T (T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    T_{j,j+1} = sqrt(beta_j)/alpha_j) has Ritz values inside the spectrum that
+    approach its ends; kappa = largest / smallest Ritz value."""
     n = len(b)
     x = np.zeros(n) if x0 is None else x0.copy()
     if n == 0:
@@ -634,6 +644,7 @@ def cg(apply, b, tol, maxit, x0=None):
     p = r.copy()
     rr = r @ r
     it = 0
+    alphas, betas = [], []
     while np.sqrt(rr) > tol * bn and it < maxit:
         w = apply(p)
         alpha = rr / (p @ w)
@@ -641,8 +652,16 @@ def cg(apply, b, tol, maxit, x0=None):
         r -= alpha * w
         rr_new = r @ r
         p = r + (rr_new / rr) * p
+        alphas.append(alpha)
+        betas.append(rr_new / rr)
         rr = rr_new
         it += 1
+    if info is not None and alphas:
+        k = len(alphas)
+        d = np.array([1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0) for j in range(k)])
+        e = np.array([np.sqrt(betas[j]) / alphas[j] for j in range(k - 1)])
+        ritz = sla.eigvalsh_tridiagonal(d, e)
+        info["kappa"] = float(ritz[-1] / ritz[0])
     return x, it, np.sqrt(rr) / bn
 
 

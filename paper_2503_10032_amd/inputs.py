@@ -77,6 +77,46 @@ def hidden_params(N: int, M: int, d: int, a: float, seed: int):
     return np.ascontiguousarray(W), np.ascontiguousarray(b)
 
 
+def paper_hidden_params(nx: int, ny: int, M: int, c: float, seed: int, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    """Hidden parameters drawn with the paper's initialisation (sec. 4.1, eq.
+    init_be), returned in the local coordinates the library uses.
+
+    Per subdomain Omega_i (a box of half widths (hx, hy) about its centre):
+    r = diam(Omega_i)/2, B_r = the closed r-neighbourhood of Omega_i (so
+    diam(B_r) = 2 diam(Omega_i)), l = c M^{1/d} / diam(B_r) with d = 2;
+    w ~ U([-l, l]^2) acting on global coordinates, b = -w . xi with xi drawn
+    uniformly from B_r (by rejection from its bounding box).  With
+    x = centre + (hx, hy) * xi_loc the same neuron reads
+    w . x + b = (w * (hx, hy)) . xi_loc + w . (centre - xi).
+    Returns W (N, M, 2) and b (N, M) like hidden_params."""
+    rng = np.random.default_rng(seed)
+    N = nx * ny
+    hx = (hi[0] - lo[0]) / nx
+    hy = (hi[1] - lo[1]) / ny
+    diam = math.hypot(hx, hy)
+    r = 0.5 * diam
+    ell = c * math.sqrt(M) / (2.0 * diam)
+    W = np.empty((N, M, 2))
+    b = np.empty((N, M))
+    for iy in range(ny):
+        for ix in range(nx):
+            i = iy * nx + ix
+            x0, y0 = lo[0] + ix * hx, lo[1] + iy * hy
+            x1, y1 = x0 + hx, y0 + hy
+            w = rng.uniform(-ell, ell, size=(M, 2))
+            xi = np.empty((0, 2))
+            while len(xi) < M:
+                cand = rng.uniform((x0 - r, y0 - r), (x1 + r, y1 + r), size=(2 * M, 2))
+                dx = np.maximum(np.maximum(x0 - cand[:, 0], cand[:, 0] - x1), 0.0)
+                dy = np.maximum(np.maximum(y0 - cand[:, 1], cand[:, 1] - y1), 0.0)
+                xi = np.concatenate([xi, cand[dx * dx + dy * dy <= r * r]])
+            xi = xi[:M]
+            centre = np.array([x0 + 0.5 * hx, y0 + 0.5 * hy])
+            W[i] = w * np.array([0.5 * hx, 0.5 * hy])
+            b[i] = np.einsum("mk,mk->m", w, centre - xi)
+    return np.ascontiguousarray(W), np.ascontiguousarray(b)
+
+
 def interior_points(w: Workload) -> np.ndarray:
     """Uniform strictly-interior grid, shape (N, n*n, 2), x fastest.
 

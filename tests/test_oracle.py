@@ -127,7 +127,7 @@ def test_single_subdomain_is_plain_elm_least_squares():
 
 @pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (3, 3)])
 @pytest.mark.parametrize("theta", [0.0, 0.5, 0.999])
-@pytest.mark.parametrize("coarse", [1, 2])
+@pytest.mark.parametrize("coarse", [1, 2, 3, 4])
 def test_matrix_free_cg_matches_dense_definition(nx, ny, theta, coarse):
     """The recipes (K~^+ via S_Pi, (K~^+)^T, P) and CG reproduce the stacked
     weighted least-squares problem solved directly with pinv + lstsq."""
@@ -159,7 +159,8 @@ def test_matrix_free_operator_matches_dense_operator_and_is_spd():
 
 
 @pytest.mark.parametrize("nx,ny", [(2, 2), (3, 3)])
-@pytest.mark.parametrize("coarse,theta", [(0, 0.0), (1, 0.0), (1, 0.999), (2, 0.0), (2, 0.5), (2, 0.999), (2, 1.0)])
+@pytest.mark.parametrize("coarse,theta", [(0, 0.0), (1, 0.0), (1, 0.999), (2, 0.0), (2, 0.5), (2, 0.999), (2, 1.0),
+                                          (3, 0.0), (3, 0.999), (4, 0.0), (4, 0.999)])
 def test_consistent_system_reproduces_monolithic_solve(nx, ny, coarse, theta):
     """With square local systems (M = m) the coupled system of eq. ddelm is
     square; every variant must return its unique solution.  S_theta is
@@ -241,3 +242,16 @@ def test_uneven_boundary_rows():
     ms = [sb.m for sb in geo.subs]
     base = 9 + 16
     assert ms[4] == base and ms[1] == base + 4 and ms[0] == base + 8
+
+
+def test_cg_condition_estimate_matches_the_assembled_operator():
+    """The Lanczos estimate of cond(S_theta) from the CG coefficients (used to
+    bound mu differences between two solves that each meet a residual
+    tolerance) against the eigenvalues of the assembled operator."""
+    w, W, b, geo = tiny(3, 3, 14, 3, 5)
+    s = O.DDELMNN(geo, W, b, theta=0.999)
+    S = O.assemble_S_theta(s)
+    ev = np.linalg.eigvalsh(0.5 * (S + S.T))
+    r = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-14, maxit=2000)
+    kap = ev[-1] / ev[0]
+    assert kap / 2 <= r["kappa"] <= kap * (1 + 1e-8), (r["kappa"], kap)
