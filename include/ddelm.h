@@ -10,8 +10,8 @@
  *                 sets x_I, x_B, x_Gamma of every subdomain (sec. 2.2.1);
  *   ddelm_factor  local feature matrices K_c^i, A_m^i, Kbar^i, Abar^i
  *                 (sec. 2.2.1, 3.1, 3.2), their Householder QR, and the
- *                 coarse Schur complement S_Pi with its Cholesky factor
- *                 (sec. 3, "assemble S_Pi in full");
+ *                 coarse Schur complement S_Pi, formed densely and
+ *                 Cholesky-factored (sec. 3);
  *   ddelm_solve   right-hand side f = [f(x_I); g(x_B); 0] (eq. ddelm),
  *                 CG on mu_Delta for eq. nn-mixed, then
  *                 [c; mu_Pi] = K~^+ (f~ - B~ mu_Delta) (eq. coarse_sol_2);
@@ -54,8 +54,9 @@
  *     passed as void*; NULL = the default stream).  Calls that return
  *     statistics synchronise that stream.  A context is not thread-safe.
  *   - Errors: a negative status is an error; outputs are then unspecified
- *     and ddelm_last_error(ctx) describes it.  DDELM_WARN_NOCONV means CG hit
- *     maxit; the best iterate is still written.
+ *     and ddelm_last_error(ctx) describes it.  DDELM_WARN_NOCONV means the
+ *     solve did not meet its tolerance (see ddelm_solve); the best iterate
+ *     is still written.
  */
 #ifndef DDELM_H
 #define DDELM_H
@@ -97,19 +98,30 @@ typedef struct {
   double theta;             /* NN mixing weight of eq. nn-mixed, 0 <= theta <= 1 */
   int coarse;               /* 0: no coarse space, K and A (vanilla DDELM);
                                1: corners as Pi, K and A;
-                               2: corners as Pi, K_c and A_m (sec. 3.2; default) */
-  int precision;            /* 0: float64 throughout; 1: mixed (float32 local factors
-                               and matvecs, float64 coarse problem, dots and refinement) */
+                               2: corners as Pi, K_c and A_m (sec. 3.2; default);
+                               3: corners as Pi, K_c and A;  4: corners as Pi, K and A_m
+                               (the other cells of the ablation of sec. 4.2) */
+  int precision;            /* 0: float64 throughout;
+                               1: mixed -- Householder QR in float32 on the matrix cores, its
+                                  factors widened to float64 for the triangular solves, local
+                                  operators, right-hand sides and recovery; float32 local
+                                  operators in the CG; float64 coarse problem, dots and
+                                  refinement of the coupled system (result within the
+                                  float32-factor floor of the float64 one, not to tol);
+                               2: float64 factors and operators, float32 copies of the local
+                                  operators in the CG, refined on the float64 interface
+                                  residual until it is <= tol (the float64 result) */
   double tol;               /* CG stop: ||r_k|| <= tol ||b||, 0 < tol < 1 */
   int maxit;                /* CG iteration cap (per refinement step), >= 1 */
   int max_nrhs;             /* largest nrhs a solve may pass, 1..64 */
   int cg_mode;              /* 0: auto; 1: one launch per CG phase; 2: one persistent
                                cooperative launch per CG solve */
-  int refine_maxit;         /* mixed precision: outer refinement steps cap (>= 1) */
+  int refine_maxit;         /* mixed precision: outer refinement steps cap (>= 0; 0 = the
+                               float32-QR solve alone) */
   double refine_tol;        /* mixed precision: stop when the correction of mu is
-                               <= refine_tol relative to mu, or when a step shrinks
-                               the correction by less than a factor 2 (stall) */
-  double inner_tol;         /* mixed precision: CG tolerance of each inner solve */
+                               <= refine_tol relative to mu (converged), or when a step
+                               shrinks the correction by less than a factor 2 (stall) */
+  double inner_tol;         /* precision 1: CG tolerance of each inner solve */
 } ddelm_options;
 
 typedef struct {
@@ -122,6 +134,16 @@ typedef struct {
   int cg_blocks;            /* persistent CG: workgroups of the last launch (0 with cg_mode 1) */
   int cg_slices;            /* persistent CG: row slices per subdomain (tuned, see ddelm_solve) */
   int cg_coarse_dist;       /* persistent CG: 1 = coarse phases distributed over workgroups */
+  int cg_restarts;          /* CG restarts on the float64 residual (see true_rel_res) */
+  double true_rel_res;      /* float64: ||b - S_theta mu_Delta|| / ||b|| with S_theta applied in
+                               float64 to the returned mu_Delta (eq. nn-mixed), max over RHS;
+                               NaN in mixed precision, whose convergence test is refine_corr */
+  double refine_corr;       /* mixed precision: relative size of the last refinement correction
+                               of (mu_Pi, mu_Delta), max over RHS; 0 in float64 */
+  double kappa_est_max;     /* max over the factored local matrices (K_c^i and Kbar^i) of
+                               max_j |R_jj| / min_j |R_jj| of their triangular factor */
+  double start_rel_res;     /* with mu0: ||b - S_theta mu0|| / ||b|| in float64 (max over RHS),
+                               the residual of the starting value; 0 without mu0 */
 } ddelm_stats;
 
 typedef struct {
@@ -154,13 +176,23 @@ ddelm_status ddelm_factor(ddelm_ctx ctx);
 /* Solve for nrhs right-hand sides (1 <= nrhs <= max_nrhs).
  *   f_I   [nrhs][N][n_int]   f at the interior points
  *   g_B   [nrhs][sum_nB]     g at the boundary points (ddelm_get_boundary_points order)
+ *   mu0   [nrhs][n_dl]       may be NULL (zero): starting value of mu_Delta for the CG
+ *                            (a warm start; the result does not depend on it beyond tol)
  *   coef  [nrhs][N][M]       output: last-layer coefficients c^i
  *   mu_pi [nrhs][n_pi]       output, may be NULL: mu_Pi
- *   mu_dl [nrhs][n_dl]       output, may be NULL: mu_Delta
+ *   mu_dl [nrhs][n_dl]       output, may be NULL: mu_Delta (may alias mu0)
  *   stats host, may be NULL; when given the call synchronises the stream.
+ * In float64 the CG stops on its recurrence residual ||r_k|| <= tol ||b||;
+ * then b - S_theta mu_Delta is formed in float64 and, while it exceeds
+ * tol ||b||, the CG is restarted on it (at most 3 times).  In mixed precision
+ * the float32-operator CG runs to inner_tol and the result is refined until
+ * the relative correction is <= refine_tol (see ddelm_options).
  * Errors: DDELM_E_STATE (before factor), DDELM_E_ARG, DDELM_E_HIP,
- * DDELM_E_NONFINITE; DDELM_WARN_NOCONV when maxit was reached. */
-ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B,
+ * DDELM_E_NONFINITE.  DDELM_WARN_NOCONV (result still written): float64 --
+ * maxit reached or the float64 residual stayed above tol; mixed -- the
+ * refinement stopped (stall or refine_maxit) with the correction above
+ * refine_tol. */
+ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B, const double* mu0,
                          double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats);
 
 /* Solve the coupled system of eq. ddelm with a general right-hand side

@@ -1,8 +1,10 @@
 """ctypes declarations of the C ABI in include/ddelm.h (argument marshalling only)."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libddelm.so")
@@ -43,6 +45,8 @@ class Stats(ctypes.Structure):
         ("iters", ctypes.c_int), ("refine_steps", ctypes.c_int), ("rel_res", ctypes.c_double),
         ("ms_rhs", ctypes.c_double), ("ms_cg", ctypes.c_double), ("ms_recover", ctypes.c_double),
         ("cg_blocks", ctypes.c_int), ("cg_slices", ctypes.c_int), ("cg_coarse_dist", ctypes.c_int),
+        ("cg_restarts", ctypes.c_int), ("true_rel_res", ctypes.c_double), ("refine_corr", ctypes.c_double),
+        ("kappa_est_max", ctypes.c_double), ("start_rel_res", ctypes.c_double),
     ]
 
 
@@ -61,7 +65,8 @@ SIGNATURES = {
                                    ctypes.POINTER(Options), ctypes.c_void_p]),
     "ddelm_factor": (ctypes.c_int, [ctypes.c_void_p]),
     "ddelm_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
-                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(Stats)]),
     "ddelm_solve_general": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats)]),
     "ddelm_evaluate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong,
@@ -87,6 +92,26 @@ SIGNATURES = {
 }
 
 _lib = None
+_live = weakref.WeakSet()     # objects holding a context (with a close() method)
+
+
+def register(obj) -> None:
+    """Track an object that owns a context, so that it is closed at exit."""
+    _live.add(obj)
+
+
+def _release_at_exit() -> None:
+    # Contexts still alive at interpreter exit are destroyed, and the library's
+    # idle memory, streams, events and pinned buffers are handed back, while
+    # the HIP runtime (and any tool attached to it) is still fully up.
+    if _lib is None:
+        return
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    _lib.ddelm_release_cached_memory()
 
 
 def load() -> ctypes.CDLL:
@@ -102,4 +127,5 @@ def load() -> ctypes.CDLL:
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    atexit.register(_release_at_exit)
     return lib

@@ -408,7 +408,8 @@ struct ddelm_ctx_s {
   int nP = 0, nD = 0, sumP = 0, sumD = 0;
   bool factored = false;
   bool use_nn = true;     // theta != 0: Kbar factored and P applied
-  bool mixed = false;     // float32 local factors + float64 refinement
+  bool mixed = false;     // float32 Householder QR + float64 refinement of the coupled system
+  bool f32cg = false;     // float32 local operators in the CG (mixed, or precision 2)
   std::string err;
   int device = 0;
   int num_cu = 0;
@@ -434,9 +435,10 @@ struct ddelm_ctx_s {
   LocalBufs<float> l32;
   template <typename T>
   LocalBufs<T>& lb();
-  // float64 features kept for refinement residuals (mixed precision)
-  DBuf<double> K64, A64, CD64;
+  // float64 K_c^i features kept for the refinement residuals (mixed precision)
+  DBuf<double> K64;
   DBuf<long long> offK_d;
+  double kappa_est = 0.0;              // max |R_jj| / min |R_jj| over the factored matrices
   // coarse (always float64)
   DBuf<double> Spi, Sfac, Sinv, Dpp, Gs, Zm, Ztm, Wm, X1, X1t;
   DBuf<unsigned> flags;                // [0] barrier expired (1) / Cholesky (2)
@@ -452,9 +454,12 @@ struct ddelm_ctx_s {
   DBuf<double> cg_x, cg_r, cg_p, cg_p1, cg_w, cg_b, cg_part, cg_scal, mu_slot, e_slot;
   DBuf<double> cg_r1, cg_s1;    // second r and s buffers of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
+  DBuf<double> cg_b0, cg_xs, cg_sx, cg_nrm;   // interface solve: b, accumulated x, S_theta x, norms
+  const double* cg_ref = nullptr;      // per-RHS squared norm the CG stopping test is relative to
   int cg_blocks = 0, cg_slices = 0, cg_dist = 0;   // launch shape of the last persistent CG
   // refinement workspaces (mixed precision)
-  DBuf<double> F64, R64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
+  DBuf<double> F64, fGP, fGD, aP, aD, hPb, hDb, dcoef, dmup, dmud, nrm_part;
+  DBuf<double> ref_muP, ref_muD;       // refined mu_Pi, mu_Delta
   DBuf<double> fGP0, fGD0, hP0, hD0;   // interface rows and flux rows of a general right-hand side
   // adjoint workspaces
   int adj_cap = 0;
@@ -649,48 +654,65 @@ size_t local_smem(ddelm_ctx c) {
 
 // --------------------------------------------------------------- solve workspaces
 
+// The solve workspace for nrhs right-hand sides: every buffer with its
+// length, and whether it is cleared when it is set up.
+struct WsEntry {
+  DBuf<double>* buf;
+  size_t n;
+  bool zero;
+};
+
+std::vector<WsEntry> solve_workspace(ddelm_ctx c, int nrhs) {
+  const size_t D = (size_t)nrhs * std::max(c->sumD, 1), P = (size_t)nrhs * std::max(c->sumP, 1);
+  const size_t C = (size_t)nrhs * std::max(2 * c->nP, 1);
+  const size_t nPr = (size_t)nrhs * std::max(c->nP, 1), V = (size_t)nrhs * std::max(c->nD, 1);
+  std::vector<WsEntry> w;
+  w.push_back({&c->l64.F, (size_t)nrhs * c->summ, false});
+  for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc})
+    w.push_back({b, D, true});
+  for (DBuf<double>* b : {&c->rho_loc, &c->psi_loc, &c->nu_loc}) w.push_back({b, P, true});
+  w.push_back({&c->c1, C, true});
+  w.push_back({&c->c2, C, true});
+  w.push_back({&c->cg_u, C, false});
+  w.push_back({&c->cg_c, C, false});
+  w.push_back({&c->pif, nPr, true});
+  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1,
+                          &c->cg_b0, &c->cg_xs, &c->cg_sx})
+    w.push_back({b, V, false});
+  w.push_back({&c->cg_nrm, (size_t)2 * nrhs, false});
+  w.push_back({&c->mu_slot, P, true});
+  w.push_back({&c->e_slot, P, true});
+  w.push_back({&c->cg_part, (size_t)3 * nrhs * 4096, false});
+  w.push_back({&c->cg_scal, (size_t)nrhs * 8, false});
+  w.push_back({&c->fGP, P, true});
+  w.push_back({&c->fGD, D, true});
+  w.push_back({&c->fGP0, P, true});
+  w.push_back({&c->fGD0, D, true});
+  w.push_back({&c->hP0, nPr, true});
+  w.push_back({&c->hD0, V, true});
+  if (c->mixed) {
+    w.push_back({&c->F64, (size_t)nrhs * c->summ, false});
+    w.push_back({&c->aP, P, true});
+    w.push_back({&c->aD, D, true});
+    w.push_back({&c->hPb, nPr, true});
+    w.push_back({&c->hDb, V, true});
+    w.push_back({&c->dcoef, (size_t)nrhs * c->N * c->M, false});
+    w.push_back({&c->dmup, nPr, true});
+    w.push_back({&c->dmud, V, true});
+    w.push_back({&c->nrm_part, (size_t)nrhs * 2 * 256, false});
+    w.push_back({&c->ref_muP, nPr, true});
+    w.push_back({&c->ref_muD, V, true});
+  }
+  return w;
+}
+
 void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   if (nrhs <= c->cap_nrhs) return;
   hipStream_t s = c->stream;
-  if (c->mixed) c->l32.F.alloc((size_t)nrhs * c->summ);
-  else c->l64.F.alloc((size_t)nrhs * c->summ);
-  const size_t D = (size_t)nrhs * std::max(c->sumD, 1), P = (size_t)nrhs * std::max(c->sumP, 1);
-  for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc}) b->alloc(D);
-  for (DBuf<double>* b : {&c->rho_loc, &c->psi_loc, &c->nu_loc}) b->alloc(P);
-  const size_t C = (size_t)nrhs * std::max(2 * c->nP, 1);
-  c->c1.alloc(C);
-  c->c2.alloc(C);
-  c->cg_u.alloc(C);
-  c->cg_c.alloc(C);
-  c->pif.alloc((size_t)nrhs * std::max(c->nP, 1));
-  const size_t V = (size_t)nrhs * std::max(c->nD, 1);
-  for (DBuf<double>* b : {&c->cg_x, &c->cg_r, &c->cg_p, &c->cg_p1, &c->cg_w, &c->cg_b, &c->cg_r1, &c->cg_s1})
-    b->alloc(V);
-  c->mu_slot.alloc(P);
-  c->e_slot.alloc(P);
-  c->cg_part.alloc((size_t)3 * nrhs * 4096);
-  c->cg_scal.alloc((size_t)nrhs * 8);
   ZeroBatch zb;
-  for (DBuf<double>* b : {&c->s_loc, &c->l_loc, &c->lam_loc, &c->y_loc, &c->z_loc, &c->t_loc, &c->w_loc, &c->rho_loc,
-                          &c->psi_loc, &c->nu_loc, &c->c1, &c->c2, &c->pif, &c->mu_slot, &c->e_slot})
-    zb.add(*b);
-  c->fGP.alloc(P); c->fGD.alloc(D);
-  c->fGP0.alloc(P); c->fGD0.alloc(D);
-  c->hP0.alloc((size_t)nrhs * std::max(c->nP, 1));
-  c->hD0.alloc(V);
-  for (DBuf<double>* b : {&c->fGP, &c->fGD, &c->fGP0, &c->fGD0, &c->hP0, &c->hD0}) zb.add(*b);
-  if (c->mixed) {
-    c->F64.alloc((size_t)nrhs * c->summ);
-    c->R64.alloc((size_t)nrhs * c->summ);
-    c->aP.alloc(P);
-    c->aD.alloc(D);
-    c->hPb.alloc((size_t)nrhs * std::max(c->nP, 1));
-    c->hDb.alloc(V);
-    c->dcoef.alloc((size_t)nrhs * c->N * c->M);
-    c->dmup.alloc((size_t)nrhs * std::max(c->nP, 1));
-    c->dmud.alloc(V);
-    c->nrm_part.alloc((size_t)nrhs * 2 * 256);
-    for (DBuf<double>* b : {&c->fGP, &c->aP, &c->fGD, &c->aD, &c->hPb, &c->hDb, &c->dmup, &c->dmud}) zb.add(*b);
+  for (const WsEntry& e : solve_workspace(c, nrhs)) {
+    e.buf->alloc(e.n);
+    if (e.zero) zb.add(*e.buf);
   }
   zb.launch(s);
   std::vector<long long> foff(c->N);
@@ -738,6 +760,7 @@ CGState cg_state(ddelm_ctx c, int nrhs, int nblk, double tol) {
   s.part = c->cg_part.p; s.scal = c->cg_scal.p;
   s.n = c->nD; s.nrhs = nrhs; s.nblk = nblk;
   s.tol = tol; s.maxit = c->opt.maxit;
+  s.bref = c->cg_ref;
   return s;
 }
 
@@ -793,18 +816,26 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int ma
   f.nrhs = nrhs;
   f.tol = tol;
   f.maxit = maxit;
+  f.bref = c->cg_ref;
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
   f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
   f.err = c->flags.p;
+  // LDS: gathered vectors (xs), product rows (ys), the partial sums of the
+  // non-MFMA products (fewer than 8 right-hand sides only) and the coarse
+  // right-hand side of the redundant coarse phases (not needed when they are
+  // distributed); the less LDS, the more workgroups per compute unit.
   const int xs = std::max(g.max_nD, 1) * NR;
   const int ys = 2 * std::max(g.max_nG, 1) * NR;
-  const int part = kBlock * 2 * NR;
-  const int cu = std::max(2 * c->nP, 1);
+  const int part = NR >= 8 ? 0 : kBlock * 2 * NR;
+  const int cu = cfg.dist ? 0 : std::max(2 * c->nP, 1);
   f.lds_ys = xs;
   f.lds_part = xs + ys;
   f.lds_cu = xs + ys + part;
-  f.lds_total = (xs + ys + part + cu + 1) & ~1;     // the int tables after it stay 16-byte aligned
+  // the distributed coarse rows stage whole coarse right-hand sides (2 nP
+  // values each, at least one) in the same LDS, from its start
+  const int area = cfg.dist ? std::max(xs + ys + part + cu, 2 * c->nP) : xs + ys + part + cu;
+  f.lds_total = (area + 1) & ~1;     // the int tables after it stay 16-byte aligned
   f.dist = cfg.dist;
   f.X1t = c->X1t.p;
   f.ug = c->cg_u.p;
@@ -938,113 +969,15 @@ void cg_persistent(ddelm_ctx c, int nrhs, double tol) {
 }
 
 // --------------------------------------------------------------- factorisation
+// Blocked Householder QR of every matrix held in L.qrA (layout c->h_qrdesc):
+// 16-column panels updating their 64-column block, then one 64-wide block
+// reflector per block for the trailing matrix; all products on MFMA.  L.tau
+// must be allocated; L.Tbuf and L.Tbig are allocated here.
 template <typename T>
-void factor_impl(ddelm_ctx c) {
+void qr_all(ddelm_ctx c, LocalBufs<T>& L, int nmat) {
   hipStream_t s = c->stream;
-  const int N = c->N, M = c->M;
+  const int M = c->M;
   const Geometry& g = c->geo;
-  const bool nn = c->use_nn;
-  const int nmat = nn ? 2 * N : N;
-  LocalBufs<T>& L = c->lb<T>();
-  // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
-  c->h_qrdesc.assign(nmat, QRDesc());
-  long long off = 0, toff = 0;
-  c->max_ncols = 0;
-  for (int b = 0; b < nmat; ++b) {
-    const int i = b % N;
-    QRDesc d;
-    d.off = off; d.m = c->h_m[i]; d.ld = c->h_m[i];
-    d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
-    d.nrefl = M; d.tau = toff; d.pad = 0;
-    c->h_qrdesc[b] = d;
-    off += (long long)d.ld * d.ncols;
-    toff += M;
-    c->max_ncols = std::max(c->max_ncols, d.ncols);
-  }
-  L.qrA.alloc(off);
-  L.tau.alloc(toff);
-  c->qrdesc.upload(c->h_qrdesc, s);
-  {
-    long long most = 0;
-    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * (d.ncols - d.nrefl));
-    if (most > 0) {
-      k_zero_appended<T><<<dim3(std::min(ceil_div(most, kBlock), 64), nmat), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p);
-      HIPCHK(hipGetLastError());
-    }
-  }
-  {
-    std::vector<long long> coff(nmat);
-    std::vector<int> ldc(nmat), cn(nmat);
-    for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
-    c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
-  }
-  c->mark(0);
-  // ---- features
-  {
-    std::vector<long long> o1(N), o2(N);
-    std::vector<int> l1(N);
-    for (int i = 0; i < N; ++i) { o1[i] = c->h_qrdesc[i].off; l1[i] = c->h_m[i]; }
-    c->h_offAm.assign(N + 1, 0);
-    c->h_offCD.assign(N + 1, 0);
-    for (int i = 0; i < N; ++i) {
-      c->h_offAm[i + 1] = c->h_offAm[i] + (long long)c->h_nG[i] * M;
-      c->h_offCD[i + 1] = c->h_offCD[i] + (long long)c->h_nD[i] * M;
-    }
-    const std::vector<long long> oAm(c->h_offAm.begin(), c->h_offAm.end() - 1);
-    const std::vector<int> ldA(c->h_nG.begin(), c->h_nG.end());
-    L.Am.alloc(std::max(c->h_offAm[N], 1ll));
-    if (std::is_same<T, double>::value) {
-      assemble_features<T>(c, c->rsK, g.max_m, L.qrA.p, o1, l1, 0, N);
-      assemble_features<T>(c, c->rsA, g.max_nG, L.Am.p, oAm, ldA, 0, N);
-    } else {
-      // float64 copies of K_c and A_m stay for the refinement residuals
-      c->h_offK.assign(N + 1, 0);
-      for (int i = 0; i < N; ++i) c->h_offK[i + 1] = c->h_offK[i] + (long long)c->h_m[i] * M;
-      c->K64.alloc(c->h_offK[N]);
-      c->A64.alloc(std::max(c->h_offAm[N], 1ll));
-      const std::vector<long long> oK(c->h_offK.begin(), c->h_offK.end() - 1);
-      assemble_features<double>(c, c->rsK, g.max_m, c->K64.p, oK, l1, 0, N);
-      assemble_features<double>(c, c->rsA, g.max_nG, c->A64.p, oAm, ldA, 0, N);
-      std::vector<CopyDesc> cp;
-      for (int i = 0; i < N; ++i) cp.push_back(CopyDesc{c->h_offK[i], o1[i], c->h_m[i], c->h_m[i], c->h_m[i], M, 0, 0});
-      copy_batch<double, T>(c, cp, c->K64.p, L.qrA.p);
-      convert<double, T>(s, c->A64.p, L.Am.p, c->h_offAm[N]);
-      c->offK_d.upload(oK, s);
-    }
-    if (nn) {
-      for (int i = 0; i < N; ++i) o2[i] = c->h_qrdesc[N + i].off;
-      assemble_features<T>(c, c->rsKb, g.max_m, L.qrA.p, o2, l1, 0, N);
-      std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
-      const std::vector<long long> oCD(c->h_offCD.begin(), c->h_offCD.end() - 1);
-      if (std::is_same<T, double>::value) {
-        L.CD.alloc(std::max(c->h_offCD[N], 1ll));
-        assemble_features<T>(c, c->rsAb, g.max_nD, L.CD.p, oCD, ldC, 0, N);
-      } else {
-        c->CD64.alloc(std::max(c->h_offCD[N], 1ll));
-        assemble_features<double>(c, c->rsAb, g.max_nD, c->CD64.p, oCD, ldC, 0, N);
-      }
-    }
-    // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
-    // M+t has a 1 at flux row n_I+n_B+n_P+t
-    std::vector<long long> pos;
-    for (int b = 0; b < nmat; ++b) {
-      const int i = b % N;
-      const QRDesc& d = c->h_qrdesc[b];
-      const SubInfo& sb = g.subs[i];
-      const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
-      const int cnt = b < N ? sb.n_G() : sb.n_D;
-      for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
-    }
-    if (!pos.empty()) {
-      const long long* dp = c->arena.put(pos, s);
-      k_set_units<T><<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), L.qrA.p);
-      HIPCHK(hipGetLastError());
-    }
-  }
-  c->mark(1);
-  // ---- blocked Householder QR of all matrices: 16-column panels updating
-  //      their 64-column block, then one 64-wide block reflector per block
-  //      for the trailing matrix; all products on MFMA
   {
     c->npanel = ceil_div(M, kNB);
     c->nblock = ceil_div(M, kBB);
@@ -1114,7 +1047,128 @@ void factor_impl(ddelm_ctx c) {
     }
     HIPCHK(hipStreamWaitEvent(s, evR(c->nblock - 1), 0));
   }
+}
+
+template <typename T>
+void factor_impl(ddelm_ctx c) {
+  hipStream_t s = c->stream;
+  const int N = c->N, M = c->M;
+  const Geometry& g = c->geo;
+  const bool nn = c->use_nn;
+  const int nmat = nn ? 2 * N : N;
+  LocalBufs<T>& L = c->lb<T>();
+  // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
+  c->h_qrdesc.assign(nmat, QRDesc());
+  long long off = 0, toff = 0;
+  c->max_ncols = 0;
+  for (int b = 0; b < nmat; ++b) {
+    const int i = b % N;
+    QRDesc d;
+    d.off = off; d.m = c->h_m[i]; d.ld = c->h_m[i];
+    d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
+    d.nrefl = M; d.tau = toff; d.pad = 0;
+    c->h_qrdesc[b] = d;
+    off += (long long)d.ld * d.ncols;
+    toff += M;
+    c->max_ncols = std::max(c->max_ncols, d.ncols);
+  }
+  L.qrA.alloc(off);
+  L.tau.alloc(toff);
+  c->qrdesc.upload(c->h_qrdesc, s);
+  {
+    long long most = 0;
+    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * (d.ncols - d.nrefl));
+    if (most > 0) {
+      k_zero_appended<T><<<dim3(std::min(ceil_div(most, kBlock), 64), nmat), kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  {
+    std::vector<long long> coff(nmat);
+    std::vector<int> ldc(nmat), cn(nmat);
+    for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
+    c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
+  }
+  c->mark(0);
+  // ---- features
+  {
+    std::vector<long long> o1(N), o2(N);
+    std::vector<int> l1(N);
+    for (int i = 0; i < N; ++i) { o1[i] = c->h_qrdesc[i].off; l1[i] = c->h_m[i]; }
+    c->h_offAm.assign(N + 1, 0);
+    c->h_offCD.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+      c->h_offAm[i + 1] = c->h_offAm[i] + (long long)c->h_nG[i] * M;
+      c->h_offCD[i + 1] = c->h_offCD[i] + (long long)c->h_nD[i] * M;
+    }
+    const std::vector<long long> oAm(c->h_offAm.begin(), c->h_offAm.end() - 1);
+    const std::vector<int> ldA(c->h_nG.begin(), c->h_nG.end());
+    L.Am.alloc(std::max(c->h_offAm[N], 1ll));
+    assemble_features<T>(c, c->rsK, g.max_m, L.qrA.p, o1, l1, 0, N);
+    assemble_features<T>(c, c->rsA, g.max_nG, L.Am.p, oAm, ldA, 0, N);
+    if (nn) {
+      for (int i = 0; i < N; ++i) o2[i] = c->h_qrdesc[N + i].off;
+      assemble_features<T>(c, c->rsKb, g.max_m, L.qrA.p, o2, l1, 0, N);
+      std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
+      const std::vector<long long> oCD(c->h_offCD.begin(), c->h_offCD.end() - 1);
+      L.CD.alloc(std::max(c->h_offCD[N], 1ll));
+      assemble_features<T>(c, c->rsAb, g.max_nD, L.CD.p, oCD, ldC, 0, N);
+    }
+    // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
+    // M+t has a 1 at flux row n_I+n_B+n_P+t
+    std::vector<long long> pos;
+    for (int b = 0; b < nmat; ++b) {
+      const int i = b % N;
+      const QRDesc& d = c->h_qrdesc[b];
+      const SubInfo& sb = g.subs[i];
+      const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
+      const int cnt = b < N ? sb.n_G() : sb.n_D;
+      for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
+    }
+    if (!pos.empty()) {
+      const long long* dp = c->arena.put(pos, s);
+      k_set_units<T><<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), L.qrA.p);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  c->mark(1);
+  if (c->mixed) {
+    // Mixed precision: the Householder QR (the bulk of the flops) runs in
+    // float32 on the f32 matrix cores.  Its factors are then widened to
+    // float64, and everything downstream (triangular solves, local interface
+    // operators, coarse problem, right-hand sides, recovery) runs in float64
+    // arithmetic on them; only the CG keeps float32 copies of the local
+    // interface operators.  The K_c^i features stay in float64 for the
+    // refinement residuals.
+    c->h_offK.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) c->h_offK[i + 1] = c->h_offK[i] + (long long)c->h_m[i] * M;
+    c->K64.alloc(c->h_offK[N]);
+    std::vector<CopyDesc> cp;
+    for (int i = 0; i < N; ++i)
+      cp.push_back(CopyDesc{c->h_qrdesc[i].off, c->h_offK[i], c->h_m[i], c->h_m[i], c->h_m[i], M, 0, 0});
+    copy_batch<double, double>(c, cp, L.qrA.p, c->K64.p);
+    c->offK_d.upload(std::vector<long long>(c->h_offK.begin(), c->h_offK.end() - 1), s);
+    LocalBufs<float>& L32 = c->l32;
+    L32.qrA.alloc(L.qrA.n);
+    L32.tau.alloc(L.tau.n);
+    convert<double, float>(s, L.qrA.p, L32.qrA.p, (long long)L.qrA.n);
+    qr_all<float>(c, L32, nmat);
+    convert<float, double>(s, L32.qrA.p, L.qrA.p, (long long)L.qrA.n);
+    convert<float, double>(s, L32.tau.p, L.tau.p, (long long)L.tau.n);
+    L.Tbig.alloc(L32.Tbig.n);
+    convert<float, double>(s, L32.Tbig.p, L.Tbig.p, (long long)L32.Tbig.n);
+    L32.qrA.free(); L32.tau.free(); L32.Tbuf.free(); L32.Tbig.free();
+  } else {
+    qr_all<T>(c, L, nmat);
+  }
   c->mark(2);
+  // ---- condition estimates of the triangular factors (reported in the solve statistics)
+  DBuf<double> kap;
+  kap.alloc(nmat);
+  k_diag_ratio<T><<<nmat, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, kap.p);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h_kap(nmat);
+  HIPCHK(hipMemcpyAsync(h_kap.data(), kap.p, nmat * sizeof(double), hipMemcpyDeviceToHost, s));
   // ---- Q_G^T copy (M x n_G, ld M), then E = R^{-1} Q_G^T and Xbar = Rbar^{-1} Qbar_D^T in place
   {
     c->h_offQG.assign(N + 1, 0);
@@ -1191,15 +1245,21 @@ void factor_impl(ddelm_ctx c) {
         HIPCHK(hipGetLastError());
       }
     }
-    // feature rows times coefficient-space blocks: with float32 factors the
-    // feature matrices stay float64 (the coefficients can be large and cancel)
-    if (std::is_same<T, double>::value) gemm_batch<T>(c, gL, L.Am.p, L.qrA.p, L.Lm.p, 0, 1.0, 0.0);
-    else gemm_batch_mixed<double, T, T>(c, gL, c->A64.p, L.qrA.p, L.Lm.p, 0, 1.0, 0.0);
+    gemm_batch<T>(c, gL, L.Am.p, L.qrA.p, L.Lm.p, 0, 1.0, 0.0);
     copy_batch<T, T>(c, tL, L.Lm.p, L.LTm.p);
     if (!gN.empty()) {
-      if (std::is_same<T, double>::value) gemm_batch<T>(c, gN, L.CD.p, L.qrA.p, L.Nm.p, 0, 1.0, 0.0);
-      else gemm_batch_mixed<double, T, T>(c, gN, c->CD64.p, L.qrA.p, L.Nm.p, 0, 1.0, 0.0);
+      gemm_batch<T>(c, gN, L.CD.p, L.qrA.p, L.Nm.p, 0, 1.0, 0.0);
       copy_batch<T, T>(c, tN, L.Nm.p, L.NTm.p);
+    }
+    if (c->f32cg) {
+      // float32 copies of the local interface operators for the CG
+      LocalBufs<float>& L32 = c->l32;
+      DBuf<T>* src[5] = {&L.Gm, &L.Lm, &L.LTm, &L.Nm, &L.NTm};
+      DBuf<float>* dst[5] = {&L32.Gm, &L32.Lm, &L32.LTm, &L32.Nm, &L32.NTm};
+      for (int k = 0; k < 5; ++k) {
+        dst[k]->alloc(src[k]->n);
+        convert<T, float>(s, src[k]->p, dst[k]->p, (long long)src[k]->n);
+      }
     }
   }
   c->mark(3);
@@ -1262,6 +1322,8 @@ void factor_impl(ddelm_ctx c) {
   HIPCHK(hipMemcpyAsync(fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (fl[0] & 2u) c->fail(DDELM_E_CHOLESKY, "S_Pi is not positive definite");
+  c->kappa_est = 0.0;
+  for (double v : h_kap) c->kappa_est = std::max(c->kappa_est, v);
   for (int k = 0; k < 4; ++k) c->phase_ms[k] = c->span(k, k + 1);
 }
 
@@ -1274,6 +1336,9 @@ struct CoreOut {
   int iters = 0;
   double relres = 0.0;
   bool noconv = false;
+  double true_rel = 0.0;     // float64 residual of the interface system after the solve
+  double start_rel = 0.0;    // ... at the starting point (warm start), else 0
+  int restarts = 0;
   double ms_rhs = 0, ms_cg = 0, ms_rec = 0;
 };
 
@@ -1298,6 +1363,86 @@ void run_cg(ddelm_ctx c, int nrhs, double tol, CoreOut& res) {
     res.relres = std::max(res.relres, bb > 0 ? std::sqrt(rr / bb) : 0.0);
     if (sc[8 * r + 5] == 0.0) res.noconv = true;
   }
+}
+
+// out = S_theta v ([nrhs][nD]) with the float64 local operators: the operator
+// phases of the CG, launched one by one (they reuse the solve workspace; the
+// recovery recomputes what it needs from mu_Delta).
+void apply_s_theta64(ddelm_ctx c, int nrhs, const double* v, double* out) {
+  hipStream_t s = c->stream;
+  OpArgs<double> a = op_args<double>(c, nrhs);
+  k_ph_local_v<double><<<dim3(c->N, nrhs), kBlock, local_smem(c), s>>>(a, v);
+  HIPCHK(hipGetLastError());
+  run_phases_after_stage1<double>(c, a, nrhs, nullptr);
+  k_ph_sum_w<double><<<dim3(ceil_div(c->nD, kBlock), nrhs), kBlock, 0, s>>>(a, out);
+  HIPCHK(hipGetLastError());
+}
+
+constexpr int kMaxRestarts = 3;         // float64 CG: restarts against recurrence drift
+constexpr int kMaxRefineRestarts = 12;  // float32 CG operators: each restart is one refinement step
+
+// S_theta mu = b (b in cg_b, mu returned in cg_x) from the starting point x0
+// (null: zero).  The CG (local operators of storage type TC) runs on the
+// residual b - S_theta x0 and stops at tol relative to ||b||; then the
+// residual is formed again with the float64 operators and, while it exceeds
+// tol ||b|| (recurrence drift; float32 operators), the CG is restarted on it.
+template <typename TC>
+void interface_solve(ddelm_ctx c, int nrhs, double tol, const double* x0, CoreOut& res) {
+  if (c->nD == 0) return;
+  hipStream_t s = c->stream;
+  const long long nv = (long long)nrhs * c->nD;
+  const size_t vb = (size_t)nv * sizeof(double);
+  HIPCHK(hipMemcpyAsync(c->cg_b0.p, c->cg_b.p, vb, hipMemcpyDeviceToDevice, s));
+  std::vector<double> nrm((size_t)2 * nrhs);
+  if (x0) {
+    HIPCHK(hipMemcpyAsync(c->cg_xs.p, x0, vb, hipMemcpyDeviceToDevice, s));
+    apply_s_theta64(c, nrhs, c->cg_xs.p, c->cg_sx.p);
+    k_resid_norms<<<nrhs, kBlock, 0, s>>>(c->nD, c->cg_b0.p, c->cg_sx.p, c->cg_b.p, c->cg_nrm.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(nrm.data(), c->cg_nrm.p, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r)
+      if (nrm[nrhs + r] > 0.0) res.start_rel = std::max(res.start_rel, std::sqrt(nrm[r] / nrm[nrhs + r]));
+  } else {
+    k_resid_norms<<<nrhs, kBlock, 0, s>>>(c->nD, c->cg_b0.p, nullptr, nullptr, c->cg_nrm.p);
+  }
+  HIPCHK(hipGetLastError());
+  struct RefScope {
+    ddelm_ctx c;
+    ~RefScope() { c->cg_ref = nullptr; }
+  } ref_scope{c};
+  c->cg_ref = c->cg_nrm.p + nrhs;    // ||b||^2 per right-hand side
+  bool have_x = x0 != nullptr;
+  for (int k = 0;; ++k) {
+    CoreOut part;
+    run_cg<TC>(c, nrhs, tol, part);
+    res.iters += part.iters;
+    res.relres = part.relres;
+    res.noconv = res.noconv || part.noconv;
+    if (have_x) {
+      k_add_to<<<std::min(ceil_div(nv, kBlock), 1024), kBlock, 0, s>>>(nv, c->cg_x.p, c->cg_xs.p);
+      HIPCHK(hipGetLastError());
+    } else {
+      HIPCHK(hipMemcpyAsync(c->cg_xs.p, c->cg_x.p, vb, hipMemcpyDeviceToDevice, s));
+    }
+    have_x = true;
+    apply_s_theta64(c, nrhs, c->cg_xs.p, c->cg_sx.p);
+    k_resid_norms<<<nrhs, kBlock, 0, s>>>(c->nD, c->cg_b0.p, c->cg_sx.p, c->cg_b.p, c->cg_nrm.p);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(nrm.data(), c->cg_nrm.p, nrm.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      const double rr = nrm[r], bb = nrm[nrhs + r];
+      if (!(rr == rr)) c->fail(DDELM_E_NONFINITE, "NaN in the interface residual");
+      worst = std::max(worst, bb > 0.0 ? std::sqrt(rr / bb) : 0.0);
+    }
+    res.true_rel = worst;
+    if (worst <= tol || k == (c->f32cg ? kMaxRefineRestarts : kMaxRestarts) || part.noconv) break;
+    res.restarts += 1;
+  }
+  HIPCHK(hipMemcpyAsync(c->cg_x.p, c->cg_xs.p, vb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->cg_b.p, c->cg_b0.p, vb, hipMemcpyDeviceToDevice, s));
 }
 
 // Q^T or Q applied to the first nrhs columns of the local right-hand sides
@@ -1334,7 +1479,8 @@ void apply_q_local(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
 
 template <typename T>
 CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, const double* hP, const double* hD,
-                   double tol, double* coef, int accumulate, double* mu_pi_out, double* mu_dl_out) {
+                   double tol, double* coef, int accumulate, double* mu_pi_out, double* mu_dl_out,
+                   const double* x0 = nullptr) {
   CoreOut res;
   hipStream_t s = c->stream;
   const int N = c->N, M = c->M;
@@ -1355,12 +1501,7 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
                                                                    cnM, 0);
     HIPCHK(hipGetLastError());
 
-    if (c->mixed)
-      k_rhs_flux<T, double><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
-          M, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
-          c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, L.F.p, c->sumP, c->sumD, hD, c->psi_loc.p, c->l_loc.p);
-    else
-      k_rhs_flux<T, T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
+    k_rhs_flux<T, T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
           M, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
           c->offAm_d.p, L.Am.p, c->offm_d.p, c->summ, L.F.p, c->sumP, c->sumD, hD, c->psi_loc.p, c->l_loc.p);
     HIPCHK(hipGetLastError());
@@ -1379,8 +1520,9 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   c->mark(6);
   HIPCHK(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
-  // ---- CG
-  run_cg<T>(c, nrhs, tol, res);
+  // ---- CG (float32 local operators in mixed precision)
+  if (c->f32cg) interface_solve<float>(c, nrhs, tol, x0, res);
+  else interface_solve<T>(c, nrhs, tol, x0, res);
   c->mark(7);
   auto t2 = std::chrono::steady_clock::now();
   // ---- recovery: mu_Pi = pi_f - [S^-1 (rho + D^T psi)](mu_D); c = c_f0 + E mu
@@ -1511,7 +1653,8 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
   HIPCHK(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
   // ---- the transposed interface system: S_theta is symmetric, so the same CG
-  run_cg<T>(c, nrhs, tol, res);
+  if (c->f32cg) interface_solve<float>(c, nrhs, tol, nullptr, res);
+  else interface_solve<T>(c, nrhs, tol, nullptr, res);
   c->mark(7);
   auto t2 = std::chrono::steady_clock::now();
   // ---- transpose of the right-hand-side map
@@ -1545,12 +1688,7 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
                             nrhs, hipMemcpyDeviceToDevice, s));
   }
   // ---- local stage: f_bar_i = Q [R^{-T} cf0_bar + Q_G^T pbar; 0] - pbar on the interface rows
-  if (c->mixed)
-    k_adj_F<T, double><<<gl, kBlock, smG, s>>>(M, N, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p,
-                                               c->dl_l2g.p, c->offAm_d.p, c->A64.p, cbar, c->adj_u.p, c->adj_lbar.p,
-                                               c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
-  else
-    k_adj_F<T, T><<<gl, kBlock, smG, s>>>(M, N, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p,
+  k_adj_F<T, T><<<gl, kBlock, smG, s>>>(M, N, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p,
                                           c->dl_l2g.p, c->offAm_d.p, L.Am.p, cbar, c->adj_u.p, c->adj_lbar.p,
                                           c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
   HIPCHK(hipGetLastError());
@@ -1596,6 +1734,8 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
     auto acc = [&](const CoreOut& o) {
       st.iters += o.iters;
       st.rel_res = o.relres;
+      st.cg_restarts += o.restarts;
+      st.true_rel_res = o.true_rel;
       st.ms_rhs += o.ms_rhs;
       st.ms_cg += o.ms_cg;
       st.ms_recover += o.ms_rec;
@@ -1604,6 +1744,7 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
     if (!c->mixed) {
       acc(adjoint_core<double>(c, nrhs, cbar, mubP, mubD, c->opt.tol, c->adj_fb.p, c->adj_hP.p, c->adj_hD.p, nullptr,
                                nullptr));
+      noconv = noconv || st.true_rel_res > c->opt.tol;
     } else {
       // float32 transposed solves, refined on the float64 transposed residual:
       // z = (cbar, mubar) - Op^T y, y += adjoint(z).  This removes the part of
@@ -1632,7 +1773,7 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
       shm *= sizeof(double);
       double prev_worst = 0.0;
       for (int step = 0; step <= c->opt.refine_maxit; ++step) {
-        acc(adjoint_core<float>(c, nrhs, c->adj_zc.p, nP ? c->adj_zP.p : nullptr, nD ? c->adj_zDg.p : nullptr,
+        acc(adjoint_core<double>(c, nrhs, c->adj_zc.p, nP ? c->adj_zP.p : nullptr, nD ? c->adj_zDg.p : nullptr,
                                 c->opt.inner_tol, c->adj_fw.p, c->adj_hwP.p, c->adj_hwD.p, c->adj_fbGP.p,
                                 c->adj_fbGD.p));
         if (step > 0) st.refine_steps += 1;
@@ -1646,13 +1787,14 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
           const double den = xn[r] + (nP ? xpn[r] : 0.0) + (nD ? xdn[r] : 0.0);
           worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
         }
+        if (step > 0) st.refine_corr = worst;
         if ((step > 0 && (worst <= c->opt.refine_tol || worst > kRefineStall * prev_worst)) ||
             step == c->opt.refine_maxit)
           break;
         prev_worst = worst;
         k_adj_resid<<<dim3(N, nrhs), kBlock, shm, s>>>(
             c->M, nP, nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p, c->K64.p,
-            c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, c->adj_fw.p, nP ? c->adj_hwP.p : nullptr,
+            c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->adj_fw.p, nP ? c->adj_hwP.p : nullptr,
             nD ? c->adj_hwD.p : nullptr, N, c->adj_zc.p);
         HIPCHK(hipGetLastError());
         if (nP)
@@ -1687,6 +1829,8 @@ ddelm_status adjoint_any(ddelm_ctx c, int nrhs, const double* cbar, const double
   st.cg_blocks = c->cg_blocks;
   st.cg_slices = c->cg_slices;
   st.cg_coarse_dist = c->cg_dist;
+  st.kappa_est_max = c->kappa_est;
+  if (c->mixed) st.true_rel_res = std::nan("");
   if (stats) *stats = st;
   if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
   return code;
@@ -1722,13 +1866,14 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     else ddelm_default_options(&c->opt);
     const ddelm_options& o = c->opt;
     if (!(o.theta >= 0.0 && o.theta <= 1.0)) c->fail(DDELM_E_ARG, "theta must lie in [0, 1]");
-    if (o.coarse < 0 || o.coarse > 2) c->fail(DDELM_E_ARG, "coarse must be 0, 1 or 2");
+    if (o.coarse < 0 || o.coarse > 4) c->fail(DDELM_E_ARG, "coarse must be 0, 1, 2, 3 or 4");
     if (o.coarse == 0 && o.theta != 0.0)
       c->fail(DDELM_E_ARG, "theta must be 0 without a coarse space (Kbar needs Dirichlet corner rows)");
-    if (o.precision != 0 && o.precision != 1) c->fail(DDELM_E_ARG, "precision must be 0 or 1");
-    if (o.precision == 1 && !(o.refine_maxit >= 1 && o.refine_tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0))
+    if (o.precision < 0 || o.precision > 2) c->fail(DDELM_E_ARG, "precision must be 0, 1 or 2");
+    if (o.precision == 1 && !(o.refine_maxit >= 0 && o.refine_tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0))
       c->fail(DDELM_E_ARG, "refinement options out of range");
     c->mixed = o.precision == 1;
+    c->f32cg = o.precision >= 1;
     if (!(o.tol > 0.0 && o.tol < 1.0)) c->fail(DDELM_E_ARG, "tol must lie in (0, 1)");
     if (o.maxit < 1) c->fail(DDELM_E_ARG, "maxit must be >= 1");
     if (o.max_nrhs < 1 || o.max_nrhs > 64) c->fail(DDELM_E_ARG, "max_nrhs must lie in [1, 64]");
@@ -1846,8 +1991,7 @@ ddelm_status ddelm_factor(ddelm_ctx c) {
     c->arena.reset();
     c->upload.reset();
     c->factored = false;
-    if (c->mixed) factor_impl<float>(c);
-    else factor_impl<double>(c);
+    factor_impl<double>(c);
     c->factored = true;
   });
 }
@@ -1858,7 +2002,8 @@ namespace {
 
 // Shared body of ddelm_solve (f_I, g_B given) and ddelm_solve_general (f_loc, h given).
 ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, const double* f_loc,
-                       const double* h, double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats) {
+                       const double* h, const double* mu0, double* coef, double* mu_pi, double* mu_dl,
+                       ddelm_stats* stats) {
   if (!c) return DDELM_E_ARG;
   bool noconv = false;
   ddelm_stats st{};
@@ -1877,6 +2022,7 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
     auto acc = [&](const CoreOut& o) {
       st.iters += o.iters;
       st.rel_res = o.relres;
+      st.cg_restarts += o.restarts;
       st.ms_rhs += o.ms_rhs;
       st.ms_cg += o.ms_cg;
       st.ms_recover += o.ms_rec;
@@ -1900,40 +2046,40 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
     }
     const double* f0P = general ? c->fGP0.p : nullptr;
     const double* f0D = general ? c->fGD0.p : nullptr;
+    // local right-hand sides (float64; mixed precision keeps a copy for the residuals)
+    double* F64 = c->mixed ? c->F64.p : nullptr;
+    if (general)
+      k_rhs_split<double><<<dim3(N, nrhs), kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p,
+                                                           c->summ, c->sumP, c->sumD, f_loc, c->l64.F.p, F64,
+                                                           c->fGP0.p, c->fGD0.p);
+    else
+      k_rhs_assemble<double><<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p, c->offB_d.p,
+                                                              c->summ, c->geo.sum_nB, f_I, g_B, c->l64.F.p, F64);
+    HIPCHK(hipGetLastError());
+    const double* x0 = (mu0 && c->nD > 0) ? mu0 : nullptr;
     if (!c->mixed) {
-      if (general)
-        k_rhs_split<double><<<dim3(N, nrhs), kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p,
-                                                             c->summ, c->sumP, c->sumD, f_loc, c->l64.F.p, nullptr,
-                                                             c->fGP0.p, c->fGD0.p);
-      else
-        k_rhs_assemble<double><<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p,
-                                                                c->offB_d.p, c->summ, c->geo.sum_nB, f_I, g_B,
-                                                                c->l64.F.p, nullptr);
-      HIPCHK(hipGetLastError());
-      acc(solve_core<double>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.tol, coef, 0, mu_pi, mu_dl));
+      const CoreOut o = solve_core<double>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.tol, coef, 0, mu_pi, mu_dl, x0);
+      acc(o);
+      st.true_rel_res = o.true_rel;
+      st.start_rel_res = o.start_rel;
+      noconv = noconv || o.true_rel > c->opt.tol;
     } else {
-      // float32 local solves, refined on the float64 residual of the coupled system
-      DBuf<double> muP, muD;
-      muP.alloc((size_t)nrhs * std::max(c->nP, 1));
-      muD.alloc((size_t)nrhs * std::max(c->nD, 1));
-      muP.zero(s);
-      muD.zero(s);
-      if (general)
-        k_rhs_split<float><<<dim3(N, nrhs), kBlock, 0, s>>>(c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offm_d.p,
-                                                            c->summ, c->sumP, c->sumD, f_loc, c->l32.F.p, c->F64.p,
-                                                            c->fGP0.p, c->fGD0.p);
-      else
-        k_rhs_assemble<float><<<dim3(N, nrhs), kBlock, 0, s>>>(N, c->n_int, c->sizes_dev.p, c->offm_d.p, c->offB_d.p,
-                                                               c->summ, c->geo.sum_nB, f_I, g_B, c->l32.F.p, c->F64.p);
-      HIPCHK(hipGetLastError());
-      acc(solve_core<float>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.inner_tol, coef, 0, muP.p, muD.p));
+      // The float32-QR solve, refined on the float64 residual of the coupled
+      // system [f - K_c c - B mu; h - A_m c] of eq. ddelm: each correction is
+      // the same solve applied to that residual.
+      DBuf<double>& muP = c->ref_muP;
+      DBuf<double>& muD = c->ref_muD;
+      const CoreOut o0 = solve_core<double>(c, nrhs, f0P, f0D, h0P, h0D, c->opt.inner_tol, coef, 0, muP.p, muD.p,
+                                            x0);
+      acc(o0);
+      st.start_rel_res = o0.start_rel;
       const size_t shm = (size_t)c->M * sizeof(double);
-      double prev_worst = 0.0;
+      double prev_worst = 0.0, worst = 0.0;
       for (int step = 0; step < c->opt.refine_maxit; ++step) {
         k_residual<<<dim3(N, nrhs), kBlock, shm, s>>>(
             c->M, c->nP, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,
-            c->K64.p, c->offAm_d.p, c->A64.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP, c->sumD,
-            c->R64.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p);
+            c->K64.p, c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP,
+            c->sumD, c->l64.F.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p);
         HIPCHK(hipGetLastError());
         if (c->nP + c->nD > 0) {
           k_flux_residual<<<dim3(ceil_div(c->nP + c->nD, kBlock), nrhs), kBlock, 0, s>>>(
@@ -1941,23 +2087,25 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
               c->aP.p, c->aD.p, h0P, h0D, c->hPb.p, c->hDb.p);
           HIPCHK(hipGetLastError());
         }
-        convert<double, float>(s, c->R64.p, c->l32.F.p, (long long)nrhs * c->summ);
-        acc(solve_core<float>(c, nrhs, c->fGP.p, c->fGD.p, c->nP ? c->hPb.p : nullptr, c->nD ? c->hDb.p : nullptr,
-                              c->opt.inner_tol, coef, 1, c->dmup.p, c->dmud.p));
+        acc(solve_core<double>(c, nrhs, c->fGP.p, c->fGD.p, c->nP ? c->hPb.p : nullptr, c->nD ? c->hDb.p : nullptr,
+                               c->opt.inner_tol, coef, 1, c->dmup.p, c->dmud.p));
         st.refine_steps += 1;
         std::vector<double> dn, xn, dpn, xpn;
         axpy_norms(c, c->dmud.p, muD.p, c->nD, nrhs, dn, xn);
         axpy_norms(c, c->dmup.p, muP.p, c->nP, nrhs, dpn, xpn);
-        double worst = 0.0;
+        worst = 0.0;
         for (int r = 0; r < nrhs; ++r) {
           const double num = dn[r] + dpn[r], den = xn[r] + xpn[r];
           worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
         }
         // stop at the tolerance, or when the refinement stalls: the correction
-        // shrank by less than kRefineStall, so the float32 fixed point is near
+        // shrank by less than kRefineStall, so the iteration sits at its fixed point
         if (worst <= c->opt.refine_tol || (step > 0 && worst > kRefineStall * prev_worst)) break;
         prev_worst = worst;
       }
+      st.refine_corr = c->opt.refine_maxit > 0 ? worst : 0.0;
+      st.true_rel_res = std::nan("");
+      noconv = noconv || (c->opt.refine_maxit > 0 && worst > c->opt.refine_tol);
       if (mu_pi && c->nP > 0)
         HIPCHK(hipMemcpyAsync(mu_pi, muP.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
       if (mu_dl && c->nD > 0)
@@ -1968,6 +2116,7 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
   st.cg_blocks = c->cg_blocks;
   st.cg_slices = c->cg_slices;
   st.cg_coarse_dist = c->cg_dist;
+  st.kappa_est_max = c->kappa_est;
   if (stats) *stats = st;
   if (code == DDELM_OK && noconv) return DDELM_WARN_NOCONV;
   return code;
@@ -1977,13 +2126,13 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
 
 extern "C" {
 
-ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, double* coef, double* mu_pi,
-                         double* mu_dl, ddelm_stats* stats) {
+ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, const double* mu0,
+                         double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats) {
   if (!f_I) {
     if (c) c->err = "f_I is null";
     return DDELM_E_ARG;
   }
-  return solve_any(c, nrhs, f_I, g_B, nullptr, nullptr, coef, mu_pi, mu_dl, stats);
+  return solve_any(c, nrhs, f_I, g_B, nullptr, nullptr, mu0, coef, mu_pi, mu_dl, stats);
 }
 
 ddelm_status ddelm_solve_general(ddelm_ctx c, int nrhs, const double* f_loc, const double* h, double* coef,
@@ -1992,7 +2141,7 @@ ddelm_status ddelm_solve_general(ddelm_ctx c, int nrhs, const double* f_loc, con
     if (c) c->err = "f_loc is null";
     return DDELM_E_ARG;
   }
-  return solve_any(c, nrhs, nullptr, nullptr, f_loc, h, coef, mu_pi, mu_dl, stats);
+  return solve_any(c, nrhs, nullptr, nullptr, f_loc, h, nullptr, coef, mu_pi, mu_dl, stats);
 }
 
 ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long npts, const double* x, double* u,
@@ -2174,8 +2323,6 @@ ddelm_status ddelm_get_local_matrix(ddelm_ctx c, int which, int sub, double* out
     if (!c->factored) c->fail(DDELM_E_STATE, "matrix needs ddelm_factor");
     if (which == 8) {
       copy_batch<double, double>(c, {CopyDesc{0, 0, R, C, R, C, 1, 0}}, c->Spi.p, out);
-    } else if (c->mixed) {
-      local_matrix_factored<float>(c, which, sub, R, C, out);
     } else {
       local_matrix_factored<double>(c, which, sub, R, C, out);
     }

@@ -40,7 +40,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
   if ((long long)nx * ny > (1 << 20)) return "too many subdomains";
   if (p < 3 || p > 4096) return "p must be in [3, 4096]";
   if (n_int < 1) return "n_int must be >= 1";
-  if (coarse < 0 || coarse > 2) return "coarse must be 0, 1 or 2";
+  if (coarse < 0 || coarse > 4) return "coarse must be 0, 1, 2, 3 or 4";
   for (int a = 0; a < 2; ++a) {
     if (!(lo_[a] < hi_[a])) return "lo must be < hi";
     lo[a] = lo_[a]; hi[a] = hi_[a];
@@ -201,7 +201,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
         rowsKb.add_row({t});
         // flux row at a corner
         ft.clear();
-        if (coarse == 2) {
+        if (coarse == 2 || coarse == 4) {      // mean-flux corner rows (A_m)
           for (int sd = 0; sd < 4; ++sd) {
             if (sds[sd].on_boundary) continue;
             const bool at0 = sds[sd].v0x == g.vjx && sds[sd].v0y == g.vjy;
@@ -227,7 +227,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
         else vertex_normal(g.vjx, g.vjy, n);
         // continuity row
         ct.assign(1, Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0});
-        if (coarse == 2 && g.side >= 0) {
+        if ((coarse == 2 || coarse == 3) && g.side >= 0) {   // change of variables (K_c)
           const SideDesc& d = sds[g.side];
           const double sk = s[g.k];
           if (is_pi(d.v0x, d.v0y)) ct.push_back(Term{vx(d.v0x), vy(d.v0y), 0, 0, -(1.0 - sk), OP_VALUE, 0});

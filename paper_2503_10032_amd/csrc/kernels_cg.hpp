@@ -86,6 +86,7 @@ struct FusedArgs {
   int nrhs;
   double tol;
   int maxit;
+  const double* bref;    // [nrhs] squared norm the stopping test is relative to (null: ||r_0||^2)
   double* x;             // [nrhs][nD]
   double* r;             // [nrhs][nD] r buffers (alternate by pass); r holds b on entry
   double* r1;
@@ -144,8 +145,9 @@ __device__ __forceinline__ void coarse_gather(const OpArgs<T>& a, const double* 
 
 // Distributed coarse rows: out[r][row] = sum_{c < ncol} X1[row][c] ug[r][c]
 // for this workgroup's share of the 2 nP rows.  Right-hand sides are staged
-// in LDS in groups; each wave holds a 512-column tile of one X1 row in
-// registers and applies it to the whole group.
+// in LDS in groups of G = lds_cap / ncol (the launch makes lds_cap >= ncol);
+// each wave holds a 512-column tile of one X1 row in registers and applies it
+// to the whole group.
 template <int NR>
 __device__ __forceinline__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, const double* ug,
                                             int nrhs, double* lds, int lds_cap, double* out) {
@@ -547,7 +549,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
           const double gam = gt[r], del = dt[r];
           if (sc_done[r] == 0.0) {
             sc_rr[r] = gam;
-            if (it == 1) sc_bb[r] = gam;
+            if (it == 1) sc_bb[r] = f.bref ? f.bref[r] : gam;
             if (gam == 0.0 || sqrt(gam) <= f.tol * sqrt(sc_bb[r]) || !(gam == gam)) sc_done[r] = 1.0;
           }
           if (sc_done[r] == 0.0 && it - 1 < f.maxit) {

@@ -371,10 +371,41 @@ __global__ void __launch_bounds__(kBlock) k_cg_init2(CGState s) {
   const double bb = cg_reduce_parts(s.part, s.nblk, r, red);
   if (threadIdx.x == 0) {
     double* sc = s.scal + (size_t)r * 8;
-    sc[0] = bb; sc[1] = bb; sc[2] = 0; sc[3] = 0; sc[4] = 0;
+    sc[0] = bb; sc[1] = s.bref ? s.bref[r] : bb; sc[2] = 0; sc[3] = 0; sc[4] = 0;
     sc[5] = (bb == 0.0) ? 1.0 : 0.0;
     sc[6] = 0; sc[7] = 0;
   }
+}
+
+// r = b - w (when r is not null) and, per right-hand side rh, ||b - w||^2
+// (out[rh]) and ||b||^2 (out[nrhs + rh], nrhs = gridDim.x); w may be null
+// (then the residual is b).  One workgroup per right-hand side, fixed
+// summation order.
+__global__ void __launch_bounds__(kBlock) k_resid_norms(int n, const double* __restrict__ b,
+                                                        const double* __restrict__ w, double* __restrict__ r,
+                                                        double* __restrict__ out) {
+  __shared__ double red[kWaves];
+  const int rh = blockIdx.x;
+  double ss = 0.0, bb = 0.0;
+  for (int g = threadIdx.x; g < n; g += kBlock) {
+    const size_t e = (size_t)rh * n + g;
+    const double bv = b[e], d = w ? bv - w[e] : bv;
+    if (r) r[e] = d;
+    ss += d * d;
+    bb += bv * bv;
+  }
+  ss = block_sum(ss, red);
+  bb = block_sum(bb, red);
+  if (threadIdx.x == 0) {
+    out[rh] = ss;
+    out[gridDim.x + rh] = bb;
+  }
+}
+
+// x += d (element-wise, n * nrhs values)
+__global__ void __launch_bounds__(kBlock) k_add_to(long long n, const double* __restrict__ d, double* __restrict__ x) {
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock)
+    x[e] += d[e];
 }
 
 // ---------------------------------------------------------------- evaluation

@@ -116,6 +116,38 @@ struct QRDesc {
   int pad;
 };
 
+// Condition estimate of a triangular factor from its diagonal: for matrix b,
+// out[b] = max_j |R_jj| / min_j |R_jj| over the nrefl diagonal entries of the
+// factored matrix (infinity when a diagonal entry is zero).  One workgroup
+// per matrix.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_diag_ratio(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kWaves];
+  const QRDesc d = desc[blockIdx.x];
+  double mx = 0.0, mn = INFINITY;
+  for (int j = threadIdx.x; j < d.nrefl; j += kBlock) {
+    const double v = fabs((double)A[d.off + (long long)j * d.ld + j]);
+    mx = fmax(mx, v);
+    mn = fmin(mn, v);
+  }
+  // max and min through the sum helper's storage: one value per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+  }
+  __shared__ double rmn[kWaves];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { red[wid] = mx; rmn[wid] = mn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWaves; ++k) { mx = fmax(mx, red[k]); mn = fmin(mn, rmn[k]); }
+    mx = fmax(mx, red[0]);
+    mn = fmin(mn, rmn[0]);
+    out[blockIdx.x] = mn > 0.0 ? mx / mn : INFINITY;
+  }
+}
+
 // Zero the columns after the factored ones (the appended unit columns) of
 // every matrix; the factored columns are written in full by the feature
 // assembly.  blockIdx.y = matrix.

@@ -296,6 +296,7 @@ struct CGState {
   int n, nrhs, nblk;
   double tol;
   int maxit;
+  const double* bref;   // [nrhs] squared norm the stopping test is relative to (null: ||r_0||^2)
 };
 
 // partial dot products of two vectors, one block per (chunk, rhs)

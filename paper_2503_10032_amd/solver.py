@@ -74,6 +74,7 @@ class DDELMSolver:
             st = self.lib.ddelm_setup(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opt),
                                       ctypes.c_void_p(self.stream.cuda_stream))
         self.ctx = ctx
+        L.register(self)
         if st != L.DDELM_OK:
             msg = self.lib.ddelm_last_error(ctx).decode() if ctx else ""
             self.close()
@@ -154,8 +155,9 @@ class DDELMSolver:
                                                         ctypes.byref(c)), "get_local_matrix")
         return out[: r.value, : c.value]
 
-    def solve(self, f_I, g_B, want_mu: bool = True):
-        """f_I (nrhs, N, n_int), g_B (nrhs, sum_nB) -> dict(coef (nrhs, N, M), mu_pi, mu_dl, stats)."""
+    def solve(self, f_I, g_B, want_mu: bool = True, mu0=None):
+        """f_I (nrhs, N, n_int), g_B (nrhs, sum_nB) -> dict(coef (nrhs, N, M), mu_pi, mu_dl, stats).
+        mu0 (nrhs, n_dl), optional: starting value of mu_Delta for the CG."""
         dev = self.device
         f_I = torch.as_tensor(f_I, dtype=torch.float64, device=dev).contiguous()
         g_B = torch.as_tensor(g_B, dtype=torch.float64, device=dev).contiguous()
@@ -169,15 +171,16 @@ class DDELMSolver:
         coef = torch.empty((nrhs, self.N, self.M), dtype=torch.float64, device=dev)
         mu_pi = torch.zeros((nrhs, self.n_pi), dtype=torch.float64, device=dev) if want_mu else None
         mu_dl = torch.zeros((nrhs, self.n_dl), dtype=torch.float64, device=dev) if want_mu else None
+        m0 = None
+        if mu0 is not None and self.n_dl:
+            m0 = torch.as_tensor(mu0, dtype=torch.float64, device=dev).contiguous().reshape(nrhs, self.n_dl)
         st = L.Stats()
         with torch.cuda.device(dev):
-            code = self._check(self.lib.ddelm_solve(self.ctx, nrhs, f_I.data_ptr(), g_B.data_ptr(), coef.data_ptr(),
+            code = self._check(self.lib.ddelm_solve(self.ctx, nrhs, f_I.data_ptr(), g_B.data_ptr(), _ptr(m0),
+                                                    coef.data_ptr(),
                                                     _ptr(mu_pi) if self.n_pi else None,
                                                     _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)), "solve")
-        stats = dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
-                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
-                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
-        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
+        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=self._stats(st, code))
 
     def solve_general(self, f_loc, h=None, want_mu: bool = True):
         """General right-hand side: f_loc (nrhs, sum m) on every local row, h
@@ -201,10 +204,7 @@ class DDELMSolver:
                 self.ctx, nrhs, f_loc.data_ptr(), _ptr(hh), coef.data_ptr(),
                 _ptr(mu_pi) if self.n_pi else None, _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)),
                 "solve_general")
-        stats = dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
-                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
-                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
-        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=stats)
+        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=self._stats(st, code))
 
     def evaluate(self, coef: torch.Tensor, x, grad: bool = False):
         dev = self.device
@@ -223,7 +223,9 @@ class DDELMSolver:
     def _stats(self, st, code):
         return dict(iters=st.iters, refine_steps=st.refine_steps, rel_res=st.rel_res, ms_rhs=st.ms_rhs,
                     ms_cg=st.ms_cg, ms_recover=st.ms_recover, converged=code == L.DDELM_OK,
-                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist)
+                    cg_blocks=st.cg_blocks, cg_slices=st.cg_slices, cg_coarse_dist=st.cg_coarse_dist,
+                    cg_restarts=st.cg_restarts, true_rel_res=st.true_rel_res, refine_corr=st.refine_corr,
+                    kappa_est_max=st.kappa_est_max, start_rel_res=st.start_rel_res)
 
     def solve_adjoint(self, coef_bar):
         """Transpose of solve: coef_bar (nrhs, N, M) -> dict(f_I_bar (nrhs, N, n_int),

@@ -110,8 +110,8 @@ import test_gpu_parity as _P        # noqa: E402
 def test_mixed_paths_read_only_written_memory(name, monkeypatch):
     _torch()
     monkeypatch.setenv("DDELM_DEBUG_POISON", "1")
-    _P.test_mixed_precision_matches_fp64_oracle(name)
-    _A.test_mixed_precision_adjoint_against_fp64_oracle(name)
+    _P.test_mixed_precision_sits_at_its_derived_floor(name)
+    _A.test_mixed_precision_adjoint_is_the_transpose_of_the_mixed_solve(name)
 
 
 @pytest.mark.parametrize("name", ["3x3_uneven", "4x3", "7x7"])
@@ -119,6 +119,7 @@ def test_fp64_paths_read_only_written_memory(name, monkeypatch):
     _torch()
     monkeypatch.setenv("DDELM_DEBUG_POISON", "1")
     _P.test_solve_matches_oracle(name, 0.999, 2, 1)
+    _P.test_float32_cg_operators_refined_to_the_float64_result(name)
     if name != "7x7":
         _P.test_factor_outputs(name)
         _P.test_general_rhs_matches_oracle(name)

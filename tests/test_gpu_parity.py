@@ -87,7 +87,7 @@ def test_indexing_bit_exact(name, coarse):
 # ------------------------------------------------------------------ local matrices
 
 @pytest.mark.parametrize("name", ["small", "3x3_uneven"])
-@pytest.mark.parametrize("coarse", [1, 2])
+@pytest.mark.parametrize("coarse", [1, 2, 3, 4])
 def test_feature_matrices(name, coarse):
     c = Case(**CASES[name], coarse=coarse)
     g = c.gpu()
@@ -148,10 +148,21 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+# Both sides stop once the relative residual of S_theta mu = b is below the
+# solve tolerance (the library checks its float64 residual after the CG), so
+# each mu is within cond(S_theta) * tol of the exact one: the two differ by
+# at most 2 cond(S_theta) tol.  cond(S_theta) is the oracle's Lanczos
+# estimate from its CG coefficients (from inside the spectrum, so a further
+# factor 2), and the benchmark spec's 1e-10 is the bar wherever that bound is lower.
+def mu_tol(ref, tol):
+    return max(1e-10, 4.0 * ref["kappa"] * tol)
+
+
 @pytest.mark.parametrize("name,theta,coarse", [
     ("small", 0.999, 2), ("small", 0.0, 2), ("small", 0.999, 1), ("small", 0.5, 2),
     ("3x3_uneven", 0.999, 2), ("4x3", 0.999, 2), ("4x3", 1.0, 2),
     ("strip_no_pi", 0.999, 2), ("single", 0.999, 2), ("4x3", 0.0, 0), ("7x7", 0.999, 2),
+    ("4x3", 0.999, 3), ("4x3", 0.0, 3), ("4x3", 0.999, 4), ("3x3_uneven", 0.0, 4),
 ])
 @pytest.mark.parametrize("cg_mode", [1, 2])
 def test_solve_matches_oracle(name, theta, coarse, cg_mode):
@@ -163,9 +174,11 @@ def test_solve_matches_oracle(name, theta, coarse, cg_mode):
     u_ref = O.evaluate(geo, c.W, c.b, ref["c"], X)
     assert _rel(u, u_ref) < 1e-10, _rel(u, u_ref)
     if s.nD:
-        assert _rel(out["mu_dl"][0].cpu().numpy(), ref["mu_dl"]) < 1e-9
+        assert _rel(out["mu_dl"][0].cpu().numpy(), ref["mu_dl"]) < mu_tol(ref, c.tol)
     if s.nP:
-        assert _rel(out["mu_pi"][0].cpu().numpy(), ref["mu_pi"]) < 1e-9
+        assert _rel(out["mu_pi"][0].cpu().numpy(), ref["mu_pi"]) < mu_tol(ref, c.tol)
+    # the float64 residual of eq. nn-mixed at the returned mu meets the tolerance
+    assert out["stats"]["true_rel_res"] <= c.tol
     # iteration counts of two CG runs on the same operator agree closely
     assert abs(out["stats"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
 
@@ -191,22 +204,25 @@ def test_general_rhs_matches_oracle(name):
     for r in range(2):
         assert _rel(u[r], O.evaluate(geo, c.W, c.b, refs[r]["c"], X)) < 1e-9
         if s.nD:
-            assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < 1e-9
+            assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < mu_tol(refs[r], c.tol)
         if s.nP:
-            assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < 1e-9
+            assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < mu_tol(refs[r], c.tol)
 
 
-@pytest.mark.parametrize("nrhs", [4, 12])
+@pytest.mark.parametrize("nrhs", [4, 12, 16, 20])
 def test_multi_rhs_matches_oracle(nrhs):
-    # 12 right-hand sides: the CG with MFMA local products and the evaluation with 16 per thread
+    # 12 and 16 right-hand sides: the persistent CG with MFMA local products (16
+    # fills its tile) and the evaluation with 16 per thread; 20: more than one
+    # persistent launch holds, so the CG runs phase by phase
     c = Case(nx=3, ny=3, M=40, n_int=6, p=8, a=2.0, seed=5, extra=True, tol=1e-12, rhs="fourier", nrhs=nrhs)
     g, geo, s, out, refs = _solve_both(c)
     X = I.eval_grid(c.w)
     u = g.evaluate(out["coef"], X).cpu().numpy()
+    assert out["stats"]["true_rel_res"] <= c.tol
     for r in range(c.nrhs):
         u_ref = O.evaluate(geo, c.W, c.b, refs[r]["c"], X)
         assert _rel(u[r], u_ref) < 1e-10
-        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < 1e-9
+        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < mu_tol(refs[r], c.tol)
 
 
 @pytest.mark.parametrize("name,nrhs", [("4x3", 1), ("7x7", 1), ("3x3_uneven", 4)])
@@ -220,8 +236,8 @@ def test_distributed_coarse_phases_match_oracle(name, nrhs, monkeypatch):
     u = g.evaluate(out["coef"], X).cpu().numpy()
     for r in range(nrhs):
         assert _rel(u[r], O.evaluate(geo, c.W, c.b, refs[r]["c"], X)) < 1e-10
-        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < 1e-9
-        assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < 1e-9
+        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) < mu_tol(refs[r], c.tol)
+        assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < mu_tol(refs[r], c.tol)
 
 
 def test_cg_modes_agree_and_runs_repeat_bitwise():
@@ -269,18 +285,66 @@ def test_noconvergence_is_reported():
     assert not out["stats"]["converged"] and out["stats"]["iters"] == 2
 
 
-# ------------------------------------------------------------------ mixed precision (float32 local solves + refinement)
-#
-# Refinement on the float64 residual of the coupled system converges to a
-# fixed point whose distance from the float64 result is set by the float32
-# local operators times the least-squares residual of the ELM fit; it does
-# not vanish.  Measured on these moderately conditioned problems it is
-# 1-4e-6 in u and up to ~4e-5 in mu (relative L2), above the 1e-6 target;
-# MIXED_TOL and MIXED_TOL_MU state those measured levels, and the design
-# notes list the gap.
+# ------------------------------------------------------------------ boundary fields: warm start, true residual, kappa
 
-MIXED_TOL = 5e-6
-MIXED_TOL_MU = 1e-4
+def test_warm_start_true_residual_and_condition_estimate():
+    c = Case(**CASES["4x3"], tol=1e-12)
+    g = c.gpu().factor()
+    geo, s = c.oracle()
+    xB = g.boundary_points().cpu().numpy()
+    fI, gB = I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None]
+    out = g.solve(fI, gB)
+    st = out["stats"]
+    assert st["converged"] and st["true_rel_res"] <= c.tol
+    # condition estimate max|R_jj| / min|R_jj| against the oracle's factors of K_c^i and Kbar^i
+    kap = max(np.abs(np.diag(L.R)).max() / np.abs(np.diag(L.R)).min() for L in s.ls + s.lsb)
+    assert abs(st["kappa_est_max"] - kap) <= 1e-6 * kap, (st["kappa_est_max"], kap)
+    mu = out["mu_dl"]
+    # started at the solution the CG has nothing left to do
+    warm = g.solve(fI, gB, mu0=mu)
+    assert warm["stats"]["iters"] <= 1 and warm["stats"]["true_rel_res"] <= c.tol
+    assert _rel(warm["mu_dl"][0].cpu().numpy(), mu[0].cpu().numpy()) < 1e-12
+    # from a perturbed start it converges to the same solution
+    rng = np.random.default_rng(3)
+    noisy = mu + 0.1 * mu.abs().max() * __import__("torch").as_tensor(rng.standard_normal(mu.shape), device=mu.device)
+    again = g.solve(fI, gB, mu0=noisy)
+    assert again["stats"]["converged"] and again["stats"]["true_rel_res"] <= c.tol
+    ref = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-13, maxit=20000)
+    assert _rel(again["mu_dl"][0].cpu().numpy(), mu[0].cpu().numpy()) < mu_tol(ref, c.tol)
+
+
+# ------------------------------------------------------------------ precision 2: float64 factors, float32 CG operators
+
+@pytest.mark.parametrize("name", ["small", "3x3_uneven", "4x3", "7x7"])
+def test_float32_cg_operators_refined_to_the_float64_result(name):
+    """The CG runs on float32 copies of the local operators; its result is
+    refined on the float64 interface residual until that meets tol, so the
+    result is the float64 one."""
+    c = Case(**CASES[name], tol=1e-12)
+    g = c.gpu(precision=2).factor()
+    geo, s = c.oracle()
+    ref = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-13, maxit=20000)
+    xB = g.boundary_points().cpu().numpy()
+    out = g.solve(I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None])
+    st = out["stats"]
+    assert st["converged"] and st["true_rel_res"] <= c.tol
+    X = I.eval_grid(c.w)
+    u = g.evaluate(out["coef"], X)[0].cpu().numpy()
+    assert _rel(u, O.evaluate(geo, c.W, c.b, ref["c"], X)) < 1e-10
+    if s.nD:
+        assert _rel(out["mu_dl"][0].cpu().numpy(), ref["mu_dl"]) < mu_tol(ref, c.tol)
+
+
+# ------------------------------------------------------------------ precision 1: float32 QR + float64 refinement
+#
+# Refinement on the float64 residual r = y - Psi z of the coupled system
+# Psi z = y (eq. ddelm) with the float32-QR solve F32 as the correction has
+# the fixed point z_inf = (F32 Psi)^{-1} F32 y.  With z* = F64 y the float64
+# result and r* = y - Psi z* its least-squares residual (F64 r* = 0 but
+# F32 r* != 0), z_inf - z* = (F32 Psi)^{-1} F32 r*, so while the refinement
+# contracts (||I - F32 Psi|| <= 1/2) the distance from the float64 result is
+# at most 2 ||F32 r*||.  The tests compute F32 r* on the GPU from the
+# oracle's float64 residual and hold the refined result to that bound.
 
 MIXED = {
     "2x2_M64": dict(nx=2, ny=2, M=64, n_int=16, p=16, a=2.0, seed=0),
@@ -289,61 +353,100 @@ MIXED = {
 }
 
 
+def _coupled_residual(s, f, ref, h=None):
+    """r* = [f - K_c c - B mu; h - A_m c] of the oracle's float64 solution, in
+    the layout of ddelm_solve_general (local rows subdomain by subdomain; flux
+    rows Pi then Delta)."""
+    Kc = s.Kmul(ref["c"])
+    BP, BD = s.B_Pi(ref["mu_pi"]), s.B_Dl(ref["mu_dl"])
+    rf = np.concatenate([f[i] - Kc[i] - BP[i] - BD[i] for i in range(s.N)])
+    hP = np.zeros(s.nP) if h is None else h[0]
+    hD = np.zeros(s.nD) if h is None else h[1]
+    rh = np.concatenate([hP - s.A_Pi(ref["c"]), hD - s.A_Dl(ref["c"])])
+    return rf, rh
+
+
+def _float32_floor(c, rfs, rhs, X, u_norms, mu_norms):
+    """||F32 r*|| in u on the evaluation grid and in mu_Delta, relative."""
+    g0 = c.gpu(precision=1, refine_maxit=0, inner_tol=1e-12, max_nrhs=len(rfs)).factor()
+    fl = g0.solve_general(np.stack(rfs), np.stack(rhs))
+    uf = g0.evaluate(fl["coef"], X).cpu().numpy()
+    mf = fl["mu_dl"].cpu().numpy()
+    return ([np.linalg.norm(uf[r]) / u_norms[r] for r in range(len(rfs))],
+            [np.linalg.norm(mf[r]) / mu_norms[r] for r in range(len(rfs))])
+
+
 @pytest.mark.parametrize("name", sorted(MIXED))
-def test_mixed_precision_matches_fp64_oracle(name):
-    """Float32 factors and local products, float64 coarse problem, dots and
-    refinement residuals."""
+def test_mixed_precision_sits_at_its_derived_floor(name):
+    """Shipped refinement settings: the refinement converges (its last
+    correction is below refine_tol) and u, mu are within twice the derived
+    float32 floor of the float64 oracle."""
     c = Case(**MIXED[name], tol=1e-12)
     geo, s = c.oracle()
-    ref = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-13, maxit=20000)
+    f = O.local_rhs(geo, I.sinsin_f, I.sinsin_u)
+    ref = s.solve(f, tol=1e-13, maxit=20000)
     X = I.eval_grid(c.w)
     u_ref = O.evaluate(geo, c.W, c.b, ref["c"], X)
-    g = c.gpu(precision=1, inner_tol=1e-9, refine_tol=1e-11, refine_maxit=6).factor()
+    g = c.gpu(precision=1).factor()
     xB = g.boundary_points().cpu().numpy()
     out = g.solve(I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None])
+    st = out["stats"]
+    assert st["converged"] and st["refine_steps"] >= 1 and st["refine_corr"] <= 1e-9
     u = g.evaluate(out["coef"], X)[0].cpu().numpy()
-    assert out["stats"]["refine_steps"] >= 1
-    assert _rel(u, u_ref) < MIXED_TOL, _rel(u, u_ref)
-    if s.nD:
-        assert _rel(out["mu_dl"][0].cpu().numpy(), ref["mu_dl"]) < MIXED_TOL_MU
-    if s.nP:
-        assert _rel(out["mu_pi"][0].cpu().numpy(), ref["mu_pi"]) < MIXED_TOL_MU
+    rf, rh = _coupled_residual(s, f, ref)
+    fu, fm = _float32_floor(c, [rf], [rh], X, [np.linalg.norm(u_ref)], [np.linalg.norm(ref["mu_dl"])])
+    eu, em = _rel(u, u_ref), _rel(out["mu_dl"][0].cpu().numpy(), ref["mu_dl"])
+    print(f"{name}: u {eu:.3e} (floor {fu[0]:.3e})  mu {em:.3e} (floor {fm[0]:.3e})")
+    assert eu <= 2 * fu[0] + 1e-10, (eu, fu[0])
+    assert em <= 2 * fm[0] + 1e-10, (em, fm[0])
 
 
 def test_mixed_refinement_reduces_the_float32_error():
-    """A harder case (M = 200): one refinement step removes most of the
-    float32 error of the first solve."""
+    """A harder case (M = 200, cond(K_c^i) ~ 1e9): refinement removes most of
+    the error of the float32-QR solve; where it stalls above refine_tol the
+    solve says so."""
     c = Case(nx=2, ny=2, M=200, n_int=18, p=18, a=2.0, seed=0, tol=1e-12)
     geo, s = c.oracle()
     ref = s.solve(O.local_rhs(geo, I.sinsin_f, I.sinsin_u), tol=1e-13, maxit=20000)
     X = I.eval_grid(c.w)
     u_ref = O.evaluate(geo, c.W, c.b, ref["c"], X)
     errs = []
-    for maxit in (1, 4):
-        g = c.gpu(precision=1, inner_tol=1e-9, refine_tol=1e-14, refine_maxit=maxit).factor()
+    for maxit in (0, 10):
+        g = c.gpu(precision=1, refine_maxit=maxit).factor()
         xB = g.boundary_points().cpu().numpy()
         out = g.solve(I.sinsin_f(c.xi)[None], I.sinsin_u(xB)[None])
         errs.append(_rel(g.evaluate(out["coef"], X)[0].cpu().numpy(), u_ref))
-    assert errs[1] < 0.1 * errs[0] or errs[1] < MIXED_TOL, errs
+        st = out["stats"]
+        if maxit:
+            assert st["converged"] == (st["refine_corr"] <= 1e-9), st
+    assert errs[1] < 0.1 * errs[0], errs
 
 
 def test_mixed_precision_multi_rhs():
-    """Four right-hand sides through the float32 path at once; the Fourier
-    sources are under-resolved at M = 48 (larger fit residual), so u is held
-    to the mu level of the single-RHS cases."""
+    """Four right-hand sides through the float32-QR path at once, each within
+    twice its own derived floor."""
     c = Case(nx=3, ny=3, M=48, n_int=10, p=12, a=2.0, seed=5, extra=True, tol=1e-12, rhs="fourier", nrhs=4)
-    g = c.gpu(precision=1, inner_tol=1e-9, refine_tol=1e-11, refine_maxit=6).factor()
+    g = c.gpu(precision=1).factor()
     geo, s = c.oracle()
     f_fn, g_fn = I.rhs_functions(c.w)
     xB = g.boundary_points().cpu().numpy()
     out = g.solve(f_fn(c.xi), g_fn(xB))
     X = I.eval_grid(c.w)
     u = g.evaluate(out["coef"], X).cpu().numpy()
+    refs, u_refs, rfs, rhs = [], [], [], []
     for r in range(c.nrhs):
         f = O.local_rhs(geo, lambda x, r=r: f_fn(x)[r], lambda x, r=r: g_fn(x)[r])
         ref = s.solve(f, tol=1e-13, maxit=20000)
-        assert _rel(u[r], O.evaluate(geo, c.W, c.b, ref["c"], X)) < MIXED_TOL_MU
-        assert _rel(out["mu_dl"][r].cpu().numpy(), ref["mu_dl"]) < MIXED_TOL_MU
+        refs.append(ref)
+        u_refs.append(O.evaluate(geo, c.W, c.b, ref["c"], X))
+        rf, rh = _coupled_residual(s, f, ref)
+        rfs.append(rf)
+        rhs.append(rh)
+    fu, fm = _float32_floor(c, rfs, rhs, X, [np.linalg.norm(x) for x in u_refs],
+                            [np.linalg.norm(x["mu_dl"]) for x in refs])
+    for r in range(c.nrhs):
+        assert _rel(u[r], u_refs[r]) <= 2 * fu[r] + 1e-10, (r, _rel(u[r], u_refs[r]), fu[r])
+        assert _rel(out["mu_dl"][r].cpu().numpy(), refs[r]["mu_dl"]) <= 2 * fm[r] + 1e-10
 
 
 def test_cg_launch_autotuner_configurations_all_match_oracle(monkeypatch):
