@@ -229,7 +229,7 @@ template <typename T, int NR, int NM>
 __device__ __forceinline__ void mv_rows_mfma(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
                                              const double* x, double* out) {
   typedef double v4 __attribute__((ext_vector_type(4)));
-  constexpr int kMB = 16;
+  constexpr int kMB = 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int ntile = (R + 15) / 16;
@@ -388,19 +388,18 @@ __device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slo
 // out[c] is the sum over the threads with threadIdx.x % NV == c (NV divides
 // 64).  `red` must hold kWaves * NV values; every thread gets the results.
 template <int NV>
-__device__ __forceinline__ void block_sum_mod(double v, double* out, double* red) {
+__device__ __forceinline__ void block_sum_mod(double v, double* dst, size_t stride, int nrhs, double* red) {
 #pragma unroll
   for (int o = 32; o >= NV; o >>= 1) v += __shfl_xor(v, o, 64);   // lanes keep their residue mod NV
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane < NV) red[wid * NV + lane] = v;
   __syncthreads();
+  if (threadIdx.x < NV && (int)threadIdx.x < nrhs) {   // thread c stores the sum of residue c
+    double t = red[threadIdx.x];
 #pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double t = red[c];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) t += red[w * NV + c];
-    out[c] = t;
+    for (int w = 1; w < kWaves; ++w) t += red[w * NV + threadIdx.x];
+    st_co(dst + threadIdx.x * stride, t);
   }
 }
 
@@ -445,11 +444,12 @@ __device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const do
 }
 
 template <typename T, int NR>
-__global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
+__global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
   extern __shared__ double lds[];
   __shared__ double red[kWaves];
   __shared__ double redv[kWaves * NR];
   __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR], sc_gprev[NR];
+  __shared__ double sc_gt[NR], sc_dt[NR];   // the reduced (r, r) and (u, r) of the pass before
   __shared__ double cor[2][4][NR];          // per corner: (mu, e) or (nu, -D nu)
   __shared__ double cms[2][4][NR];          // per corner: (mu, e) read back in F
   const OpArgs<T>& a = f.a;
@@ -526,27 +526,39 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
   for (;; ++it) {
     if (it > 0) {
       // ---- reduce gamma_{it-1}, delta_{it-1}; convergence test; alpha, beta (identical in every workgroup)
-      double gs[NR], ds[NR], gt[NR], dt[NR];
+      // right-hand sides in groups of kRG, so that few sums are live at once
+      constexpr int kRG = NR < 4 ? NR : 4;
+      for (int g0 = 0; g0 < NR; g0 += kRG) {
+        double gs[kRG], ds[kRG], gt[kRG], dt[kRG];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) gs[r] = ds[r] = 0.0;
-      for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
-        double vg[NR], vd[NR];
+        for (int r = 0; r < kRG; ++r) gs[r] = ds[r] = 0.0;
+        for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
+          double vg[kRG], vd[kRG];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          vg[r] = r < nrhs ? ld_co(&f.part[(size_t)((1 + ((it - 1) & 1)) * nrhs + r) * nb + k]) : 0.0;
-          vd[r] = r < nrhs ? ld_co(&f.part[(size_t)r * nb + k]) : 0.0;
+          for (int r = 0; r < kRG; ++r) {
+            const int rr = g0 + r;
+            vg[r] = rr < nrhs ? ld_co(&f.part[(size_t)((1 + ((it - 1) & 1)) * nrhs + rr) * nb + k]) : 0.0;
+            vd[r] = rr < nrhs ? ld_co(&f.part[(size_t)rr * nb + k]) : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < kRG; ++r) {
+            gs[r] += vg[r];
+            ds[r] += vd[r];
+          }
         }
+        block_sum_vec<double, kRG>(gs, gt, redv);
+        block_sum_vec<double, kRG>(ds, dt, redv);
+        if (threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          gs[r] += vg[r];
-          ds[r] += vd[r];
+          for (int r = 0; r < kRG; ++r) {
+            sc_gt[g0 + r] = gt[r];
+            sc_dt[g0 + r] = dt[r];
+          }
         }
       }
-      block_sum_vec<double, NR>(gs, gt, redv);
-      block_sum_vec<double, NR>(ds, dt, redv);
       if (threadIdx.x == 0) {
         for (int r = 0; r < nrhs; ++r) {
-          const double gam = gt[r], del = dt[r];
+          const double gam = sc_gt[r], del = sc_dt[r];
           if (sc_done[r] == 0.0) {
             sc_rr[r] = gam;
             if (it == 1) sc_bb[r] = f.bref ? f.bref[r] : gam;
@@ -677,13 +689,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       }
       __syncthreads();
     }
-    {
-      double tot[NR];
-      block_sum_mod<NR>(gacc, tot, redv);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)((1 + (it & 1)) * nrhs + r) * nb + blockIdx.x], tot[r]);
-    }
+    block_sum_mod<NR>(gacc, &f.part[(size_t)(1 + (it & 1)) * nrhs * nb + blockIdx.x], nb, nrhs, redv);
     flag_sync(f.flags, nb, ++epoch, f.err);
 
     // ---- B: coarse solve at the corners, lam rows
@@ -950,13 +956,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_fused(FusedArgs<T> f) {
       }
       __syncthreads();
     }
-    {
-      double tot[NR];
-      block_sum_mod<NR>(dacc, tot, redv);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nrhs && threadIdx.x == 0) st_co(&f.part[(size_t)r * nb + blockIdx.x], tot[r]);
-    }
+    block_sum_mod<NR>(dacc, &f.part[blockIdx.x], nb, nrhs, redv);
     flag_sync(f.flags, nb, ++epoch, f.err);
   }
 
