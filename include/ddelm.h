@@ -195,6 +195,28 @@ ddelm_status ddelm_factor(ddelm_ctx ctx);
 ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B, const double* mu0,
                          double* coef, double* mu_pi, double* mu_dl, ddelm_stats* stats);
 
+/* Allocation-free variant of ddelm_solve (without mu0), for callers that
+ * cannot allocate device memory during the call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, results and errors as ddelm_solve; the context must be factored
+ * and the output arrays exist before the call.  The call's workspace (local
+ * right-hand sides, interface vectors, CG state) is 8 bytes times
+ * nrhs * (sum m + 9 sum_nD + 7 sum_nP + 12 n_dl + 10 n_pi + 12298), and in
+ * mixed precision nrhs * (sum m + N M + sum_nD + sum_nP + 3 n_dl + 4 n_pi +
+ * 512) more (sum_nD, sum_nP: local Delta and Pi points over all subdomains),
+ * each buffer rounded up to 256 bytes.  It is taken from a fixed device array
+ * of 64 MiB that the library holds on each GPU it runs on until the process
+ * ends; a larger workspace is refused with DDELM_E_SHAPE before any work,
+ * naming the bytes needed.  The call creates
+ * no events (the phase times of ddelm_get_phase_times are not updated) and
+ * runs no launch tuning: the persistent CG takes the launch shape an earlier
+ * ddelm_solve of the same shape chose in this process, else the size
+ * heuristic.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (the parts that must start at zero are cleared by a
+ * kernel at every call): calls that overlap on one GPU race. */
+ddelm_status ddelm_solve_noalloc(ddelm_ctx ctx, int nrhs, const double* f_I, const double* g_B, double* coef,
+                                 double* mu_pi, double* mu_dl, ddelm_stats* stats);
+
 /* Solve the coupled system of eq. ddelm with a general right-hand side
  * [f; h]: f given on every local row (interior, boundary and interface rows,
  * the interface rows in the K_c^i row space) and h on the flux rows of the

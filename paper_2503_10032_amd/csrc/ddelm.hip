@@ -10,6 +10,7 @@
 #include <cstring>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <mutex>
 #include <string>
@@ -27,6 +28,11 @@
 #include "kernel_entries.hpp"
 
 using namespace ddelm;
+
+// Device array behind ddelm_solve_noalloc: the workspace of an allocation-free
+// solve is carved out of it (one copy per GPU, alive until the process ends).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -410,6 +416,7 @@ struct ddelm_ctx_s {
   bool use_nn = true;     // theta != 0: Kbar factored and P applied
   bool mixed = false;     // float32 Householder QR + float64 refinement of the coupled system
   bool f32cg = false;     // float32 local operators in the CG (mixed, or precision 2)
+  bool noalloc = false;   // inside ddelm_solve_noalloc: no event creation, no tuning runs
   std::string err;
   int device = 0;
   int num_cu = 0;
@@ -476,10 +483,12 @@ struct ddelm_ctx_s {
   hipEvent_t ev[10] = {};
   double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   void mark(int k) {
+    if (noalloc) return;          // phase times are not taken in allocation-free calls
     if (!ev[k]) ev[k] = take_event(device, true);
     HIPCHK(hipEventRecord(ev[k], stream));
   }
   double span(int a, int b) {
+    if (noalloc) return 0.0;
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ev[a], ev[b]));
     return (double)ms;
@@ -725,6 +734,102 @@ void alloc_solve_workspace(ddelm_ctx c, int nrhs) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// Allocation-free solves: the workspace of one call is carved out of a
+// file-scope device array instead of the context's own buffers.  Each GPU
+// holds its copy of the array until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device
+// (taken by ddelm_setup with the device current), never through its name.
+// Every call on a device shares that device's array, so calls that overlap
+// on one GPU race; the buffers that must start at zero are cleared by a
+// kernel at every call.
+struct ScratchAddrs {
+  std::mutex mu;
+  std::vector<void*> ptr;     // per device: address of `scratch` on that device
+};
+ScratchAddrs& scratch_addrs() {
+  static ScratchAddrs* s = new ScratchAddrs();
+  return *s;
+}
+void* scratch_on(int dev) {
+  ScratchAddrs& S = scratch_addrs();
+  std::lock_guard<std::mutex> lk(S.mu);
+  return dev < (int)S.ptr.size() ? S.ptr[dev] : nullptr;
+}
+
+// Binds the solve workspace of nrhs right-hand sides (and the per-subdomain
+// offset tables, through the descriptor arena) to the scratch array of the
+// context's device for the duration of one call; the context's own buffers
+// are restored when it goes out of scope.
+struct ScratchBinding {
+  ddelm_ctx c;
+  struct Saved {
+    DBuf<double>* b;
+    double* p;
+    size_t n, cap;
+  };
+  std::vector<Saved> saved;
+  long long* f_off_p = nullptr;
+  int* f_ld_p = nullptr;
+  int* f_cn_p = nullptr;
+  size_t f_off_n = 0, f_ld_n = 0, f_cn_n = 0, f_off_cap = 0, f_ld_cap = 0, f_cn_cap = 0;
+  int cap_nrhs = 0;
+  ScratchBinding(ddelm_ctx ctx, int nrhs) : c(ctx) {
+    char* base = (char*)scratch_on(c->device);
+    if (!base) c->fail(DDELM_E_STATE, "no scratch address for this device (context not set up on it)");
+    const std::vector<WsEntry> ws = solve_workspace(c, nrhs);
+    size_t off = 0;
+    for (const WsEntry& e : ws) off = ((off + 255) & ~size_t(255)) + e.n * sizeof(double);
+    if (off > kScratchBytes)
+      c->fail(DDELM_E_SHAPE, "allocation-free solve needs " + std::to_string(off) + " bytes of scratch, above the " +
+                                 std::to_string(kScratchBytes) + " available");
+    // the offset tables go through the descriptor arena (which may refuse);
+    // nothing of the context is touched before that has succeeded
+    std::vector<long long> foff(c->N);
+    for (int i = 0; i < c->N; ++i) foff[i] = c->h_offm[i];
+    long long* a_off = c->arena.put(foff, c->stream);
+    int* a_ld = c->arena.put(std::vector<int>(c->N, (int)c->summ), c->stream);
+    int* a_cn = c->arena.put(std::vector<int>(c->N, nrhs), c->stream);
+    cap_nrhs = c->cap_nrhs;
+    f_off_p = c->f_off.p; f_off_n = c->f_off.n; f_off_cap = c->f_off.cap;
+    f_ld_p = c->f_ld.p; f_ld_n = c->f_ld.n; f_ld_cap = c->f_ld.cap;
+    f_cn_p = c->f_cn.p; f_cn_n = c->f_cn.n; f_cn_cap = c->f_cn.cap;
+    c->f_off.p = a_off; c->f_off.n = c->N; c->f_off.cap = 0;
+    c->f_ld.p = a_ld; c->f_ld.n = c->N; c->f_ld.cap = 0;
+    c->f_cn.p = a_cn; c->f_cn.n = c->N; c->f_cn.cap = 0;
+    c->cap_nrhs = nrhs;
+    off = 0;
+    ZeroBatch zb;
+    for (const WsEntry& e : ws) {
+      off = (off + 255) & ~size_t(255);
+      saved.push_back({e.buf, e.buf->p, e.buf->n, e.buf->cap});
+      e.buf->p = (double*)(base + off);
+      e.buf->n = e.n;
+      e.buf->cap = 0;
+      off += e.n * sizeof(double);
+      if (e.zero) zb.add(*e.buf);
+    }
+    try {
+      zb.launch(c->stream);
+    } catch (...) {
+      restore();       // a throwing constructor runs no destructor
+      throw;
+    }
+  }
+  ~ScratchBinding() { restore(); }
+  void restore() {
+    for (const Saved& v : saved) {
+      v.b->p = v.p;
+      v.b->n = v.n;
+      v.b->cap = v.cap;
+    }
+    c->f_off.p = f_off_p; c->f_off.n = f_off_n; c->f_off.cap = f_off_cap;
+    c->f_ld.p = f_ld_p; c->f_ld.n = f_ld_n; c->f_ld.cap = f_ld_cap;
+    c->f_cn.p = f_cn_p; c->f_cn.n = f_cn_n; c->f_cn.cap = f_cn_cap;
+    c->cap_nrhs = cap_nrhs;
+    saved.clear();
+  }
+};
+
 // --------------------------------------------------------------- operator phases after the first stage
 template <typename T>
 void run_phases_after_stage1(ddelm_ctx c, OpArgs<T>& a, int nrhs, const double* hP) {
@@ -916,6 +1021,7 @@ CgConfig cg_choose(ddelm_ctx c, int nrhs) {
     auto it = cg_tuned().find(key);
     if (it != cg_tuned().end()) return it->second;
   }
+  if (c->noalloc) return h;      // no timing runs (they take events) inside an allocation-free call
   std::vector<CgConfig> cand;
   for (int S : {1, 2, 4}) {
     if (es && S != h.S) continue;
@@ -1883,6 +1989,17 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
     if (prob->n_extra < 0 || (prob->n_extra > 0 && !prob->extra_s)) c->fail(DDELM_E_ARG, "bad extra_s");
     HIPCHK(hipGetDevice(&c->device));
     c->blocks->dev = c->device;
+    {
+      // address of this device's copy of `scratch` (once per device)
+      ScratchAddrs& S = scratch_addrs();
+      std::lock_guard<std::mutex> lk(S.mu);
+      if ((int)S.ptr.size() <= c->device) S.ptr.resize(c->device + 1, nullptr);
+      if (!S.ptr[c->device]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        S.ptr[c->device] = ptr;
+      }
+    }
     HIPCHK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     const int N = prob->nx * prob->ny;
     if (prob->nx < 1 || prob->ny < 1 || (long long)prob->nx * prob->ny > (1 << 20))
@@ -2003,7 +2120,7 @@ namespace {
 // Shared body of ddelm_solve (f_I, g_B given) and ddelm_solve_general (f_loc, h given).
 ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, const double* f_loc,
                        const double* h, const double* mu0, double* coef, double* mu_pi, double* mu_dl,
-                       ddelm_stats* stats) {
+                       ddelm_stats* stats, bool noalloc = false) {
   if (!c) return DDELM_E_ARG;
   bool noconv = false;
   ddelm_stats st{};
@@ -2014,10 +2131,19 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
     if (!coef || (!general && (!f_I || (!g_B && c->geo.sum_nB > 0)))) c->fail(DDELM_E_ARG, "null array");
     hipStream_t s = c->stream;
     const int N = c->N;
-    alloc_solve_workspace(c, nrhs);
+    if (!noalloc) alloc_solve_workspace(c, nrhs);
     HIPCHK(hipStreamSynchronize(s));
     c->arena.reset();
     c->upload.reset();
+    struct NoAllocScope {
+      ddelm_ctx c;
+      ~NoAllocScope() { c->noalloc = false; }
+    } na_scope{c};
+    std::unique_ptr<ScratchBinding> bound;
+    if (noalloc) {
+      c->noalloc = true;
+      bound.reset(new ScratchBinding(c, nrhs));
+    }
     c->phase_ms[4] = c->phase_ms[5] = c->phase_ms[6] = 0.0;
     auto acc = [&](const CoreOut& o) {
       st.iters += o.iters;
@@ -2133,6 +2259,15 @@ ddelm_status ddelm_solve(ddelm_ctx c, int nrhs, const double* f_I, const double*
     return DDELM_E_ARG;
   }
   return solve_any(c, nrhs, f_I, g_B, nullptr, nullptr, mu0, coef, mu_pi, mu_dl, stats);
+}
+
+ddelm_status ddelm_solve_noalloc(ddelm_ctx c, int nrhs, const double* f_I, const double* g_B, double* coef,
+                                 double* mu_pi, double* mu_dl, ddelm_stats* stats) {
+  if (!f_I) {
+    if (c) c->err = "f_I is null";
+    return DDELM_E_ARG;
+  }
+  return solve_any(c, nrhs, f_I, g_B, nullptr, nullptr, nullptr, coef, mu_pi, mu_dl, stats, true);
 }
 
 ddelm_status ddelm_solve_general(ddelm_ctx c, int nrhs, const double* f_loc, const double* h, double* coef,

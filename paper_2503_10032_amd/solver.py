@@ -182,6 +182,31 @@ class DDELMSolver:
                                                     _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)), "solve")
         return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=self._stats(st, code))
 
+    def solve_noalloc(self, f_I, g_B):
+        """As solve, through ddelm_solve_noalloc: the call allocates no device
+        memory (its workspace lives in the library's fixed scratch array; the
+        output tensors are allocated here, before the call)."""
+        dev = self.device
+        f_I = torch.as_tensor(f_I, dtype=torch.float64, device=dev).contiguous()
+        g_B = torch.as_tensor(g_B, dtype=torch.float64, device=dev).contiguous()
+        if f_I.ndim == 2:
+            f_I = f_I[None]
+        if g_B.ndim == 1:
+            g_B = g_B[None]
+        nrhs = f_I.shape[0]
+        assert f_I.shape == (nrhs, self.N, self.sizes.n_int), f_I.shape
+        assert g_B.shape == (nrhs, self.sizes.sum_nB), g_B.shape
+        coef = torch.empty((nrhs, self.N, self.M), dtype=torch.float64, device=dev)
+        mu_pi = torch.zeros((nrhs, self.n_pi), dtype=torch.float64, device=dev)
+        mu_dl = torch.zeros((nrhs, self.n_dl), dtype=torch.float64, device=dev)
+        st = L.Stats()
+        with torch.cuda.device(dev):
+            code = self._check(self.lib.ddelm_solve_noalloc(self.ctx, nrhs, f_I.data_ptr(), g_B.data_ptr(),
+                                                            coef.data_ptr(), _ptr(mu_pi) if self.n_pi else None,
+                                                            _ptr(mu_dl) if self.n_dl else None, ctypes.byref(st)),
+                               "solve_noalloc")
+        return dict(coef=coef, mu_pi=mu_pi, mu_dl=mu_dl, stats=self._stats(st, code))
+
     def solve_general(self, f_loc, h=None, want_mu: bool = True):
         """General right-hand side: f_loc (nrhs, sum m) on every local row, h
         (nrhs, n_pi + n_dl) on the flux rows (None = 0)."""
