@@ -47,7 +47,10 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "f32cg": 2}
 # only for the kernel sources they were taken with (sha256 of the three files
 # below) and for the workload named; otherwise the bench reports null.
 CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
-CG_TRAFFIC = {}
+CG_TRAFFIC = {
+    ("large", "fp64"): dict(fetch_kib=195639986.8125, write_kib=81298253.5, fetch_scale=0.5, write_scale=1.0,
+                            sha256="adb3a2bfc8e8fc7e5698f908b5ee5105f4eba206a55f01c352e2a4f8fea99db7"),
+}
 
 
 def cg_bytes_per_iteration(counts, n_pi, nrhs, elem=8):
