@@ -17,6 +17,9 @@ with Coarse Space for Domain Decomposition of Extreme Learning Machines"):
   * Neumann-Neumann map P = Abar Kbar^+ Bbar and the theta-mixed normal
     equation (eq. nn-mixed), solved by CG on mu_Delta           (sec. 3.1)
   * change of variables T^i (fig. change) and mean-flux rows A_m  (sec. 3.2)
+  * optionally the variable-coefficient operator -div(rho grad u)
+    (sec. 4.3): interior rows rho (-Laplace phi) - grad rho . grad phi,
+    flux rows the conormal derivative rho dphi/dn
 
 Readings where the paper is silent (all listed in the design notes):
   - hidden weights act on local coordinates xi = (x - centre)/(h/2);
@@ -28,7 +31,10 @@ Readings where the paper is silent (all listed in the design notes):
   - an A_m corner row is the sum, over this subdomain's interface edges
     meeting the corner, of the edge-mean flux excluding the opposite end;
   - Kbar and Abar use point values (no T, no A_m), Abar is summed;
-  - CG stops on the recurrence residual ||r_k|| <= tol ||b||, from mu=0.
+  - CG stops on the recurrence residual ||r_k|| <= tol ||b||, from mu=0;
+  - with a coefficient rho, the flux continuity and Neumann rows use the
+    conormal derivative rho dphi/dn (rho is continuous, so this is the same
+    interface condition as dphi/dn, with rows scaled by rho).
 
 Precision: float64 throughout.  Library primitives used as steps: numpy QR
 (LAPACK Householder), scipy Cholesky and triangular solves, pinv/lstsq in
@@ -300,12 +306,23 @@ def tanh_features(W, b, half, center, x):
     return t, grad, -lap
 
 
-def local_matrices(geo: Geometry2D, i: int, W: np.ndarray, b: np.ndarray):
-    """K^i (or K_c^i), A^i (or A_m^i) rows at local Gamma, Kbar^i and Abar^i."""
+def local_matrices(geo: Geometry2D, i: int, W: np.ndarray, b: np.ndarray, rho=None):
+    """K^i (or K_c^i), A^i (or A_m^i) rows at local Gamma, Kbar^i and Abar^i.
+
+    rho: None for the Poisson operator -Laplace u, else a callable
+    x (n, 2) -> (rho(x) (n,), grad rho(x) (n, 2)) for -div(rho grad u)
+    (sec. 4.3, variable-coefficient Poisson).  Then an interior row is
+    -div(rho grad phi) = rho (-Laplace phi) - grad rho . grad phi, and every
+    flux row (the A / A_m rows and the Delta rows of Kbar) takes the conormal
+    derivative rho dphi/dn at each of its points; value rows do not change.
+    """
     sb = geo.subs[i]
-    phi_I, _, Lphi_I = tanh_features(W, b, sb.half, sb.center, sb.x_I)
+    phi_I, grad_I, Lphi_I = tanh_features(W, b, sb.half, sb.center, sb.x_I)
     phi_B, _, _ = tanh_features(W, b, sb.half, sb.center, sb.x_B)
     phi_G, grad_G, _ = tanh_features(W, b, sb.half, sb.center, sb.x_G)
+    if rho is not None:
+        r_I, dr_I = rho(sb.x_I)
+        Lphi_I = r_I[:, None] * Lphi_I - np.einsum("nmk,nk->nm", grad_I, dr_I)
     # K_c: Gamma rows are (T^i)^{-1} C phi(x_Gamma)  (sec. 3.2)
     CG = np.linalg.inv(sb.T) @ phi_G
     K = np.vstack([Lphi_I, phi_B, CG])
@@ -314,10 +331,13 @@ def local_matrices(geo: Geometry2D, i: int, W: np.ndarray, b: np.ndarray):
     for r, terms in enumerate(sb.flux_terms):
         for wgt, xy, n in terms:
             _, g, _ = tanh_features(W, b, sb.half, sb.center, xy[None, :])
-            A[r] += wgt * (g[0] @ n)
+            scale = 1.0 if rho is None else rho(xy[None, :])[0][0]
+            A[r] += wgt * scale * (g[0] @ n)
     # Kbar: Dirichlet at Pi, point flux at Delta (sec. 3.1); Abar: trace at Delta
     nP = sb.n_P
     flux_D = np.einsum("nmk,nk->nm", grad_G[nP:], sb.dl_normal)
+    if rho is not None:
+        flux_D = rho(sb.x_G[nP:])[0][:, None] * flux_D
     Kbar = np.vstack([Lphi_I, phi_B, phi_G[:nP], flux_D])
     Abar = phi_G[nP:]
     return K, A, Kbar, Abar
@@ -345,13 +365,13 @@ class DDELMNN:
     interface vectors are global arrays over Pi or Delta.
     """
 
-    def __init__(self, geo: Geometry2D, W, b, theta=0.999):
+    def __init__(self, geo: Geometry2D, W, b, theta=0.999, rho=None):
         self.geo = geo
         self.theta = float(theta)
         self.N = len(geo.subs)
         self.K, self.A, self.Kb, self.Ab = [], [], [], []
         for i in range(self.N):
-            K, A, Kb, Ab = local_matrices(geo, i, W[i], b[i])
+            K, A, Kb, Ab = local_matrices(geo, i, W[i], b[i], rho=rho)
             self.K.append(K); self.A.append(A); self.Kb.append(Kb); self.Ab.append(Ab)
         self.ls = [LocalLS(K) for K in self.K]
         self.lsb = [LocalLS(Kb) for Kb in self.Kb] if self.theta != 0.0 else None

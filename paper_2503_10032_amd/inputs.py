@@ -37,8 +37,11 @@ class Workload:
     extra_boundary: bool = False   # boundary subdomains get edge midpoints as extra rows
     lo: tuple = (0.0, 0.0)
     hi: tuple = (1.0, 1.0)
-    rhs: str = "sinsin"     # "sinsin" (manufactured) or "fourier"
+    rhs: str = "sinsin"     # "sinsin" (manufactured), "fourier" or "one" (f = 1, g = 0)
     rhs_seed: int = 100
+    rho: str = "one"        # coefficient of -div(rho grad u): "one" or "grf" (tanh(GRF) + 1.1)
+    rho_alpha: float = 32.0
+    rho_seed: int = 7
 
     @property
     def N(self) -> int:
@@ -53,6 +56,10 @@ def workload(name: str) -> Workload:
     large    32x32, M=400, U(-2,2), 40x40 interior, 40 per edge, uneven
              boundary subdomains, 16 random Fourier right-hand sides
     adjoint  16x16, M=300, U(-2,2), 32x32 interior, 32 per edge
+    varcoef  16x16, M=256, U(-2,2), 20x20 interior, 20 per edge: the
+             variable-coefficient problem -div(rho grad u) = 1, u = 0 on the
+             boundary, rho = tanh(GRF) + 1.1 with alpha = 32 (65,536 neurons
+             in total and a 320 x 320 training grid, as in the paper's table)
     """
     if name == "small":
         return Workload("small", 2, 2, 64, 2.0, 0, 16, 16, tol=1e-10)
@@ -63,6 +70,8 @@ def workload(name: str) -> Workload:
                         extra_boundary=True, rhs="fourier", rhs_seed=100)
     if name == "adjoint":
         return Workload("adjoint", 16, 16, 300, 2.0, 4, 32, 32, tol=1e-10)
+    if name == "varcoef":
+        return Workload("varcoef", 16, 16, 256, 2.0, 3, 20, 20, tol=1e-8, rhs="one", rho="grf")
     raise KeyError(name)
 
 
@@ -262,6 +271,8 @@ def eval_grid(w: Workload) -> np.ndarray:
 
 def rhs_functions(w: Workload):
     """(f, g) callables returning arrays of shape (nrhs, npts)."""
+    if w.rhs == "one":
+        return (lambda x: np.ones((w.nrhs,) + x.shape[:-1])), (lambda x: np.zeros((w.nrhs,) + x.shape[:-1]))
     if w.rhs == "sinsin":
         f1 = lambda x: sinsin_f(x)[None]
         g1 = lambda x: sinsin_u(x)[None]
@@ -270,3 +281,66 @@ def rhs_functions(w: Workload):
         fr = fourier_rhs(w.nrhs, w.rhs_seed)
         return (lambda x: fr(x)), (lambda x: np.zeros((w.nrhs,) + x.shape[:-1]))
     raise KeyError(w.rhs)
+
+
+# ---------------------------------------------------------------- coefficients
+
+@dataclasses.dataclass
+class GRF:
+    """Approximate Gaussian random field grf(x) = sum_i a_i sin(w_i . x + b_i)
+    with n terms, a_i ~ N(0, alpha^4/n), w_i ~ N(0, alpha^2 I), b_i ~ U(0, 2 pi)
+    (eq. grf, n = 256); a larger alpha gives a more oscillatory field."""
+
+    a: np.ndarray           # (n,)
+    w: np.ndarray           # (n, 2)
+    b: np.ndarray           # (n,)
+
+    # Elementwise products and a sum along the last axis (no BLAS product),
+    # so a point's value does not depend on which batch it is evaluated in.
+    def _phase(self, x: np.ndarray) -> np.ndarray:
+        return x[..., 0, None] * self.w[:, 0] + x[..., 1, None] * self.w[:, 1] + self.b
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        return (np.sin(self._phase(x)) * self.a).sum(axis=-1)
+
+    def grad(self, x: np.ndarray) -> np.ndarray:
+        c = np.cos(self._phase(x)) * self.a
+        return np.stack([(c * self.w[:, 0]).sum(axis=-1), (c * self.w[:, 1]).sum(axis=-1)], axis=-1)
+
+
+def grf(alpha: float, seed: int, n: int = 256) -> GRF:
+    """Draws a, then w, then b from one generator seeded with `seed`."""
+    rng = np.random.default_rng(seed)
+    a = rng.normal(0.0, alpha * alpha / math.sqrt(n), size=n)
+    w = rng.normal(0.0, alpha, size=(n, 2))
+    b = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    return GRF(a=a, w=w, b=b)
+
+
+@dataclasses.dataclass
+class TanhGRFCoefficient:
+    """rho(x) = tanh(grf(x)) + shift of the variable-coefficient Poisson
+    problem (sec. 4.3, shift 1.1), so 0.1 < rho < 2.1 for shift 1.1.
+
+    Called on points x (..., 2) it returns (rho(x), grad rho(x)) with shapes
+    (...) and (..., 2)."""
+
+    field: GRF
+    shift: float = 1.1
+
+    def __call__(self, x: np.ndarray):
+        x = np.asarray(x, dtype=np.float64)
+        flat = x.reshape(-1, 2)
+        t = np.tanh(self.field(flat))
+        g = (1.0 - t * t)[:, None] * self.field.grad(flat)
+        return (t + self.shift).reshape(x.shape[:-1]), g.reshape(x.shape)
+
+
+def coefficient(w: Workload):
+    """The workload's coefficient as a callable x -> (rho, grad rho), or None
+    for rho = 1."""
+    if w.rho == "one":
+        return None
+    if w.rho == "grf":
+        return TanhGRFCoefficient(grf(w.rho_alpha, w.rho_seed))
+    raise KeyError(w.rho)
