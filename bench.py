@@ -120,7 +120,7 @@ def cpu_baseline(w, iters):
     def measure():
         t0 = time.perf_counter()
         geo = O.Geometry2D(3, 3, I.edge_params(s3.p), I.extra_boundary_params(s3), xi)
-        s = O.DDELMNN(geo, W, b, theta=s3.theta)
+        s = O.DDELMNN(geo, W, b, theta=s3.theta, rho=I.coefficient(w))
         t1 = time.perf_counter()
         e = np.zeros(s.nP)
         e[0] = 1.0
@@ -147,11 +147,26 @@ def cpu_baseline(w, iters):
     return {
         "value": est, "unit": "s", "cores": int(blas_threads()), "kind": "oracle",
         "value_1thread": one,
-        "sample": (f"oracle on a 3x3 partition with the large workload's local shapes: setup without the "
+        "sample": (f"oracle on a 3x3 partition with the {w.name} workload's local shapes: setup without the "
                    f"coarse columns {t_set:.2f}s, one S_Pi column sweep {t_col:.3f}s, one S_theta application "
                    f"{t_op:.3f}s; scaled as N*t_setup/9 + n_Pi*N*t_col/9 + nrhs*I*N*t_op/9 with N={N}, "
                    f"n_Pi={nP}, nrhs={w.nrhs}, I={iters}"),
     }
+
+
+def coefficient_arrays(rho_fn, solver, xi, dev):
+    """Device arrays of ddelm_set_coefficient for a coefficient callable (None
+    for rho = 1), evaluated once at the interior and interface points so that
+    they are resident before any timed step."""
+    if rho_fn is None:
+        return None
+    import torch
+    r, g = rho_fn(xi.reshape(-1, 2))
+    rho_I = np.concatenate([r.reshape(-1, 1), g.reshape(-1, 2)], axis=1).reshape(xi.shape[0], xi.shape[1], 3)
+    xp, xd = (t.cpu().numpy() for t in solver.interface_points())
+    rp = rho_fn(xp)[0] if len(xp) else np.zeros(0)
+    rd = rho_fn(xd)[0]
+    return tuple(torch.as_tensor(np.ascontiguousarray(a), device=dev) for a in (rho_I, rp, rd))
 
 
 ABLATION = [   # (label, coarse, theta): the paper's comparison columns and the cells of table chov
@@ -180,12 +195,28 @@ def ablation(args):
     if w.rhs == "sinsin":
         u_exact = torch.as_tensor(I.sinsin_u(X), device=dev)
     rows = []
+    rho_fn = I.coefficient(w)
+    # inputs resident on the device before any timed step (the boundary
+    # points do not depend on the variant)
+    Wd, bd, xid = (torch.as_tensor(a, device=dev) for a in (W, b, xi))
+    fI = torch.as_tensor(f_fn(xi), device=dev)
+    probe = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra)
+    gB = torch.as_tensor(g_fn(probe.boundary_points().cpu().numpy()), device=dev)
+    probe.close()
     for label, coarse, theta in ABLATION:
+        rho_dev = None
+        if rho_fn is not None:
+            probe = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=theta, coarse=coarse)
+            rho_dev = coefficient_arrays(rho_fn, probe, xi, dev)
+            probe.close()
+
         def step():
-            s = DDELMSolver(w.nx, w.ny, w.M, W, b, xi, s_edge, s_extra, theta=theta, coarse=coarse, tol=1e-8,
-                            max_nrhs=w.nrhs, maxit=50000).factor()
-            gB = g_fn(s.boundary_points().cpu().numpy())
-            out = s.solve(f_fn(xi), gB, want_mu=False)
+            s = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=theta, coarse=coarse, tol=1e-8,
+                            max_nrhs=w.nrhs, maxit=50000)
+            if rho_dev is not None:
+                s.set_coefficient(*rho_dev)
+            s.factor()
+            out = s.solve(fI, gB, want_mu=False)
             u = s.evaluate(out["coef"], Xd)
             torch.cuda.synchronize()
             s.close()
@@ -219,7 +250,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large")
+    ap.add_argument("--workload", default=None, help="large (default), medium, small, adjoint; medium for --ablation")
     ap.add_argument("--cg-mode", type=int, default=0)
     ap.add_argument("--precision", default="all", help="fp64, mixed, f32cg or all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -247,8 +278,7 @@ def main():
               f"design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
     if args.ablation:
-        if args.workload == "large":
-            args.workload = "medium"
+        args.workload = args.workload or "medium"
         ablation(args)
         return
 
@@ -256,7 +286,7 @@ def main():
     from paper_2503_10032_amd import DDELMSolver, inputs as I
     from paper_2503_10032_amd import _lib
 
-    w = I.workload(args.workload)
+    w = I.workload(args.workload or "large")
     W, b = I.hidden_params(w.N, w.M, 2, w.a, w.seed)
     xi = I.interior_points(w)
     s_edge, s_extra = I.edge_params(w.p), I.extra_boundary_params(w)
@@ -270,14 +300,20 @@ def main():
     modes = list(PRECISIONS) if args.precision == "all" else args.precision.split(",")
     tol = 1e-8
 
+    rho_dev = None
+
     def make(prec):
-        return DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=w.theta, tol=tol,
-                           max_nrhs=w.nrhs, cg_mode=args.cg_mode, precision=PRECISIONS[prec])
+        s = DDELMSolver(w.nx, w.ny, w.M, Wd, bd, xid, s_edge, s_extra, theta=w.theta, tol=tol,
+                        max_nrhs=w.nrhs, cg_mode=args.cg_mode, precision=PRECISIONS[prec])
+        if rho_dev is not None:
+            s.set_coefficient(*rho_dev)
+        return s
 
     probe = make("fp64")
     gB = torch.as_tensor(g_fn(probe.boundary_points().cpu().numpy()), device=dev)
     counts = probe.counts()
     n_pi = probe.n_pi
+    rho_dev = coefficient_arrays(I.coefficient(w), probe, xi, dev)
     probe.close()
     if not args.quiet:
         print(f"bench: workload {w.name} ({w.nx}x{w.ny}, M={w.M}, nrhs={w.nrhs}) precisions {modes}",
@@ -383,7 +419,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: 2-D Poisson {w.nx}x{w.ny} subdomains, M={w.M}, "
+        "config": {"workload": f"{w.name}: 2-D {'Poisson' if w.rho == 'one' else 'variable-coefficient Poisson (rho = tanh(GRF) + 1.1, alpha ' + format(w.rho_alpha, 'g') + ')'} {w.nx}x{w.ny} subdomains, M={w.M}, "
                                f"{w.n_int}x{w.n_int} interior + {w.p} per edge"
                                f"{' + extra boundary rows' if w.extra_boundary else ''}, nrhs={w.nrhs} "
                                f"({w.rhs} sources), theta={w.theta}, rel res {tol:g}",

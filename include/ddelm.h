@@ -168,6 +168,25 @@ void ddelm_default_options(ddelm_options* opt);
 ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob,
                          const ddelm_options* opt, void* stream);
 
+/* Variable coefficient: the operator becomes -div(rho grad u) = f with u = g
+ * on the boundary (sec. 4.3, variable-coefficient Poisson equation, where
+ * rho = tanh(grf) + 1.1).  Interior rows of K_c^i and Kbar^i become
+ * rho (-Laplace phi) - grad rho . grad phi; every flux row (A / A_m and the
+ * Delta rows of Kbar^i) becomes the conormal derivative rho dphi/dn at each of
+ * its points; value and continuity rows are unchanged.
+ *   rho_I  device [N][n_int][3]: rho, d rho/dx, d rho/dy at the interior points
+ *          (the x_int order of ddelm_problem)
+ *   rho_pi device [n_pi]: rho at the Pi points (ddelm_get_interface_points
+ *          order); may be NULL when n_pi == 0
+ *   rho_dl device [n_dl]: rho at the Delta points
+ * All three NULL: back to rho = 1.  The arrays are copied (borrowed for the
+ * call).  Call after ddelm_setup; the context then needs ddelm_factor again.
+ * Synchronises the context's stream.  Errors: DDELM_E_STATE (setup did not
+ * complete), DDELM_E_ARG (a required array NULL, rho <= 0 anywhere),
+ * DDELM_E_NONFINITE, DDELM_E_HIP, DDELM_E_NOMEM. */
+ddelm_status ddelm_set_coefficient(ddelm_ctx ctx, const double* rho_I, const double* rho_pi,
+                                   const double* rho_dl);
+
 /* Assemble local matrices, factor them (Householder QR), build the local
  * interface operators and the coarse problem.  Errors: DDELM_E_HIP,
  * DDELM_E_CHOLESKY. */

@@ -64,6 +64,7 @@ SIGNATURES = {
     "ddelm_setup": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Problem),
                                    ctypes.POINTER(Options), ctypes.c_void_p]),
     "ddelm_factor": (ctypes.c_int, [ctypes.c_void_p]),
+    "ddelm_set_coefficient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ddelm_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(Stats)]),

@@ -423,6 +423,9 @@ struct ddelm_ctx_s {
 
   // problem copies
   DBuf<double> W, b, geom, x_int;
+  // coefficient of -div(rho grad u) (ddelm_set_coefficient); empty: rho = 1
+  DBuf<double> rho_int, rho_iface;
+  bool has_rho = false;
   RowSetDev rsK, rsA, rsKb, rsAb;
   // sizes per subdomain
   std::vector<int> h_m, h_nG, h_nD, h_nP, h_nB;
@@ -628,6 +631,8 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, c
   a.row0 = rs.row0.p; a.ptr = rs.ptr.p; a.terms = rs.terms.p;
   a.W = c->W.p; a.bias = c->b.p; a.geom = c->geom.p;
   a.off = c->arena.put(off, c->stream); a.ld = c->arena.put(ld, c->stream); a.M = c->M; a.sub0 = sub0;
+  a.rho_int = c->has_rho ? c->rho_int.p : nullptr;
+  a.rho_iface = c->has_rho ? c->rho_iface.p : nullptr;
   dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
   k_features<T><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
@@ -2098,6 +2103,40 @@ ddelm_status ddelm_setup(ddelm_ctx* out, const ddelm_problem* prob, const ddelm_
   }
   *out = c;
   return DDELM_OK;
+}
+
+ddelm_status ddelm_set_coefficient(ddelm_ctx c, const double* rho_I, const double* rho_pi, const double* rho_dl) {
+  if (!c) return DDELM_E_ARG;
+  return run_guarded(c, [&]() {
+    if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
+    hipStream_t s = c->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    c->factored = false;
+    if (!rho_I && !rho_pi && !rho_dl) {      // back to rho = 1
+      c->has_rho = false;
+      return;
+    }
+    if (!rho_I || !rho_dl || (c->nP > 0 && !rho_pi)) c->fail(DDELM_E_ARG, "null coefficient array");
+    const size_t nI = (size_t)c->N * c->n_int * 3, nG = (size_t)c->nP + c->nD;
+    // validated on the host: a set-up time copy of a few values per point
+    std::vector<double> hI(nI), hG(nG);
+    HIPCHK(hipMemcpy(hI.data(), rho_I, nI * sizeof(double), hipMemcpyDeviceToHost));
+    if (c->nP > 0) HIPCHK(hipMemcpy(hG.data(), rho_pi, c->nP * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hG.data() + c->nP, rho_dl, c->nD * sizeof(double), hipMemcpyDeviceToHost));
+    for (double v : hI)
+      if (!std::isfinite(v)) c->fail(DDELM_E_NONFINITE, "non-finite coefficient value");
+    for (double v : hG)
+      if (!std::isfinite(v)) c->fail(DDELM_E_NONFINITE, "non-finite coefficient value");
+    for (size_t k = 0; k < nI; k += 3)
+      if (!(hI[k] > 0.0)) c->fail(DDELM_E_ARG, "coefficient rho must be positive at the interior points");
+    for (double v : hG)
+      if (!(v > 0.0)) c->fail(DDELM_E_ARG, "coefficient rho must be positive at the interface points");
+    c->has_rho = false;
+    c->rho_int.upload(hI, s);
+    c->rho_iface.upload(hG, s);
+    HIPCHK(hipStreamSynchronize(s));
+    c->has_rho = true;
+  });
 }
 
 ddelm_status ddelm_factor(ddelm_ctx c) {

@@ -211,13 +211,15 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
             for (int k = k0; k <= k1; ++k) {
               double xy[2];
               side_point(ix, iy, sd, s[k], xy);
-              ft.push_back(Term{xy[0], xy[1], kNormal[sd][0], kNormal[sd][1], 1.0 / (p - 1), OP_FLUX, 0});
+              // the corner itself (k = 0 or p - 1) is a Pi point, the rest Delta points of the edge
+              const int gi = (k == 0 || k == p - 1) ? g.g : n_pi + sds[sd].edge * (p - 2) + (k - 1);
+              ft.push_back(Term{xy[0], xy[1], kNormal[sd][0], kNormal[sd][1], 1.0 / (p - 1), OP_FLUX, gi});
             }
           }
         } else {
           double n[2];
           vertex_normal(g.vjx, g.vjy, n);
-          ft.push_back(Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, 0});
+          ft.push_back(Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, g.g});
         }
         rowsA.add_row(ft);
       }
@@ -234,8 +236,8 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
           if (is_pi(d.v1x, d.v1y)) ct.push_back(Term{vx(d.v1x), vy(d.v1y), 0, 0, -sk, OP_VALUE, 0});
         }
         rowsK.add_row(ct);
-        rowsA.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, 0}});
-        rowsKb.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, 0}});
+        rowsA.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
+        rowsKb.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
         rowsAb.add_row({Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0}});
       }
     }

@@ -20,7 +20,9 @@ struct Term {          // one contribution  wgt * op(phi)(x)  to a matrix row
   double nx, ny;       // normal (used by OP_FLUX)
   double wgt;
   int op;
-  int pad;
+  int iface;           // OP_FLUX: global interface index of the point (the #Pi
+                       // points first, then #Delta), where a coefficient
+                       // rho of the flux rho dphi/dn is looked up; else 0
 };
 
 struct SubInfo {

@@ -219,41 +219,53 @@ __device__ __forceinline__ void slice_rows(int n, int S, int q, int& r0, int& r1
 // are split into nsplit groups over k; partial sums meet in `part` (LDS,
 // kBlock * NM * NR doubles).
 // Many right-hand sides: the same products as a small GEMM on f64 MFMA,
-// Y (R x NR) = A (R x K) X (K x NR) in 16-row tiles (one per wave at a time,
-// NR <= 16 right-hand sides padded to the 16 MFMA columns), the matrix
-// streamed from memory as the A operand (lane l: row l & 15, column l >> 4
-// of each 16 x 4 step, so 16 consecutive rows of a column per load) and X
-// read from LDS as the B operand.  kMB steps (4 columns each) of loads are
-// issued before their products.  Float32 matrices are widened to float64.
-template <typename T, int NR, int NM>
-__device__ __forceinline__ void mv_rows_mfma(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
-                                             const double* x, double* out) {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  constexpr int kMB = 8;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Y (R x NR) = A (R x K) X (K x NR) in 16-row tiles (tile w, w + 4, ... for
+// wave w; NR <= 16 right-hand sides padded to the 16 MFMA columns), the
+// matrix streamed from memory as the A operand (lane l: row l & 15, column
+// l >> 4 of each 16 x 4 step, so 16 consecutive rows of a column per load)
+// and X read from LDS as the B operand.  A wave's work is one sequence of
+// batches of kMB steps (4 columns each) over its tiles; the loads of batch
+// s + 1 are issued before the products of batch s, so a wave always has one
+// batch in flight while it computes (the matrix stream is latency bound: a
+// batch costs one memory round trip).  Float32 matrices are widened to
+// float64.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NM, int kMB>
+__device__ __forceinline__ void mfma_load_batch(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
+                                                int tile, int kb, double (&va)[kMB], double (&vb)[kMB]) {
+  // Branch-free: every lane loads from a clamped (in-range, so finite)
+  // element; nothing is masked here.  Rows past R only feed output rows that
+  // are never stored, and columns past K meet a zero x in the product, so the
+  // loads of a batch stay one unconditional group and the wait before the
+  // products can count them exactly.
+  const int lane = threadIdx.x & 63;
+  const int rowc = min(tile * 16 + (lane & 15), R - 1);
+  const T* a0 = A0 + (long long)c0 * lda + r0 + rowc;
+  const T* a1 = NM > 1 ? A1 + (long long)c0 * lda + r0 + rowc : nullptr;
+#pragma unroll
+  for (int u = 0; u < kMB; ++u) {
+    const long long kc = min(kb * 4 * kMB + 4 * u + (lane >> 4), K - 1);
+    va[u] = (double)a0[kc * lda];
+    if (NM > 1) vb[u] = (double)a1[kc * lda];
+  }
+}
+
+template <int NR, int NM, int kMB>
+__device__ __forceinline__ void mfma_batch(int R, int K, int tile, int kb, int nkb, const double (&va)[kMB],
+                                           const double (&vb)[kMB], const double* x, double* out, f64x4& acc0,
+                                           f64x4& acc1) {
+  const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const int ntile = (R + 15) / 16;
-  for (int tile = wv; tile < ntile; tile += kWaves) {
-    v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    const int row = tile * 16 + lr;
-    const bool rok = row < R;
-    const T* a0 = A0 + (long long)c0 * lda + r0 + row;
-    const T* a1 = NM > 1 ? A1 + (long long)c0 * lda + r0 + row : nullptr;
-    for (int k0 = 0; k0 < K; k0 += 4 * kMB) {
-      double va[kMB], vb[kMB], xb[kMB];
 #pragma unroll
-      for (int u = 0; u < kMB; ++u) {
-        const int kk = k0 + 4 * u + lk;
-        va[u] = (rok && kk < K) ? (double)a0[(long long)kk * lda] : 0.0;
-        vb[u] = (NM > 1 && rok && kk < K) ? (double)a1[(long long)kk * lda] : 0.0;
-        xb[u] = (kk < K && lr < NR) ? x[kk * NR + lr] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kMB; ++u) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], xb[u], acc0, 0, 0, 0);
-        if (NM > 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[u], xb[u], acc1, 0, 0, 0);
-      }
-    }
+  for (int u = 0; u < kMB; ++u) {
+    const int kk = kb * 4 * kMB + 4 * u + lk;
+    const double xv = x[min(kk, K - 1) * NR + min(lr, NR - 1)];
+    const double xb = (kk < K && lr < NR) ? xv : 0.0;
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], xb, acc0, 0, 0, 0);
+    if (NM > 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vb[u], xb, acc1, 0, 0, 0);
+  }
+  if (kb == nkb - 1) {
     // accumulator element v of lane l holds row (l >> 4) + 4 v, right-hand side l & 15
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -262,6 +274,35 @@ __device__ __forceinline__ void mv_rows_mfma(const T* A0, const T* A1, int lda, 
         out[orow * NR + lr] = acc0[v];
         if (NM > 1) out[(R + orow) * NR + lr] = acc1[v];
       }
+      acc0[v] = 0.0;
+      acc1[v] = 0.0;
+    }
+  }
+}
+
+template <typename T, int NR, int NM>
+__device__ __forceinline__ void mv_rows_mfma(const T* A0, const T* A1, int lda, int r0, int R, int c0, int K,
+                                             const double* x, double* out) {
+  constexpr int kMB = 8;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int ntile = (R + 15) / 16;
+  const int nkb = (K + 4 * kMB - 1) / (4 * kMB);                // batches per tile
+  const int mytiles = wv < ntile ? (ntile - wv + kWaves - 1) / kWaves : 0;
+  const int nsteps = mytiles * nkb;
+  if (nsteps > 0) {
+    f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    double pa[kMB], pb[kMB], qa[kMB], qb[kMB];
+    // batch s: tile wv + (s / nkb) * kWaves, column batch s % nkb.  Two
+    // register sets alternate (p for even s, q for odd s).  Every load and
+    // product is unconditional, so the waits before the products count the
+    // loads exactly: batches past the wave's last tile (an odd count's last
+    // q batch, the final prefetch) load clamped elements and store nothing.
+    mfma_load_batch<T, NM, kMB>(A0, A1, lda, r0, R, c0, K, wv, 0, pa, pb);
+    for (int s = 0; s < nsteps; s += 2) {
+      mfma_load_batch<T, NM, kMB>(A0, A1, lda, r0, R, c0, K, wv + ((s + 1) / nkb) * kWaves, (s + 1) % nkb, qa, qb);
+      mfma_batch<NR, NM, kMB>(R, K, wv + (s / nkb) * kWaves, s % nkb, nkb, pa, pb, x, out, acc0, acc1);
+      mfma_load_batch<T, NM, kMB>(A0, A1, lda, r0, R, c0, K, wv + ((s + 2) / nkb) * kWaves, (s + 2) % nkb, pa, pb);
+      mfma_batch<NR, NM, kMB>(R, K, wv + ((s + 1) / nkb) * kWaves, (s + 1) % nkb, nkb, qa, qb, x, out, acc0, acc1);
     }
   }
   __syncthreads();
@@ -339,20 +380,36 @@ __device__ __forceinline__ void mv_rows(const T* A0, const T* A1, int lda, int r
   }
 }
 
+// Element loops over (point k, right-hand side r) of a unit run RHS-major:
+// thread t takes r = t / kTPR and the points k = t % kTPR + kTPR j, so that
+// the lanes of a wave touch consecutive points of one right-hand side.  The
+// interface vectors are stored [r][point] and the points of a unit (and their
+// owner slots) run along its edges in consecutive global order, so a wave's
+// coherent loads and stores fall on a few cache lines instead of one line
+// per right-hand side.
+template <int NR>
+struct RhsMajor {
+  static constexpr int kTPR = kBlock / NR;       // threads per right-hand side
+  int r, k0;
+  __device__ __forceinline__ RhsMajor() : r(threadIdx.x / kTPR), k0(threadIdx.x % kTPR) {}
+};
+
 // sum over owners of a local Delta vector, for all Delta points of subdomain i
-// into xs[k*NR + r] (LDS); optionally mixes two vectors (theta*A + (1-theta)*B)
+// into xs[k*NR + r] (LDS); optionally mixes two vectors (theta*A + (1-theta)*B).
+// Columns r >= nrhs of xs are zeroed.
 template <int NR>
 __device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slot, const int* l2g, int d0, int nd,
                                           const double* A, const double* B, double ca, double cb, int sumD, int nrhs,
                                           double* xs) {
-  const int n = nd * NR;
-  for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
+  constexpr int kTPR = RhsMajor<NR>::kTPR;
+  const RhsMajor<NR> th;
+  for (int kb = th.k0; kb < nd; kb += kLB * kTPR) {
     double va[kLB][kMaxOwn], vb[kLB][kMaxOwn];
 #pragma unroll
     for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+      const int k = kb + u * kTPR;
       int o0 = 0, cnt = 0;
-      if (e < n && r < nrhs) {
+      if (k < nd && th.r < nrhs) {
         const int g = l2g[d0 + k];
         o0 = own_ptr[g];
         cnt = own_ptr[g + 1] - o0;
@@ -362,7 +419,7 @@ __device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slo
         va[u][o] = 0.0;
         vb[u][o] = 0.0;
         if (o < cnt) {
-          const size_t sl = (size_t)r * sumD + own_slot[o0 + o];
+          const size_t sl = (size_t)th.r * sumD + own_slot[o0 + o];
           va[u][o] = ld_co(&A[sl]);
           if (B) vb[u][o] = ld_co(&B[sl]);
         }
@@ -370,35 +427,40 @@ __device__ __forceinline__ void gather_dl(const int* own_ptr, const int* own_slo
     }
 #pragma unroll
     for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * kBlock;
-      if (e < n) {
+      const int k = kb + u * kTPR;
+      if (k < nd) {
         double sa = 0.0, sb = 0.0;
 #pragma unroll
         for (int o = 0; o < kMaxOwn; ++o) {
           sa += va[u][o];
           sb += vb[u][o];
         }
-        xs[e] = B ? ca * sa + cb * sb : sa;
+        xs[k * NR + th.r] = B ? ca * sa + cb * sb : sa;
       }
     }
   }
 }
 
-// Sum over the workgroup of one value per thread, split by right-hand side:
-// out[c] is the sum over the threads with threadIdx.x % NV == c (NV divides
-// 64).  `red` must hold kWaves * NV values; every thread gets the results.
-template <int NV>
-__device__ __forceinline__ void block_sum_mod(double v, double* dst, size_t stride, int nrhs, double* red) {
+// Sum over the workgroup of one value per thread, split by right-hand side
+// for the RHS-major element loops: out[r] is the sum over the threads
+// t / kTPR == r.  `red` must hold kBlock / min(kTPR, 64) values.  Fixed
+// order: the same bits on every run.
+template <int NR>
+__device__ __forceinline__ void block_sum_grp(double v, double* dst, size_t stride, int nrhs, double* red) {
+  constexpr int kTPR = RhsMajor<NR>::kTPR;
+  constexpr int kW = kTPR < 64 ? kTPR : 64;      // lanes of one right-hand side inside a wave
+  constexpr int kE = kBlock / kW;                // partial sums in `red`
 #pragma unroll
-  for (int o = 32; o >= NV; o >>= 1) v += __shfl_xor(v, o, 64);   // lanes keep their residue mod NV
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int o = 1; o < kW; o <<= 1) v += __shfl_xor(v, o, 64);   // sums within aligned groups of kW lanes
+  const int lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane < NV) red[wid * NV + lane] = v;
+  if (lane % kW == 0) red[threadIdx.x / kW] = v;
   __syncthreads();
-  if (threadIdx.x < NV && (int)threadIdx.x < nrhs) {   // thread c stores the sum of residue c
-    double t = red[threadIdx.x];
+  if ((int)threadIdx.x < nrhs) {
+    constexpr int kPer = kE / NR;                // partial sums per right-hand side
+    double t = 0.0;
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) t += red[w * NV + threadIdx.x];
+    for (int j = 0; j < kPer; ++j) t += red[threadIdx.x * kPer + j];
     st_co(dst + threadIdx.x * stride, t);
   }
 }
@@ -407,21 +469,22 @@ __device__ __forceinline__ void block_sum_mod(double v, double* dst, size_t stri
 template <int NR>
 __device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const double* A, const double* B, double ca,
                                               double cb, int sumD, int nrhs, double* xs) {
-  const int n = nd * NR;
-  for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
+  constexpr int kTPR = RhsMajor<NR>::kTPR;
+  const RhsMajor<NR> th;
+  for (int kb = th.k0; kb < nd; kb += kLB * kTPR) {
     double va[kLB][kMaxOwn], vb[kLB][kMaxOwn];
 #pragma unroll
     for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * kBlock, k = e / NR, r = e % NR;
+      const int k = kb + u * kTPR;
       int4 sl = make_int4(-1, -1, -1, -1);
-      if (e < n && r < nrhs) sl = tab_slots(tslot, k);
+      if (k < nd && th.r < nrhs) sl = tab_slots(tslot, k);
       const int so[kMaxOwn] = {sl.x, sl.y, sl.z, sl.w};
 #pragma unroll
       for (int o = 0; o < kMaxOwn; ++o) {
         va[u][o] = 0.0;
         vb[u][o] = 0.0;
         if (so[o] >= 0) {
-          const size_t q = (size_t)r * sumD + so[o];
+          const size_t q = (size_t)th.r * sumD + so[o];
           va[u][o] = ld_co(&A[q]);
           if (B) vb[u][o] = ld_co(&B[q]);
         }
@@ -429,15 +492,15 @@ __device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const do
     }
 #pragma unroll
     for (int u = 0; u < kLB; ++u) {
-      const int e = e0 + u * kBlock;
-      if (e < n) {
+      const int k = kb + u * kTPR;
+      if (k < nd) {
         double sa = 0.0, sb = 0.0;
 #pragma unroll
         for (int o = 0; o < kMaxOwn; ++o) {
           sa += va[u][o];
           sb += vb[u][o];
         }
-        xs[e] = B ? ca * sa + cb * sb : sa;
+        xs[k * NR + th.r] = B ? ca * sa + cb * sb : sa;
       }
     }
   }
@@ -456,6 +519,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
   const unsigned nb = gridDim.x;
   const int nrhs = f.nrhs;
   const int nunits = a.N * f.S;
+  constexpr int kTPR = RhsMajor<NR>::kTPR;
+  const RhsMajor<NR> th;
   // LDS layout: inputs [max n_D][NR], outputs [2][max n_G][NR], partial sums
   // [kBlock][2][NR], coarse right-hand side [2 nP] (one rhs at a time)
   double* xs = lds;
@@ -592,7 +657,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
     double* s_new = odd ? f.s0 : f.s1;
 
     // ---- A: CG update at the unit's Delta points, rows of [G; L](:, Delta) r_it
-    // (every thread's elements belong to the right-hand side threadIdx.x % NR)
+    // (RHS-major element loops: every thread's elements belong to the
+    // right-hand side th.r)
     double gacc = 0.0;
     for (int u = blockIdx.x, t = 0; u < nunits; u += nb, ++t) {
       const bool use_tab = t < f.tab_units;
@@ -602,20 +668,20 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       const int ng = np + nd;
       int r0, r1;
       slice_rows(ng, f.S, q, r0, r1);
-      constexpr int kLA = NR >= 4 ? 4 : NR;   // elements per thread whose loads are issued together
-      for (int e0 = threadIdx.x; e0 < nd * NR; e0 += kLA * kBlock) {
+      constexpr int kLA = 4;     // points per thread whose loads are issued together
+      for (int kb = th.k0; kb < nd; kb += kLA * kTPR) {
         double rv[kLA], pv[kLA], sv[kLA], wv[kLA][kMaxOwn];
         int gg[kLA];
         bool own[kLA];
 #pragma unroll
         for (int v = 0; v < kLA; ++v) {
-          const int e = e0 + v * kBlock, k = e / NR, r = e % NR;
+          const int k = kb + v * kTPR;
           rv[v] = pv[v] = sv[v] = 0.0;
 #pragma unroll
           for (int o = 0; o < kMaxOwn; ++o) wv[v][o] = 0.0;
           gg[v] = 0;
           own[v] = false;
-          if (e < nd * NR && r < nrhs) {
+          if (k < nd && th.r < nrhs) {
             int so[kMaxOwn];
             if (use_tab) {
               const int tv = tg[t * f.tab_nd + k];
@@ -630,53 +696,55 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
               for (int o = 0; o < kMaxOwn; ++o) so[o] = o < cnt ? a.dl_own_slot[o0 + o] : -1;
               own[v] = so[0] == d0 + k;
             }
-            const size_t ge = (size_t)r * a.nD + gg[v];
+            const size_t ge = (size_t)th.r * a.nD + gg[v];
             // (source chosen before the load: alternative loads into one register wait on each other)
             rv[v] = ld_co(&(it == 0 ? r_cur : r_old)[ge]);
             if (it != 0) {
-              pv[v] = ld_co(&p_old[ge]);
+              if (own[v] && q == 0) pv[v] = ld_co(&p_old[ge]);     // p is only updated by the owner
               sv[v] = ld_co(&s_old[ge]);
               // u_{it-1} at the point: the owners' rows from phase F of the pass before
 #pragma unroll
               for (int o = 0; o < kMaxOwn; ++o)
-                if (so[o] >= 0) wv[v][o] = ld_co(&a.w_loc[(size_t)r * a.sumD + so[o]]);
+                if (so[o] >= 0) wv[v][o] = ld_co(&a.w_loc[(size_t)th.r * a.sumD + so[o]]);
             }
           }
         }
 #pragma unroll
         for (int v = 0; v < kLA; ++v) {
-          const int e = e0 + v * kBlock, r = e % NR;
-          if (e >= nd * NR) continue;
+          const int k = kb + v * kTPR;
+          if (k >= nd) continue;
           double x = 0.0;
-          if (r < nrhs) {
+          if (th.r < nrhs) {
             if (it == 0) {
               x = rv[v];
             } else {
               double uu = 0.0;
 #pragma unroll
               for (int o = 0; o < kMaxOwn; ++o) uu += wv[v][o];
-              const double be = sc_beta[r], al = sc_alpha[r];
+              const double be = sc_beta[th.r], al = sc_alpha[th.r];
               const double pn = rv[v] + be * pv[v];
               const double sn = uu + be * sv[v];
               x = rv[v] - al * sn;
               if (q == 0 && own[v]) {
-                const size_t ge = (size_t)r * a.nD + gg[v];
+                const size_t ge = (size_t)th.r * a.nD + gg[v];
                 st_co(&p_new[ge], pn);
                 st_co(&s_new[ge], sn);
                 st_co(&r_cur[ge], x);
-                st_co(&f.x[ge], ld_co(&f.x[ge]) + al * pn);
+                // the solution is read and written only by this thread (the
+                // owner's unit stays with its workgroup), so plain accesses;
+                // the prologue's zero stands for x_0 and is not read back
+                f.x[ge] = (it == 1 ? 0.0 : f.x[ge]) + al * pn;
               }
             }
             if (q == 0 && own[v]) gacc += x * x;
           }
-          xs[e] = x;
+          xs[k * NR + th.r] = x;
         }
       }
       __syncthreads();
       mv_rows<T, NR, 2>(a.Gm + a.offG[i], a.Lm + a.offG[i], ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
-      for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
-        const int tt = e / NR, r = e % NR;
-        if (r >= nrhs) continue;
+      for (int tt = th.k0; tt < r1 - r0 && th.r < nrhs; tt += kTPR) {
+        const int r = th.r;
         const int row = r0 + tt;
         const double sg = ys[(0 * (r1 - r0) + tt) * NR + r], sl = ys[(1 * (r1 - r0) + tt) * NR + r];
         if (row < np) {
@@ -689,7 +757,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       }
       __syncthreads();
     }
-    block_sum_mod<NR>(gacc, &f.part[(size_t)(1 + (it & 1)) * nrhs * nb + blockIdx.x], nb, nrhs, redv);
+    block_sum_grp<NR>(gacc, &f.part[(size_t)(1 + (it & 1)) * nrhs * nb + blockIdx.x], nb, nrhs, redv);
     flag_sync(f.flags, nb, ++epoch, f.err);
 
     // ---- B: coarse solve at the corners, lam rows
@@ -770,18 +838,19 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       int r0, r1;
       slice_rows(nd, f.S, q, r0, r1);
       const T* L = a.Lm + a.offG[i];
-      for (int e0 = threadIdx.x; e0 < (r1 - r0) * nrhs; e0 += kLB * kBlock) {
+      for (int kb = th.k0; kb < r1 - r0 && th.r < nrhs; kb += kLB * kTPR) {
+        const int r = th.r;
         double lv[kLB];
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock;
-          lv[u] = e < (r1 - r0) * nrhs ? ld_co(&a.l_loc[(size_t)(e % nrhs) * a.sumD + d0 + r0 + e / nrhs]) : 0.0;
+          const int tt = kb + u * kTPR;
+          lv[u] = tt < r1 - r0 ? ld_co(&a.l_loc[(size_t)r * a.sumD + d0 + r0 + tt]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock;
-          if (e >= (r1 - r0) * nrhs) continue;
-          const int row = r0 + e / nrhs, r = e % nrhs;
+          const int tt = kb + u * kTPR;
+          if (tt >= r1 - r0) continue;
+          const int row = r0 + tt;
           double acc = lv[u];
           for (int b = 0; b < np; ++b) acc -= (double)L[(long long)b * ng + np + row] * cor[0][b][r];
           st_co(&a.lam_loc[(size_t)r * a.sumD + d0 + row], acc);
@@ -804,10 +873,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
                            nrhs, xs);
         __syncthreads();
         mv_rows<T, NR, 1>(a.Nm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
-        for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
-          const int tt = e / NR, r = e % NR;
-          if (r < nrhs) st_co(&a.y_loc[(size_t)r * a.sumD + d0 + r0 + tt], -ys[tt * NR + r]);
-        }
+        for (int tt = th.k0; tt < r1 - r0 && th.r < nrhs; tt += kTPR)
+          st_co(&a.y_loc[(size_t)th.r * a.sumD + d0 + r0 + tt], -ys[tt * NR + th.r]);
         __syncthreads();
       }
       flag_sync(f.flags, nb, ++epoch, f.err);
@@ -823,10 +890,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
                            nrhs, xs);
         __syncthreads();
         mv_rows<T, NR, 1>(a.NTm + a.offN[i], nullptr, nd, r0, r1 - r0, 0, nd, xs, nrhs, ys, part);
-        for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
-          const int tt = e / NR, r = e % NR;
-          if (r < nrhs) st_co(&a.z_loc[(size_t)r * a.sumD + d0 + r0 + tt], -ys[tt * NR + r]);
-        }
+        for (int tt = th.k0; tt < r1 - r0 && th.r < nrhs; tt += kTPR)
+          st_co(&a.z_loc[(size_t)th.r * a.sumD + d0 + r0 + tt], -ys[tt * NR + th.r]);
         __syncthreads();
       }
       flag_sync(f.flags, nb, ++epoch, f.err);
@@ -850,10 +915,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       }
       __syncthreads();
       mv_rows<T, NR, 1>(a.LTm + a.offG[i], nullptr, ng, r0, r1 - r0, np, nd, xs, nrhs, ys, part);
-      for (int e = threadIdx.x; e < (r1 - r0) * NR; e += kBlock) {
-        const int tt = e / NR, r = e % NR;
-        if (r >= nrhs) continue;
-        const int row = r0 + tt;
+      for (int tt = th.k0; tt < r1 - r0 && th.r < nrhs; tt += kTPR) {
+        const int r = th.r, row = r0 + tt;
         if (row < np) st_co(&a.nu_loc[(size_t)r * a.sumP + p0 + row], ys[tt * NR + r]);
         else st_co(&a.t_loc[(size_t)r * a.sumD + d0 + row - np], ys[tt * NR + r]);
       }
@@ -862,7 +925,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
     flag_sync(f.flags, nb, ++epoch, f.err);
 
     // ---- F: coarse nu at the corners, rows of u = A r_it; partial (u, r_it)
-    double dacc = 0.0;    // right-hand side threadIdx.x % NR
+    double dacc = 0.0;    // right-hand side th.r
     if (f.dist) {
       coarse_gather(a, a.nu_loc, (const double*)nullptr, nrhs, f.ug);
       flag_sync(f.flags, nb, ++epoch, f.err);
@@ -922,17 +985,18 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       slice_rows(nd, f.S, q, r0, r1);
       const T* G = a.Gm + a.offG[i];
       const T* LT = a.LTm + a.offG[i];
-      const int nrow = (r1 - r0) * NR;
-      for (int e0 = threadIdx.x; e0 < nrow; e0 += kLB * kBlock) {
+      const int nrow = r1 - r0;
+      for (int kb = th.k0; kb < nrow && th.r < nrhs; kb += kLB * kTPR) {
+        const int r = th.r;
         double sv[kLB], tv[kLB], rc[kLB];
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock, r = e % NR;
+          const int tt = kb + u * kTPR;
           sv[u] = 0.0;
           tv[u] = 0.0;
           rc[u] = 0.0;
-          if (e < nrow && r < nrhs) {
-            const int k = r0 + e / NR;
+          if (tt < nrow) {
+            const int k = r0 + tt;
             const size_t el = (size_t)r * a.sumD + d0 + k;
             const int g = use_tab ? tg[t * f.tab_nd + k] & ~kOwnerFlag : a.dl_l2g[d0 + k];
             sv[u] = ld_co(&a.s_loc[el]);
@@ -942,9 +1006,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
-          const int e = e0 + u * kBlock, r = e % NR;
-          if (e >= nrow || r >= nrhs) continue;
-          const int row = r0 + e / NR;
+          const int tt = kb + u * kTPR;
+          if (tt >= nrow) continue;
+          const int row = r0 + tt;
           double acc = sv[u] + tv[u];
           for (int b = 0; b < np; ++b) {
             acc -= (double)G[(long long)b * ng + np + row] * (cms[0][b][r] + cor[0][b][r]);
@@ -956,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       }
       __syncthreads();
     }
-    block_sum_mod<NR>(dacc, &f.part[blockIdx.x], nb, nrhs, redv);
+    block_sum_grp<NR>(dacc, &f.part[blockIdx.x], nb, nrhs, redv);
     flag_sync(f.flags, nb, ++epoch, f.err);
   }
 

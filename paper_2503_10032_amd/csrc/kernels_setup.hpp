@@ -14,6 +14,10 @@ namespace ddelm {
 //   value      t
 //   -Laplace   2 t (1 - t^2) (w0^2/hx^2 + w1^2/hy^2)
 //   flux       (1 - t^2) (w0 nx/hx + w1 ny/hy)
+// With a coefficient rho (operator -div(rho grad u), sec. 4.3) an interior
+// row is rho (-Laplace phi) - grad rho . grad phi, grad phi = (1 - t^2)
+// (w0/hx, w1/hy), and a flux term is multiplied by rho at its point, looked up
+// by the term's global interface index.
 // Output: column-major, element (r, j) at out[off[i] + j*ld[i] + r].
 struct FeatArgs {
   int lead;              // implicit interior rows per subdomain (-Laplace at xint)
@@ -28,7 +32,19 @@ struct FeatArgs {
   const int* ld;         // [N]
   int M;
   int sub0;              // first subdomain of this launch
+  const double* rho_int;   // [N][lead][3] rho, d rho/dx, d rho/dy at xint, or nullptr (rho = 1)
+  const double* rho_iface; // [#Pi + #Delta] rho at the interface points, or nullptr
 };
+
+// One feature value of a stored-row term, t = tanh(w . xi + b) at the term's point.
+__device__ __forceinline__ double term_value(const FeatArgs& a, const Term& tm, double t, double gx, double gy,
+                                             double lap) {
+  const double dt = 1.0 - t * t;
+  if (tm.op == OP_VALUE) return t;
+  if (tm.op == OP_NEG_LAPLACE) return 2.0 * t * dt * lap;
+  const double v = dt * (gx * tm.nx + gy * tm.ny);
+  return a.rho_iface ? a.rho_iface[tm.iface] * v : v;
+}
 
 // Rows with more terms than this (the mean-flux rows at the corners, 2(p-1)
 // terms) are left to k_features_long, which spreads a row's terms over the
@@ -51,7 +67,12 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   if (r < a.lead) {            // interior row: -Laplace(phi) at the interior point
     const double px = a.xint[((size_t)i * a.lead + r) * 2], py = a.xint[((size_t)i * a.lead + r) * 2 + 1];
     const double t = tanh_fast(w0 * ((px - cx) / hx) + w1 * ((py - cy) / hy) + bj);
-    const double v = 2.0 * t * (1.0 - t * t) * lap;
+    const double dt = 1.0 - t * t;
+    double v = 2.0 * t * dt * lap;
+    if (a.rho_int) {
+      const double* q = a.rho_int + ((size_t)i * a.lead + r) * 3;
+      v = q[0] * v - dt * (q[1] * gx + q[2] * gy);
+    }
     out[a.off[i] + (long long)j * a.ld[i] + r] = (T)v;
     return;
   }
@@ -59,14 +80,8 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   if (a.ptr[row + 1] - a.ptr[row] > kLongTerms) return;
   for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
     const Term tm = a.terms[q];
-    const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
-    const double t = tanh_fast(z);
-    const double dt = 1.0 - t * t;
-    double v;
-    if (tm.op == OP_VALUE) v = t;
-    else if (tm.op == OP_NEG_LAPLACE) v = 2.0 * t * dt * lap;
-    else v = dt * (gx * tm.nx + gy * tm.ny);
-    acc += tm.wgt * v;
+    const double t = tanh_fast(w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj);
+    acc += tm.wgt * term_value(a, tm, t, gx, gy, lap);
   }
   out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;
 }
@@ -88,14 +103,8 @@ __global__ void __launch_bounds__(kBlock) k_features_long(FeatArgs a, const int*
   double acc = 0.0;
   for (int q = a.ptr[row] + lane; q < a.ptr[row + 1]; q += 64) {
     const Term tm = a.terms[q];
-    const double z = w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj;
-    const double t = tanh_fast(z);
-    const double dt = 1.0 - t * t;
-    double v;
-    if (tm.op == OP_VALUE) v = t;
-    else if (tm.op == OP_NEG_LAPLACE) v = 2.0 * t * dt * lap;
-    else v = dt * (gx * tm.nx + gy * tm.ny);
-    acc += tm.wgt * v;
+    const double t = tanh_fast(w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj);
+    acc += tm.wgt * term_value(a, tm, t, gx, gy, lap);
   }
   acc = wave_sum(acc);
   if (lane == 0) out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;

@@ -106,6 +106,37 @@ class DDELMSolver:
             pass
 
     # ------------------------------------------------------------ API
+    def set_coefficient(self, rho_I, rho_pi, rho_dl):
+        """Coefficient rho of -div(rho grad u) (ddelm_set_coefficient):
+        rho_I (N, n_int, 3) = rho, d rho/dx, d rho/dy at the interior points,
+        rho_pi (n_pi,) and rho_dl (n_dl,) = rho at the interface_points().
+        All None: back to rho = 1.  The solver must be factored again."""
+        dev = self.device
+        if rho_I is None and rho_pi is None and rho_dl is None:
+            keep = ()
+            args = (None, None, None)
+        else:
+            keep = tuple(torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous()
+                         for t in (rho_I, rho_pi, rho_dl))
+            assert keep[0].shape == (self.N, self.x_int.shape[1], 3), "rho_I must be (N, n_int, 3)"
+            assert keep[1].shape == (self.n_pi,) and keep[2].shape == (self.n_dl,), "rho_pi (n_pi,), rho_dl (n_dl,)"
+            args = tuple(t.data_ptr() if t.numel() else None for t in keep)
+        with torch.cuda.device(dev):
+            self._check(self.lib.ddelm_set_coefficient(self.ctx, *args), "set_coefficient")
+        self.factored = False
+        return self
+
+    def coefficient_from(self, rho_fn):
+        """set_coefficient from a callable x (n, 2) numpy -> (rho (n,), grad rho (n, 2)),
+        evaluated at the interior points and at the interface points."""
+        xi = self.x_int.cpu().numpy().reshape(-1, 2)
+        r, g = rho_fn(xi)
+        rho_I = np.concatenate([np.asarray(r).reshape(-1, 1), np.asarray(g).reshape(-1, 2)], axis=1)
+        xp, xd = (t.cpu().numpy() for t in self.interface_points())
+        rp = np.asarray(rho_fn(xp)[0]).reshape(-1) if len(xp) else np.zeros(0)
+        rd = np.asarray(rho_fn(xd)[0]).reshape(-1)
+        return self.set_coefficient(rho_I.reshape(self.N, -1, 3), rp, rd)
+
     def factor(self):
         with torch.cuda.device(self.device):
             self._check(self.lib.ddelm_factor(self.ctx), "factor")

@@ -1,7 +1,19 @@
 import os
 import sys
 
-import pytest
+# The oracle makes many small LAPACK calls; a multi-threaded BLAS spends far
+# longer synchronising its threads on those than computing (a 476 x 256 QR:
+# 8 ms on one thread, seconds on eight busy ones), so the tests use one.
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+
+import pytest  # noqa: E402
+
+try:
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # also when numpy was imported before this file
+except ImportError:               # pragma: no cover
+    pass
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

@@ -20,8 +20,15 @@ generators.
                                seed 2, 16 random Fourier right-hand sides
                                (seed 100), of which 0, 7 and 15 are solved
                                here; CG to 1e-12
+  varcoef_fp64.json            the variable-coefficient workload: 16x16
+                               subdomains, M = 256, U(-2,2) seed 3, 20x20
+                               interior, 20 per edge, -div(rho grad u) = 1,
+                               u = 0, rho = tanh(GRF) + 1.1 (alpha 32, seed
+                               7); CG to 1e-10; whole mu_Delta stored,
+                               and the largest 2-norm condition number of
+                               the local matrices K_c^i and Kbar^i
 
-Usage: python tests/golden/make_fullsize_refs.py [adjoint|large_reduced ...]
+Usage: python tests/golden/make_fullsize_refs.py [adjoint|large_reduced|varcoef ...]
 """
 from __future__ import annotations
 
@@ -30,7 +37,8 @@ import os
 import sys
 import time
 
-import numpy as np
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")   # many small LAPACK calls: one thread is fastest
+import numpy as np  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -49,6 +57,8 @@ def workloads():
         "large_reduced": dict(w=I.Workload("large_reduced", 32, 32, 24, 2.0, 2, 5, 6, tol=1e-12, nrhs=16,
                                            extra_boundary=True, rhs="fourier", rhs_seed=100),
                               rhs="fourier", solve=[0, 7, 15], mu_stride=16),
+        "varcoef": dict(w=I.Workload("varcoef", 16, 16, 256, 2.0, 3, 20, 20, tol=1e-10, rhs="one", rho="grf"),
+                        rhs="one", solve=[0], mu_stride=16, full_mu=True, cond_K=True),
     }
 
 
@@ -63,18 +73,22 @@ def run(name):
     xi = I.interior_points(w)
     t0 = time.time()
     geo = O.Geometry2D(w.nx, w.ny, I.edge_params(w.p), I.extra_boundary_params(w), xi)
-    s = O.DDELMNN(geo, W, b, theta=w.theta)
+    s = O.DDELMNN(geo, W, b, theta=w.theta, rho=I.coefficient(w))
     print(f"{name}: oracle set up in {time.time() - t0:.0f} s", flush=True)
+    # 2-norm condition number of the local matrices (singular values): with a
+    # rough coefficient the diagonal of R underestimates it
+    cond_K = max(np.linalg.cond(K) for K in s.K + s.Kb) if spec.get("cond_K") else None
     if spec["rhs"] == "adjoint":
         ap = I.adjoint_params(5)
         f_fn = lambda x: ap.f(x)[None]
         g_fn = lambda x: ap.g(x)[None]
     else:
-        f_fn, g_fn = I.rhs_functions(w)
+        f_fn, g_fn = I.rhs_functions(w)     # "fourier" or "one" (f = 1, g = 0)
     X = I.eval_grid(w)
     iu = sample_indices(len(X), SAMPLE_U)
     out = dict(workload=name, nx=w.nx, ny=w.ny, M=w.M, a=w.a, seed=w.seed, n_int=w.n_int, p=w.p,
                extra_boundary=w.extra_boundary, rhs=spec["rhs"], nrhs=w.nrhs, theta=w.theta, tol=w.tol,
+               rho=w.rho, rho_alpha=w.rho_alpha, rho_seed=w.rho_seed, cond_K_max=cond_K,
                u_points=iu.tolist(), results=[])
     for r in spec["solve"]:
         t1 = time.time()
