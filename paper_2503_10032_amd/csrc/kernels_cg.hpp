@@ -144,32 +144,93 @@ __device__ __forceinline__ void coarse_gather(const OpArgs<T>& a, const double* 
 }
 
 // Distributed coarse rows: out[r][row] = sum_{c < ncol} X1[row][c] ug[r][c]
-// for this workgroup's share of the 2 nP rows.  Right-hand sides are staged
-// in LDS in groups of G = lds_cap / ncol (the launch makes lds_cap >= ncol);
-// each wave holds a 512-column tile of one X1 row in registers and applies it
-// to the whole group.
+// for this workgroup's share of the 2 nP rows.
+// One row per wave (the large case): the columns are taken in chunks of
+// Cw = lds_cap / nrhs (a multiple of 64); all right-hand sides of a chunk are
+// staged in LDS at once, the chunk of the wave's X1 row is loaded beside them,
+// and the wave keeps one accumulator per right-hand side across the chunks,
+// so X1 is read once and a chunk costs one or two batches of coherent loads.
+// Otherwise the right-hand sides are staged in groups of G = lds_cap / ncol
+// (the launch makes lds_cap >= ncol) and each wave streams a 512-column tile
+// of each of its rows per pass and applies it to the whole group.
 template <int NR>
 __device__ __forceinline__ void coarse_rows(const double* __restrict__ X1t, int nP, int ncol, const double* ug,
                                             int nrhs, double* lds, int lds_cap, double* out) {
+  constexpr int kST = NR >= 16 ? 8 : 16;   // staged elements per thread whose loads are issued together
   const unsigned nb = gridDim.x;
   const int ld = 2 * nP;
   const int chunk = (ld + (int)nb - 1) / (int)nb;
   const int row0 = blockIdx.x * chunk, row1 = min(ld, row0 + chunk);
-  const int G = max(1, min(nrhs, lds_cap / max(ncol, 1)));
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int Cw = (lds_cap / max(nrhs, 1)) / 64 * 64;
+  if (chunk <= kWaves && Cw >= 64) {
+    const int row = row0 + wid;
+    double acc[NR];
+#pragma unroll
+    for (int g = 0; g < NR; ++g) acc[g] = 0.0;
+    for (int c0 = 0; c0 < ncol; c0 += Cw) {
+      const int cw = min(Cw, ncol - c0);
+      constexpr int kXJ = NR >= 16 ? 4 : 8;
+      double xv[kXJ];                     // this lane's X1 elements of the chunk, 64 apart
+      const int nj = (cw + 63) / 64;
+      if (row1 > row0) {
+        const int n = nrhs * cw;
+        for (int e0 = threadIdx.x; e0 < n; e0 += kST * kBlock) {
+          double v[kST];
+#pragma unroll
+          for (int u = 0; u < kST; ++u) {
+            const int e = e0 + u * kBlock;
+            v[u] = e < n ? ld_co(&ug[(size_t)(e / cw) * ld + c0 + e % cw]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kST; ++u)
+            if (e0 + u * kBlock < n) lds[e0 + u * kBlock] = v[u];
+        }
+      }
+      __syncthreads();
+      for (int jb = 0; jb < nj; jb += kXJ) {
+#pragma unroll
+        for (int j = 0; j < kXJ; ++j) {
+          const int c = (jb + j) * 64 + lane;
+          xv[j] = (row < row1 && jb + j < nj && c < cw) ? X1t[(long long)row * ld + c0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kXJ; ++j) {
+          const int c = (jb + j) * 64 + lane;
+          if (row < row1 && jb + j < nj && c < cw) {
+#pragma unroll
+            for (int g = 0; g < NR; ++g)
+              if (g < nrhs) acc[g] += xv[j] * lds[g * cw + c];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (row < row1) {
+#pragma unroll
+      for (int g = 0; g < NR; ++g) {
+        if (g < nrhs) {
+          const double sum = wave_sum(acc[g]);
+          if (lane == 0) st_co(&out[(size_t)g * ld + row], sum);
+        }
+      }
+    }
+    return;
+  }
+  const int G = max(1, min(nrhs, lds_cap / max(ncol, 1)));
   for (int g0 = 0; g0 < nrhs; g0 += G) {
     const int gn = min(G, nrhs - g0);
     if (row1 > row0) {
       const int n = gn * ncol;
-      for (int e0 = threadIdx.x; e0 < n; e0 += kLB * kBlock) {
-        double v[kLB];
+      for (int e0 = threadIdx.x; e0 < n; e0 += kST * kBlock) {
+        double v[kST];
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
+        for (int u = 0; u < kST; ++u) {
           const int e = e0 + u * kBlock;
           v[u] = e < n ? ld_co(&ug[(size_t)(g0 + e / ncol) * ld + e % ncol]) : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kLB; ++u)
+        for (int u = 0; u < kST; ++u)
           if (e0 + u * kBlock < n) lds[e0 + u * kBlock] = v[u];
       }
     }
@@ -178,13 +239,13 @@ __device__ __forceinline__ void coarse_rows(const double* __restrict__ X1t, int 
       double acc[NR];
 #pragma unroll
       for (int g = 0; g < NR; ++g) acc[g] = 0.0;
-      const double* xr = X1t + (long long)row * ld;
+      const double* xrow = X1t + (long long)row * ld;
       for (int c0 = 0; c0 < ncol; c0 += 64 * 8) {
         double xv[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int c = c0 + k * 64 + lane;
-          xv[k] = c < ncol ? xr[c] : 0.0;
+          xv[k] = c < ncol ? xrow[c] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
