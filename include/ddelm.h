@@ -220,7 +220,7 @@ ddelm_status ddelm_solve(ddelm_ctx ctx, int nrhs, const double* f_I, const doubl
  * arguments, results and errors as ddelm_solve; the context must be factored
  * and the output arrays exist before the call.  The call's workspace (local
  * right-hand sides, interface vectors, CG state) is 8 bytes times
- * nrhs * (sum m + 9 sum_nD + 7 sum_nP + 12 n_dl + 10 n_pi + 12298), and in
+ * nrhs * (sum m + 12 sum_nD + 7 sum_nP + 12 n_dl + 10 n_pi + 12298), and in
  * mixed precision nrhs * (sum m + N M + sum_nD + sum_nP + 3 n_dl + 4 n_pi +
  * 512) more (sum_nD, sum_nP: local Delta and Pi points over all subdomains),
  * each buffer rounded up to 256 bytes.  It is taken from a fixed device array

@@ -465,6 +465,7 @@ struct ddelm_ctx_s {
   DBuf<double> cg_r1, cg_s1;    // second r and s buffers of the persistent CG
   DBuf<double> cg_u, cg_c;             // distributed coarse phases: gathered right-hand side, X1 times it
   DBuf<double> cg_b0, cg_xs, cg_sx, cg_nrm;   // interface solve: b, accumulated x, S_theta x, norms
+  DBuf<double> cg_rsl, cg_ssl, cg_psl; // persistent CG with one unit per subdomain: r, s, p at the slots
   const double* cg_ref = nullptr;      // per-RHS squared norm the CG stopping test is relative to
   int cg_blocks = 0, cg_slices = 0, cg_dist = 0;   // launch shape of the last persistent CG
   // refinement workspaces (mixed precision)
@@ -694,6 +695,7 @@ std::vector<WsEntry> solve_workspace(ddelm_ctx c, int nrhs) {
                           &c->cg_b0, &c->cg_xs, &c->cg_sx})
     w.push_back({b, V, false});
   w.push_back({&c->cg_nrm, (size_t)2 * nrhs, false});
+  for (DBuf<double>* b : {&c->cg_rsl, &c->cg_ssl, &c->cg_psl}) w.push_back({b, D, false});
   w.push_back({&c->mu_slot, P, true});
   w.push_back({&c->e_slot, P, true});
   w.push_back({&c->cg_part, (size_t)3 * nrhs * 4096, false});
@@ -930,6 +932,7 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int ma
   f.x = c->cg_x.p; f.r = c->cg_r.p; f.r1 = c->cg_r1.p; f.p0 = c->cg_p.p; f.p1 = c->cg_p1.p;
   f.s0 = c->cg_w.p; f.s1 = c->cg_s1.p;
   f.part = c->cg_part.p; f.mu_slot = c->mu_slot.p; f.e_slot = c->e_slot.p; f.scal = c->cg_scal.p;
+  f.rsl = c->cg_rsl.p; f.ssl = c->cg_ssl.p; f.psl = c->cg_psl.p;
   f.err = c->flags.p;
   // LDS: gathered vectors (xs), product rows (ys), the partial sums of the
   // non-MFMA products (fewer than 8 right-hand sides only) and the coarse

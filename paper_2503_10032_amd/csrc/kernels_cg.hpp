@@ -56,6 +56,16 @@ __device__ __forceinline__ double ld_co(const double* p) {
 __device__ __forceinline__ void st_co(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Values that stay inside one workgroup between phases (written and read by
+// the same unit, which keeps its workgroup for the whole launch) need no
+// agent-scope coherence: plain accesses when `own` (one unit per
+// subdomain), coherent ones otherwise (row slices of a subdomain sit in
+// different workgroups).
+__device__ __forceinline__ double ld_wg(const double* p, bool own) { return own ? *p : ld_co(p); }
+__device__ __forceinline__ void st_wg(double* p, double v, bool own) {
+  if (own) *p = v;
+  else st_co(p, v);
+}
 
 // Grid-wide synchronisation: wait until this wave's memory operations have
 // completed, publish the epoch in this workgroup's flag, then wait (bounded)
@@ -98,6 +108,9 @@ struct FusedArgs {
   double* mu_slot;       // [nrhs][sumP]  mu_Pi at the corner slots
   double* e_slot;        // [nrhs][sumP]
   double* scal;          // [nrhs][8] out: rr, bb, -, -, -, done, iters, nonfinite
+  double* rsl;           // [nrhs][sumD] with one unit per subdomain (S == 1): r, s and p at
+  double* ssl;           // every slot of the unit's Delta points, kept by the unit itself
+  double* psl;
   unsigned* flags;       // [nb * kFlagStride]
   unsigned* err;
   int lds_ys, lds_part, lds_cu;   // LDS offsets (doubles) of the output, partial-sum and coarse areas
@@ -582,6 +595,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
   const int nunits = a.N * f.S;
   constexpr int kTPR = RhsMajor<NR>::kTPR;
   const RhsMajor<NR> th;
+  // One unit per subdomain: every unit keeps r, s and p at its own Delta slots
+  // (the same values the points' other units and owner compute, bit for bit)
+  // and reads the vectors it produced itself with plain accesses.
+  const bool slot_state = f.S == 1;
   // LDS layout: inputs [max n_D][NR], outputs [2][max n_G][NR], partial sums
   // [kBlock][2][NR], coarse right-hand side [2 nP] (one rhs at a time)
   double* xs = lds;
@@ -758,11 +775,22 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
               own[v] = so[0] == d0 + k;
             }
             const size_t ge = (size_t)th.r * a.nD + gg[v];
-            // (source chosen before the load: alternative loads into one register wait on each other)
-            rv[v] = ld_co(&(it == 0 ? r_cur : r_old)[ge]);
-            if (it != 0) {
+            const size_t es = (size_t)th.r * a.sumD + d0 + k;
+            if (it == 0) {
+              rv[v] = r_cur[ge];              // b, written before the launch
+            } else if (slot_state) {
+              // r_{it-1}, s_{it-2}, p_{it-2} as this unit computed them (zero before pass 2)
+              rv[v] = f.rsl[es];
+              if (it >= 2) {
+                sv[v] = f.ssl[es];
+                if (own[v]) pv[v] = f.psl[es];
+              }
+            } else {
+              rv[v] = ld_co(&r_old[ge]);
               if (own[v] && q == 0) pv[v] = ld_co(&p_old[ge]);     // p is only updated by the owner
               sv[v] = ld_co(&s_old[ge]);
+            }
+            if (it != 0) {
               // u_{it-1} at the point: the owners' rows from phase F of the pass before
 #pragma unroll
               for (int o = 0; o < kMaxOwn; ++o)
@@ -786,17 +814,22 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
               const double pn = rv[v] + be * pv[v];
               const double sn = uu + be * sv[v];
               x = rv[v] - al * sn;
-              if (q == 0 && own[v]) {
-                const size_t ge = (size_t)th.r * a.nD + gg[v];
+              const size_t ge = (size_t)th.r * a.nD + gg[v];
+              if (slot_state) {
+                const size_t es = (size_t)th.r * a.sumD + d0 + k;
+                f.ssl[es] = sn;
+                if (own[v]) f.psl[es] = pn;
+              } else if (q == 0 && own[v]) {
                 st_co(&p_new[ge], pn);
                 st_co(&s_new[ge], sn);
                 st_co(&r_cur[ge], x);
-                // the solution is read and written only by this thread (the
-                // owner's unit stays with its workgroup), so plain accesses;
-                // the prologue's zero stands for x_0 and is not read back
-                f.x[ge] = (it == 1 ? 0.0 : f.x[ge]) + al * pn;
               }
+              // the solution is read and written only by this thread (the
+              // owner's unit stays with its workgroup), so plain accesses;
+              // the prologue's zero stands for x_0 and is not read back
+              if (q == 0 && own[v]) f.x[ge] = (it == 1 ? 0.0 : f.x[ge]) + al * pn;
             }
+            if (slot_state) f.rsl[(size_t)th.r * a.sumD + d0 + k] = x;
             if (q == 0 && own[v]) gacc += x * x;
           }
           xs[k * NR + th.r] = x;
@@ -812,8 +845,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
           st_co(&a.rho_loc[(size_t)r * a.sumP + p0 + row], sg);
           st_co(&a.psi_loc[(size_t)r * a.sumP + p0 + row], sl);
         } else {
-          st_co(&a.s_loc[(size_t)r * a.sumD + d0 + row - np], sg);
-          st_co(&a.l_loc[(size_t)r * a.sumD + d0 + row - np], sl);
+          st_wg(&a.s_loc[(size_t)r * a.sumD + d0 + row - np], sg, slot_state);   // read in F by this unit
+          st_wg(&a.l_loc[(size_t)r * a.sumD + d0 + row - np], sl, slot_state);   // read in B by this unit
         }
       }
       __syncthreads();
@@ -843,8 +876,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
         if (q == 0) {
           for (int e = threadIdx.x; e < np * nrhs; e += kBlock) {
             const int b = e / nrhs, r = e % nrhs;
-            st_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r]);
-            st_co(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r]);
+            st_wg(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r], slot_state);
+            st_wg(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r], slot_state);
           }
         }
       } else if (np > 0) {
@@ -891,8 +924,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
         if (q == 0) {
           for (int e = threadIdx.x; e < np * nrhs; e += kBlock) {
             const int b = e / nrhs, r = e % nrhs;
-            st_co(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r]);
-            st_co(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r]);
+            st_wg(&f.mu_slot[(size_t)r * a.sumP + p0 + b], cor[0][b][r], slot_state);
+            st_wg(&f.e_slot[(size_t)r * a.sumP + p0 + b], cor[1][b][r], slot_state);
           }
         }
       }
@@ -905,7 +938,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
           const int tt = kb + u * kTPR;
-          lv[u] = tt < r1 - r0 ? ld_co(&a.l_loc[(size_t)r * a.sumD + d0 + r0 + tt]) : 0.0;
+          lv[u] = tt < r1 - r0 ? ld_wg(&a.l_loc[(size_t)r * a.sumD + d0 + r0 + tt], slot_state) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kLB; ++u) {
@@ -979,7 +1012,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       for (int tt = th.k0; tt < r1 - r0 && th.r < nrhs; tt += kTPR) {
         const int r = th.r, row = r0 + tt;
         if (row < np) st_co(&a.nu_loc[(size_t)r * a.sumP + p0 + row], ys[tt * NR + r]);
-        else st_co(&a.t_loc[(size_t)r * a.sumD + d0 + row - np], ys[tt * NR + r]);
+        else st_wg(&a.t_loc[(size_t)r * a.sumD + d0 + row - np], ys[tt * NR + r], slot_state);
       }
       __syncthreads();
     }
@@ -1039,7 +1072,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       // mu and e at the corners (from B) next to nu and -D nu (cor)
       for (int e = threadIdx.x; e < 2 * np * nrhs; e += kBlock) {
         const int kind = e / (np * nrhs), b = (e / nrhs) % np, r = e % nrhs;
-        cms[kind][b][r] = ld_co(&(kind ? f.e_slot : f.mu_slot)[(size_t)r * a.sumP + p0 + b]);
+        cms[kind][b][r] = ld_wg(&(kind ? f.e_slot : f.mu_slot)[(size_t)r * a.sumP + p0 + b], slot_state);
       }
       __syncthreads();
       int r0, r1;
@@ -1060,9 +1093,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
             const int k = r0 + tt;
             const size_t el = (size_t)r * a.sumD + d0 + k;
             const int g = use_tab ? tg[t * f.tab_nd + k] & ~kOwnerFlag : a.dl_l2g[d0 + k];
-            sv[u] = ld_co(&a.s_loc[el]);
-            tv[u] = ld_co(&a.t_loc[el]);
-            rc[u] = ld_co(&r_cur[(size_t)r * a.nD + g]);
+            sv[u] = ld_wg(&a.s_loc[el], slot_state);
+            tv[u] = ld_wg(&a.t_loc[el], slot_state);
+            rc[u] = slot_state ? f.rsl[el] : ld_co(&r_cur[(size_t)r * a.nD + g]);
           }
         }
 #pragma unroll
