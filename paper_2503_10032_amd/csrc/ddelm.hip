@@ -2321,6 +2321,9 @@ ddelm_status ddelm_solve_general(ddelm_ctx c, int nrhs, const double* f_loc, con
   return solve_any(c, nrhs, nullptr, nullptr, f_loc, h, nullptr, coef, mu_pi, mu_dl, stats);
 }
 
+// From this many points on, ddelm_evaluate bins them by subdomain and runs on the matrix cores.
+constexpr long long kEvalBinMin = 4096;
+
 ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long npts, const double* x, double* u,
                             double* grad) {
   if (!c) return DDELM_E_ARG;
@@ -2328,7 +2331,49 @@ ddelm_status ddelm_evaluate(ddelm_ctx c, int nrhs, const double* coef, long long
     if (c->N == 0) c->fail(DDELM_E_STATE, "setup did not complete");
     if (nrhs < 1 || npts < 0 || !coef || (npts > 0 && (!x || !u))) c->fail(DDELM_E_ARG, "bad evaluate arguments");
     const Geometry& g = c->geo;
-    if (npts > 0) {
+    if (npts >= kEvalBinMin) {
+      // many points: bin them by subdomain, then tiles of 16 points on f64 MFMA
+      hipStream_t s = c->stream;
+      const int N = c->N, M = c->M;
+      if (npts > INT32_MAX) c->fail(DDELM_E_SHAPE, "too many evaluation points");
+      const int ngroups = ceil_div(nrhs, 16);
+      DBuf<int> cnt, cursor, perm;
+      DBuf<double> coefT;
+      cnt.alloc(N);
+      cursor.alloc(N);
+      perm.alloc((size_t)npts);
+      coefT.alloc((size_t)ngroups * N * M * 16);
+      ZeroBatch().add(cnt).add(cursor).launch(s);
+      const unsigned pb = (unsigned)ceil_div(npts, (long long)kBlock);
+      k_bin_count<<<pb, kBlock, 0, s>>>(g.nx, g.ny, g.lo[0], g.lo[1], g.h[0], g.h[1], npts, x, cnt.p);
+      HIPCHK(hipGetLastError());
+      std::vector<int> hc(N);
+      HIPCHK(hipMemcpyAsync(hc.data(), cnt.p, N * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::vector<long long> hoff(N + 1, 0), htoff(N + 1, 0);
+      for (int i = 0; i < N; ++i) {
+        hoff[i + 1] = hoff[i] + hc[i];
+        htoff[i + 1] = htoff[i] + ceil_div((long long)hc[i], 16ll);
+      }
+      c->arena.reset();
+      const long long* doff = c->arena.put(hoff, s);
+      const long long* dtoff = c->arena.put(htoff, s);
+      k_bin_scatter<<<pb, kBlock, 0, s>>>(g.nx, g.ny, g.lo[0], g.lo[1], g.h[0], g.h[1], npts, x, doff, cursor.p,
+                                          perm.p);
+      HIPCHK(hipGetLastError());
+      k_coef_transpose<<<(unsigned)std::min<long long>(ceil_div((long long)coefT.n, (long long)kBlock), 8192), kBlock, 0, s>>>(
+          N, M, nrhs, ngroups, coef, coefT.p);
+      HIPCHK(hipGetLastError());
+      const long long ntiles = htoff[N];
+      const dim3 grid((unsigned)ceil_div(ntiles, (long long)kWaves), (unsigned)ngroups);
+      if (grad)
+        k_evaluate_mfma<true><<<grid, kBlock, 0, s>>>(g.nx, M, N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p,
+                                                      coefT.p, doff, dtoff, ntiles, perm.p, npts, x, u, grad, nrhs);
+      else
+        k_evaluate_mfma<false><<<grid, kBlock, 0, s>>>(g.nx, M, N, g.lo[0], g.lo[1], g.h[0], g.h[1], c->W.p, c->b.p,
+                                                       coefT.p, doff, dtoff, ntiles, perm.p, npts, x, u, grad, nrhs);
+      HIPCHK(hipGetLastError());
+    } else if (npts > 0) {
       // right-hand sides per thread: all of them up to 16 (one tanh per point and neuron), else groups of 16
       auto launch = [&](auto nrb, auto with_grad) {
         constexpr int NRB = decltype(nrb)::value;

@@ -462,4 +462,148 @@ __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int 
   }
 }
 
+// ---------------------------------------------------------------- evaluation on the matrix cores
+//
+// For many points the evaluation runs in tiles of 16 points of one subdomain:
+// the points are binned by owning subdomain first (counting sort), then every
+// wave takes one tile and forms U (16 x 16) = T (16 x M) C^T (M x 16) on f64
+// MFMA, T = tanh(w . xi + b) computed lane by lane as the A operand (lane l:
+// point l & 15, neuron 4 s + (l >> 4) of step s, so each tanh is evaluated
+// exactly once) and C^T (coefficients of 16 right-hand sides, transposed so
+// that a neuron's 16 values are contiguous) as the B operand.  Each point's
+// value is computed on its own, so the order of the points inside a bin (set
+// by the atomics of the binning) does not change any result.
+
+// Owning subdomain of a point: the box is split uniformly, points outside it
+// are clamped to the nearest subdomain (as k_evaluate does).
+__device__ __forceinline__ int owner_of_point(double px, double py, int nx, int ny, double lo0, double lo1,
+                                              double h0, double h1) {
+  int ix = (int)ceil((px - lo0) / h0) - 1, iy = (int)ceil((py - lo1) / h1) - 1;
+  ix = ix < 0 ? 0 : (ix > nx - 1 ? nx - 1 : ix);
+  iy = iy < 0 ? 0 : (iy > ny - 1 ? ny - 1 : iy);
+  return iy * nx + ix;
+}
+
+// Points of one wave mostly share their subdomain, so the wave adds its
+// points to a bin with one atomic per distinct subdomain: the lanes of the
+// first pending subdomain find each other by a ballot, their leader takes the
+// slots, and each lane's slot is the leader's plus its rank among them.
+// Returns the lane's slot in its bin (-1 for lanes without a point).
+__device__ __forceinline__ int bin_slot(bool has, int key, int* __restrict__ ctr) {
+  const int lane = threadIdx.x & 63;
+  int slot = -1;
+  bool done = !has;
+  for (;;) {
+    const unsigned long long pending = __ballot(!done);
+    if (pending == 0) break;
+    const int lead = __ffsll((long long)pending) - 1;
+    const int k = __shfl(key, lead);
+    const bool mine = !done && key == k;
+    const unsigned long long m = __ballot(mine);
+    int base = 0;
+    if (lane == lead) base = atomicAdd(&ctr[k], __popcll(m));
+    base = __shfl(base, lead);
+    if (mine) {
+      slot = base + __popcll(m & ((1ull << lane) - 1ull));
+      done = true;
+    }
+  }
+  return slot;
+}
+
+__global__ void k_bin_count(int nx, int ny, double lo0, double lo1, double h0, double h1, long long npts,
+                            const double* __restrict__ x, int* __restrict__ cnt) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const bool has = e < npts;
+  const int i = has ? owner_of_point(x[2 * e], x[2 * e + 1], nx, ny, lo0, lo1, h0, h1) : 0;
+  bin_slot(has, i, cnt);
+}
+
+__global__ void k_bin_scatter(int nx, int ny, double lo0, double lo1, double h0, double h1, long long npts,
+                              const double* __restrict__ x, const long long* __restrict__ off,
+                              int* __restrict__ cursor, int* __restrict__ perm) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const bool has = e < npts;
+  const int i = has ? owner_of_point(x[2 * e], x[2 * e + 1], nx, ny, lo0, lo1, h0, h1) : 0;
+  const int slot = bin_slot(has, i, cursor);
+  if (has) perm[off[i] + slot] = (int)e;
+}
+
+// coefT[g][i][j][c] = coef[16 g + c][i][j] (zero for 16 g + c >= nrhs)
+__global__ void k_coef_transpose(int N, int M, int nrhs, int ngroups, const double* __restrict__ coef,
+                                 double* __restrict__ coefT) {
+  const long long n = (long long)ngroups * N * M * 16;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const int c = (int)(e % 16);
+    const long long q = e / 16;                  // (g, i, j)
+    const int j = (int)(q % M);
+    const long long gi = q / M;                  // g * N + i
+    const int i = (int)(gi % N), g = (int)(gi / N);
+    const int r = 16 * g + c;
+    coefT[e] = r < nrhs ? coef[((size_t)r * N + i) * M + j] : 0.0;
+  }
+}
+
+template <bool GRAD>
+__global__ void __launch_bounds__(kBlock) k_evaluate_mfma(int nx, int M, int N, double lo0, double lo1, double h0,
+                                                          double h1, const double* __restrict__ W,
+                                                          const double* __restrict__ bias,
+                                                          const double* __restrict__ coefT,
+                                                          const long long* __restrict__ off,
+                                                          const long long* __restrict__ toff, long long ntiles,
+                                                          const int* __restrict__ perm, long long npts,
+                                                          const double* __restrict__ x, double* __restrict__ u,
+                                                          double* __restrict__ grad, int nrhs) {
+  typedef Mfma<double>::v4 v4;
+  const long long tile = (long long)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;                    // uniform over the wave
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int g = blockIdx.y;                      // right-hand-side group of 16
+  // subdomain of the tile: toff[i] <= tile < toff[i + 1] (bins without points have no tiles)
+  int lo = 0, hi = N;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= tile) lo = mid;
+    else hi = mid;
+  }
+  const int i = lo;
+  const long long p0 = off[i] + (tile - toff[i]) * 16, pend = off[i + 1];
+  const int ix = i % nx, iy = i / nx;
+  const double hx = 0.5 * h0, hy = 0.5 * h1;
+  const double cx = lo0 + (ix + 0.5) * h0, cy = lo1 + (iy + 0.5) * h1;
+  // this lane's point for the A operand (rows past the bin repeat its last point; never stored)
+  const long long ea = perm[min(p0 + lr, pend - 1)];
+  const double xi0 = (x[2 * ea] - cx) / hx, xi1 = (x[2 * ea + 1] - cy) / hy;
+  const double* Wi = W + (size_t)i * M * 2;
+  const double* bi = bias + (size_t)i * M;
+  const double* Ci = coefT + ((size_t)g * N + i) * M * 16;
+  v4 acc = {0.0, 0.0, 0.0, 0.0}, a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < M; j0 += 4) {
+    const int j = j0 + lk;
+    const int jc = j < M ? j : M - 1;
+    const double w0 = Wi[2 * jc], w1 = Wi[2 * jc + 1];
+    const double cb = j < M ? Ci[(size_t)jc * 16 + lr] : 0.0;      // B[neuron j][rhs lr]
+    const double t = tanh_fast(w0 * xi0 + w1 * xi1 + bi[jc]);
+    acc = Mfma<double>::mma(t, cb, acc);
+    if (GRAD) {
+      const double dt = 1.0 - t * t;
+      a0 = Mfma<double>::mma(dt * w0, cb, a0);
+      a1 = Mfma<double>::mma(dt * w1, cb, a1);
+    }
+  }
+  const int r = 16 * g + lr;
+  if (r >= nrhs) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const long long p = p0 + Mfma<double>::drow(lane, v);
+    if (p >= pend) continue;
+    const long long e = perm[p];
+    u[(size_t)r * npts + e] = acc[v];
+    if (GRAD) {
+      grad[((size_t)r * npts + e) * 2] = a0[v] / hx;
+      grad[((size_t)r * npts + e) * 2 + 1] = a1[v] / hy;
+    }
+  }
+}
+
 }  // namespace ddelm

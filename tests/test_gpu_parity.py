@@ -240,6 +240,34 @@ def test_distributed_coarse_phases_match_oracle(name, nrhs, monkeypatch):
         assert _rel(out["mu_pi"][r].cpu().numpy(), refs[r]["mu_pi"]) < mu_tol(refs[r], c.tol)
 
 
+@pytest.mark.parametrize("name,nrhs", [("4x3", 1), ("4x3", 5), ("3x3_uneven", 16), ("small", 20)])
+def test_evaluate_many_points_matches_oracle(name, nrhs):
+    """Many points (binned by subdomain, tiles of 16 on f64 MFMA): u and grad u
+    for random coefficients at the evaluation grid plus random points inside
+    and outside the box, against the oracle.  Each value is a sum of M
+    products with |tanh| <= 1, so the two sides differ by at most M eps64
+    times the sum of |c_j| (times max |w_j| / h for the gradient)."""
+    torch = _torch()
+    c = Case(**CASES[name])
+    g = c.gpu()
+    geo = c.geo()
+    rng = np.random.default_rng(7)
+    X = np.concatenate([I.eval_grid(c.w), rng.uniform(-0.1, 1.1, size=(6000, 2))])
+    assert len(X) >= 4096
+    coef = rng.standard_normal((nrhs, c.w.N, c.w.M))
+    u, gr = g.evaluate(torch.as_tensor(coef, device="cuda:0"), X, grad=True)
+    u, gr = u.cpu().numpy(), gr.cpu().numpy()
+    again = g.evaluate(torch.as_tensor(coef, device="cuda:0"), X).cpu().numpy()
+    np.testing.assert_array_equal(again, u)          # the same bits with and without the gradient
+    M = c.w.M
+    for r in range(nrhs):
+        ref_u, ref_g = O.evaluate(geo, c.W, c.b, list(coef[r]), X, grad=True)
+        su = np.abs(coef[r]).sum(axis=1).max()
+        sg = max((np.abs(coef[r][i]) @ np.abs(c.W[i] / geo.subs[i].half)).max() for i in range(c.w.N))
+        np.testing.assert_allclose(u[r], ref_u, rtol=0, atol=2 * M * 1.2e-16 * su)
+        np.testing.assert_allclose(gr[r], ref_g, rtol=0, atol=2 * M * 1.2e-16 * sg)
+
+
 def test_cg_modes_agree_and_runs_repeat_bitwise():
     c = Case(**CASES["4x3"], tol=1e-12)
     res = []

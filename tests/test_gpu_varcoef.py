@@ -132,7 +132,10 @@ def test_solve_with_coefficient_matches_oracle(name, theta, coarse, kind, cg_mod
     if s.nP:
         assert _rel(out["mu_pi"][0].cpu().numpy(), ref["mu_pi"]) < bound
     assert out["stats"]["true_rel_res"] <= c.tol
-    assert abs(out["stats"]["iters"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+    # the two CG runs work on systems that differ by r (rounding of the
+    # features, the factorisation), so their iteration counts differ more than
+    # for the Poisson cases
+    assert abs(out["stats"]["iters"] - ref["iters"]) <= max(3, 0.25 * ref["iters"])
 
 
 def test_manufactured_solution_with_smooth_coefficient():
