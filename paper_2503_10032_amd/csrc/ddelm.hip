@@ -395,6 +395,7 @@ struct RowSetDev {
 template <typename T>
 struct LocalBufs {
   DBuf<T> qrA, tau, Tbuf, Tbig;        // QR matrices (K_c^i | E_G, Kbar^i | E_flux), tau, panel and block T
+  DBuf<T> topA, tau1, Tbuf1, Tbig1;    // two-stage QR: features of K_c^i, factored in their first t_i rows
   DBuf<T> Am, CD;                      // A_m^i (n_G x M), Abar^i (n_D x M)
   DBuf<T> QG;                          // Q_G^T (M x n_G) per subdomain
   DBuf<T> Gm, Lm, LTm, Nm, NTm;        // local interface operators
@@ -435,6 +436,11 @@ struct ddelm_ctx_s {
   // QR layout: 2N matrices (K_c then Kbar)
   DBuf<QRDesc> qrdesc;
   std::vector<QRDesc> h_qrdesc;
+  bool two_stage = false;              // QR of the shared interior and boundary rows first
+  DBuf<QRDesc> topdesc;
+  std::vector<QRDesc> h_topdesc;
+  DBuf<long long> top_coff;
+  DBuf<int> top_ldc, top_cn;
   int max_ncols = 0;
   int npanel = 0, nblock = 0;
   DBuf<long long> qr_coff;
@@ -1083,20 +1089,37 @@ void cg_persistent(ddelm_ctx c, int nrhs, double tol) {
 }
 
 // --------------------------------------------------------------- factorisation
-// Blocked Householder QR of every matrix held in L.qrA (layout c->h_qrdesc):
-// 16-column panels updating their 64-column block, then one 64-wide block
-// reflector per block for the trailing matrix; all products on MFMA.  L.tau
-// must be allocated; L.Tbuf and L.Tbig are allocated here.
+// A batch of matrices to factor and apply: descriptors (host and device),
+// the storage, and per matrix the column offset / leading dimension / column
+// count seen by the block-reflector updates.
 template <typename T>
-void qr_all(ddelm_ctx c, LocalBufs<T>& L, int nmat) {
+struct QRSet {
+  const QRDesc* desc = nullptr;
+  const std::vector<QRDesc>* h = nullptr;
+  const long long* coff = nullptr;
+  const int* ldc = nullptr;
+  const int* cn = nullptr;
+  int nmat = 0, max_m = 0, max_ncols = 0;
+  T* A = nullptr;
+  DBuf<T>* tau = nullptr;
+  DBuf<T>* Tbuf = nullptr;
+  DBuf<T>* Tbig = nullptr;
+};
+
+// Blocked Householder QR of every matrix of the set: 16-column panels
+// updating their 64-column block, then one 64-wide block reflector per block
+// for the trailing matrix; all products on MFMA.  tau must be allocated;
+// Tbuf and Tbig are allocated here.
+template <typename T>
+void qr_all(ddelm_ctx c, const QRSet<T>& q) {
   hipStream_t s = c->stream;
   const int M = c->M;
-  const Geometry& g = c->geo;
+  const int nmat = q.nmat;
   {
     c->npanel = ceil_div(M, kNB);
     c->nblock = ceil_div(M, kBB);
-    L.Tbuf.alloc((size_t)nmat * c->npanel * kNB * kNB);
-    L.Tbig.alloc((size_t)nmat * c->nblock * kBB * kBB);
+    q.Tbuf->alloc((size_t)nmat * c->npanel * kNB * kNB);
+    q.Tbig->alloc((size_t)nmat * c->nblock * kBB * kBB);
     // Look-ahead: after block b is factored, its block reflector is applied
     // first to the columns of block b+1 (on the main stream, which then
     // factors block b+1) and to the columns beyond on a second stream, so
@@ -1124,17 +1147,16 @@ void qr_all(ddelm_ctx c, LocalBufs<T>& L, int nmat) {
       const int* cnb = cn_dev + (size_t)2 * blk * nmat;
       for (int k = kb; k < kb + bw; k += kNB) {
         const int p = k / kNB;
-        launch_qr_panel16<T>(ceil_div(g.max_m, kPanelThreads), dim3(nmat), s, c->qrdesc.p, L.qrA.p, L.tau.p,
-                             L.Tbuf.p, k, p, c->npanel);
+        launch_qr_panel16<T>(ceil_div(q.max_m, kPanelThreads), dim3(nmat), s, q.desc, q.A, q.tau->p, q.Tbuf->p, k, p,
+                             c->npanel);
         const int c0 = k + std::min(kNB, M - k);
         if (c0 < kb + bw) {
           k_qr_wy<T><<<dim3(nmat, ceil_div(kb + bw - c0, kUC)), kBlock, 0, s>>>(
-              c->qrdesc.p, L.qrA.p, L.Tbuf.p, k, p, c->npanel, L.qrA.p, c->qr_coff.p, c->qr_ldc.p, cnb, c0, 1);
+              q.desc, q.A, q.Tbuf->p, k, p, c->npanel, q.A, q.coff, q.ldc, cnb, c0, 1);
           HIPCHK(hipGetLastError());
         }
       }
-      k_qr_tmerge<T><<<nmat, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbuf.p, L.Tbig.p, kb, blk, c->npanel,
-                                             c->nblock);
+      k_qr_tmerge<T><<<nmat, kBlock, 0, s>>>(q.desc, q.A, q.Tbuf->p, q.Tbig->p, kb, blk, c->npanel, c->nblock);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(evT(blk), s));
       const int c0 = kb + bw;                                    // first trailing column
@@ -1144,17 +1166,17 @@ void qr_all(ddelm_ctx c, LocalBufs<T>& L, int nmat) {
         if (blk > 0) HIPCHK(hipStreamWaitEvent(s, evR(blk - 1), 0));
         const int* cnn = cn_dev + (size_t)(2 * blk + 1) * nmat;   // = c1
         const int ntn = ceil_div(c1 - c0, kBC);
-        k_qr_wy64<T><<<nmat8 * ntn, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntn,
-                                                    L.qrA.p, c->qr_coff.p, c->qr_ldc.p, cnn, c0, 1);
+        k_qr_wy64<T><<<nmat8 * ntn, kBlock, 0, s>>>(q.desc, q.A, q.Tbig->p, kb, blk, c->nblock, nmat, ntn, q.A,
+                                                    q.coff, q.ldc, cnn, c0, 1);
         HIPCHK(hipGetLastError());
       }
       // far update: every column after the next block (and the appended unit
       // columns), on the side stream
-      const int ntf = ceil_div(c->max_ncols - c1, kBC);
+      const int ntf = ceil_div(q.max_ncols - c1, kBC);
       HIPCHK(hipStreamWaitEvent(s2, evT(blk), 0));
       if (ntf > 0) {
-        k_qr_wy64<T><<<nmat8 * ntf, kBlock, 0, s2>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, kb, blk, c->nblock, nmat, ntf,
-                                                     L.qrA.p, c->qr_coff.p, c->qr_ldc.p, c->qr_cn.p, c1, 1);
+        k_qr_wy64<T><<<nmat8 * ntf, kBlock, 0, s2>>>(q.desc, q.A, q.Tbig->p, kb, blk, c->nblock, nmat, ntf, q.A,
+                                                     q.coff, q.ldc, q.cn, c1, 1);
         HIPCHK(hipGetLastError());
       }
       HIPCHK(hipEventRecord(evR(blk), s2));
@@ -1171,25 +1193,41 @@ void factor_impl(ddelm_ctx c) {
   const bool nn = c->use_nn;
   const int nmat = nn ? 2 * N : N;
   LocalBufs<T>& L = c->lb<T>();
+  // ---- two-stage QR.  The interior and boundary rows (the first t_i =
+  // n_I + n_B rows) of K_c^i and Kbar^i are the same, so their QR
+  // T_i = Q1 [R1; 0] is done once; K_c^i and Kbar^i then only need the QR
+  // of the (M + n_G) x M matrix [R1; G], G their interface rows, and
+  // Q = diag(Q1, I) Q2.  The rows of Q at the interface (the transformed unit
+  // columns) and R come from the second stage alone.  Used when every
+  // subdomain has t_i >= M (otherwise one QR of the whole matrix).
+  bool two = nn;
+  for (int i = 0; i < N; ++i) two = two && c->h_m[i] - c->h_nG[i] >= M;
+  if (const char* env = getenv("DDELM_QR_TWO_STAGE"))
+    if (atoi(env) == 0) two = false;
+  c->two_stage = two;
   // ---- layout of the QR matrices: K_c^i: m x (M + n_G), Kbar^i: m x (M + n_D)
+  // (two-stage: (M + n_G) rows each)
   c->h_qrdesc.assign(nmat, QRDesc());
   long long off = 0, toff = 0;
   c->max_ncols = 0;
+  int max_rows = 0;
   for (int b = 0; b < nmat; ++b) {
     const int i = b % N;
     QRDesc d;
-    d.off = off; d.m = c->h_m[i]; d.ld = c->h_m[i];
+    const int rows = two ? M + c->h_nG[i] : c->h_m[i];
+    d.off = off; d.m = rows; d.ld = rows;
     d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
     d.nrefl = M; d.tau = toff; d.pad = 0;
     c->h_qrdesc[b] = d;
     off += (long long)d.ld * d.ncols;
     toff += M;
     c->max_ncols = std::max(c->max_ncols, d.ncols);
+    max_rows = std::max(max_rows, rows);
   }
   L.qrA.alloc(off);
   L.tau.alloc(toff);
   c->qrdesc.upload(c->h_qrdesc, s);
-  {
+  if (!two) {
     long long most = 0;
     for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * (d.ncols - d.nrefl));
     if (most > 0) {
@@ -1203,12 +1241,39 @@ void factor_impl(ddelm_ctx c) {
     for (int b = 0; b < nmat; ++b) { coff[b] = c->h_qrdesc[b].off; ldc[b] = c->h_qrdesc[b].ld; cn[b] = c->h_qrdesc[b].ncols; }
     c->qr_coff.upload(coff, s); c->qr_ldc.upload(ldc, s); c->qr_cn.upload(cn, s);
   }
+  // stage one: the full features of K_c^i (ld m_i) hold T_i in their first t_i rows
+  DBuf<T> kbfull;
+  if (two) {
+    c->h_topdesc.assign(N, QRDesc());
+    long long o = 0;
+    for (int i = 0; i < N; ++i) {
+      QRDesc d;
+      d.off = o; d.m = c->h_m[i] - c->h_nG[i]; d.ld = c->h_m[i];
+      d.ncols = M; d.nrefl = M; d.tau = (long long)i * M; d.pad = 0;
+      c->h_topdesc[i] = d;
+      o += (long long)c->h_m[i] * M;
+    }
+    L.topA.alloc(o);
+    L.tau1.alloc((size_t)N * M);
+    kbfull.alloc(o);
+    c->topdesc.upload(c->h_topdesc, s);
+    std::vector<long long> coff(N);
+    std::vector<int> ldc(N), cn(N, M);
+    for (int i = 0; i < N; ++i) { coff[i] = c->h_topdesc[i].off; ldc[i] = c->h_topdesc[i].ld; }
+    c->top_coff.upload(coff, s); c->top_ldc.upload(ldc, s); c->top_cn.upload(cn, s);
+  } else {
+    L.topA.free(); L.tau1.free(); L.Tbuf1.free(); L.Tbig1.free();
+  }
   c->mark(0);
   // ---- features
   {
     std::vector<long long> o1(N), o2(N);
     std::vector<int> l1(N);
-    for (int i = 0; i < N; ++i) { o1[i] = c->h_qrdesc[i].off; l1[i] = c->h_m[i]; }
+    for (int i = 0; i < N; ++i) {
+      o1[i] = two ? c->h_topdesc[i].off : c->h_qrdesc[i].off;
+      o2[i] = two ? c->h_topdesc[i].off : c->h_qrdesc[N + i].off;
+      l1[i] = c->h_m[i];
+    }
     c->h_offAm.assign(N + 1, 0);
     c->h_offCD.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) {
@@ -1218,62 +1283,98 @@ void factor_impl(ddelm_ctx c) {
     const std::vector<long long> oAm(c->h_offAm.begin(), c->h_offAm.end() - 1);
     const std::vector<int> ldA(c->h_nG.begin(), c->h_nG.end());
     L.Am.alloc(std::max(c->h_offAm[N], 1ll));
-    assemble_features<T>(c, c->rsK, g.max_m, L.qrA.p, o1, l1, 0, N);
+    assemble_features<T>(c, c->rsK, g.max_m, two ? L.topA.p : L.qrA.p, o1, l1, 0, N);
     assemble_features<T>(c, c->rsA, g.max_nG, L.Am.p, oAm, ldA, 0, N);
     if (nn) {
-      for (int i = 0; i < N; ++i) o2[i] = c->h_qrdesc[N + i].off;
-      assemble_features<T>(c, c->rsKb, g.max_m, L.qrA.p, o2, l1, 0, N);
+      assemble_features<T>(c, c->rsKb, g.max_m, two ? kbfull.p : L.qrA.p, o2, l1, 0, N);
       std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
       const std::vector<long long> oCD(c->h_offCD.begin(), c->h_offCD.end() - 1);
       L.CD.alloc(std::max(c->h_offCD[N], 1ll));
       assemble_features<T>(c, c->rsAb, g.max_nD, L.CD.p, oCD, ldC, 0, N);
     }
-    // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
-    // M+t has a 1 at flux row n_I+n_B+n_P+t
-    std::vector<long long> pos;
-    for (int b = 0; b < nmat; ++b) {
-      const int i = b % N;
-      const QRDesc& d = c->h_qrdesc[b];
-      const SubInfo& sb = g.subs[i];
-      const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
-      const int cnt = b < N ? sb.n_G() : sb.n_D;
-      for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
-    }
-    if (!pos.empty()) {
-      const long long* dp = c->arena.put(pos, s);
-      k_set_units<T><<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), L.qrA.p);
-      HIPCHK(hipGetLastError());
+    if (!two) {
+      // unit columns: K_c column M+t has a 1 at interface row n_I+n_B+t; Kbar column
+      // M+t has a 1 at flux row n_I+n_B+n_P+t
+      std::vector<long long> pos;
+      for (int b = 0; b < nmat; ++b) {
+        const int i = b % N;
+        const QRDesc& d = c->h_qrdesc[b];
+        const SubInfo& sb = g.subs[i];
+        const int r0 = b < N ? sb.n_I + sb.n_B : sb.n_I + sb.n_B + sb.n_P;
+        const int cnt = b < N ? sb.n_G() : sb.n_D;
+        for (int t = 0; t < cnt; ++t) pos.push_back(d.off + (long long)(M + t) * d.ld + r0 + t);
+      }
+      if (!pos.empty()) {
+        const long long* dp = c->arena.put(pos, s);
+        k_set_units<T><<<ceil_div((long long)pos.size(), kBlock), kBlock, 0, s>>>(dp, (long long)pos.size(), L.qrA.p);
+        HIPCHK(hipGetLastError());
+      }
     }
   }
   c->mark(1);
+  // Mixed precision: the Householder QR (the bulk of the flops) runs in
+  // float32 on the f32 matrix cores.  Its factors are then widened to
+  // float64, and everything downstream (triangular solves, local interface
+  // operators, coarse problem, right-hand sides, recovery) runs in float64
+  // arithmetic on them; only the CG keeps float32 copies of the local
+  // interface operators.  The K_c^i features stay in float64 for the
+  // refinement residuals.
   if (c->mixed) {
-    // Mixed precision: the Householder QR (the bulk of the flops) runs in
-    // float32 on the f32 matrix cores.  Its factors are then widened to
-    // float64, and everything downstream (triangular solves, local interface
-    // operators, coarse problem, right-hand sides, recovery) runs in float64
-    // arithmetic on them; only the CG keeps float32 copies of the local
-    // interface operators.  The K_c^i features stay in float64 for the
-    // refinement residuals.
     c->h_offK.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) c->h_offK[i + 1] = c->h_offK[i] + (long long)c->h_m[i] * M;
     c->K64.alloc(c->h_offK[N]);
     std::vector<CopyDesc> cp;
-    for (int i = 0; i < N; ++i)
-      cp.push_back(CopyDesc{c->h_qrdesc[i].off, c->h_offK[i], c->h_m[i], c->h_m[i], c->h_m[i], M, 0, 0});
-    copy_batch<double, double>(c, cp, L.qrA.p, c->K64.p);
+    for (int i = 0; i < N; ++i) {
+      const long long src = two ? c->h_topdesc[i].off : c->h_qrdesc[i].off;
+      cp.push_back(CopyDesc{src, c->h_offK[i], c->h_m[i], c->h_m[i], c->h_m[i], M, 0, 0});
+    }
+    copy_batch<double, double>(c, cp, two ? L.topA.p : L.qrA.p, c->K64.p);
     c->offK_d.upload(std::vector<long long>(c->h_offK.begin(), c->h_offK.end() - 1), s);
-    LocalBufs<float>& L32 = c->l32;
-    L32.qrA.alloc(L.qrA.n);
-    L32.tau.alloc(L.tau.n);
-    convert<double, float>(s, L.qrA.p, L32.qrA.p, (long long)L.qrA.n);
-    qr_all<float>(c, L32, nmat);
-    convert<float, double>(s, L32.qrA.p, L.qrA.p, (long long)L.qrA.n);
-    convert<float, double>(s, L32.tau.p, L.tau.p, (long long)L.tau.n);
-    L.Tbig.alloc(L32.Tbig.n);
-    convert<float, double>(s, L32.Tbig.p, L.Tbig.p, (long long)L32.Tbig.n);
-    L32.qrA.free(); L32.tau.free(); L32.Tbuf.free(); L32.Tbig.free();
-  } else {
-    qr_all<T>(c, L, nmat);
+  }
+  // one QR stage over a set of matrices, in float64 or (mixed) in float32 and widened
+  auto run_qr = [&](QRSet<T> q64) {
+    if (!c->mixed) {
+      qr_all<T>(c, q64);
+      return;
+    }
+    const size_t nA = q64.A == L.qrA.p ? L.qrA.n : L.topA.n;
+    DBuf<float> A32, tau32, Tbuf32, Tbig32;
+    A32.alloc(nA);
+    tau32.alloc(q64.tau->n);
+    convert<double, float>(s, q64.A, A32.p, (long long)nA);
+    QRSet<float> q32;
+    q32.desc = q64.desc; q32.h = q64.h; q32.coff = q64.coff; q32.ldc = q64.ldc; q32.cn = q64.cn;
+    q32.nmat = q64.nmat; q32.max_m = q64.max_m; q32.max_ncols = q64.max_ncols;
+    q32.A = A32.p; q32.tau = &tau32; q32.Tbuf = &Tbuf32; q32.Tbig = &Tbig32;
+    qr_all<float>(c, q32);
+    convert<float, double>(s, A32.p, q64.A, (long long)nA);
+    convert<float, double>(s, tau32.p, q64.tau->p, (long long)tau32.n);
+    q64.Tbig->alloc(Tbig32.n);
+    convert<float, double>(s, Tbig32.p, q64.Tbig->p, (long long)Tbig32.n);
+  };
+  if (two) {
+    QRSet<T> q1;
+    q1.desc = c->topdesc.p; q1.h = &c->h_topdesc; q1.coff = c->top_coff.p; q1.ldc = c->top_ldc.p; q1.cn = c->top_cn.p;
+    q1.nmat = N; q1.max_m = g.max_m; q1.max_ncols = M;
+    q1.A = L.topA.p; q1.tau = &L.tau1; q1.Tbuf = &L.Tbuf1; q1.Tbig = &L.Tbig1;
+    run_qr(q1);
+    // the reduced matrices [R1 0; G E] of K_c^i and Kbar^i
+    std::vector<int> uoff(nmat);
+    for (int b = 0; b < nmat; ++b) uoff[b] = b < N ? 0 : c->h_nP[b % N];
+    const int* duoff = c->arena.put(uoff, s);
+    long long most = 0;
+    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * d.ncols);
+    k_stage2_assemble<T><<<dim3((unsigned)std::min(ceil_div(most, kBlock), 512), nmat), kBlock, 0, s>>>(
+        c->qrdesc.p, c->topdesc.p, N, M, duoff, L.topA.p, kbfull.p, L.qrA.p);
+    HIPCHK(hipGetLastError());
+    kbfull.free();
+  }
+  {
+    QRSet<T> q2;
+    q2.desc = c->qrdesc.p; q2.h = &c->h_qrdesc; q2.coff = c->qr_coff.p; q2.ldc = c->qr_ldc.p; q2.cn = c->qr_cn.p;
+    q2.nmat = nmat; q2.max_m = max_rows; q2.max_ncols = c->max_ncols;
+    q2.A = L.qrA.p; q2.tau = &L.tau; q2.Tbuf = &L.Tbuf; q2.Tbig = &L.Tbig;
+    run_qr(q2);
   }
   c->mark(2);
   // ---- condition estimates of the triangular factors (reported in the solve statistics)
@@ -1563,31 +1664,56 @@ void interface_solve(ddelm_ctx c, int nrhs, double tol, const double* x0, CoreOu
 // of every K_c^i: for up to 4 columns one launch applies all blocks (columns
 // in LDS), otherwise one 64-column-tile launch per block.
 template <typename T, int NR>
-void launch_apply_narrow(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
+void launch_apply_narrow(ddelm_ctx c, const QRDesc* desc, const T* A, const T* Tbig, int nrhs, int transT,
+                         hipStream_t s) {
   LocalBufs<T>& L = c->lb<T>();
   const size_t smem = (size_t)std::max(c->geo.max_m, 1) * NR * sizeof(T);
   const void* fn = (const void*)k_qr_apply_narrow<T, NR>;
   if (smem > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  k_qr_apply_narrow<T, NR><<<c->N, an_threads(NR), smem, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, c->nblock, L.F.p, c->f_off.p,
-                                                      c->f_ld.p, nrhs, transT);
+  k_qr_apply_narrow<T, NR><<<c->N, an_threads(NR), smem, s>>>(desc, A, Tbig, c->nblock, L.F.p, c->f_off.p,
+                                                              c->f_ld.p, nrhs, transT);
   HIPCHK(hipGetLastError());
 }
 
+// Q^T (transT = 1) or Q (transT = 0) of one set of N matrices applied to the
+// local vectors F (rows 0..d.m-1 of every subdomain's block).
 template <typename T>
-void apply_q_local(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
-  if (nrhs <= 1) return launch_apply_narrow<T, 1>(c, nrhs, transT, s);
-  if (nrhs <= 2) return launch_apply_narrow<T, 2>(c, nrhs, transT, s);
-  if (nrhs <= 4) return launch_apply_narrow<T, 4>(c, nrhs, transT, s);
+void apply_q_set(ddelm_ctx c, const QRDesc* desc, const T* A, const T* Tbig, int nrhs, int transT, hipStream_t s) {
+  if (nrhs <= 1) return launch_apply_narrow<T, 1>(c, desc, A, Tbig, nrhs, transT, s);
+  if (nrhs <= 2) return launch_apply_narrow<T, 2>(c, desc, A, Tbig, nrhs, transT, s);
+  if (nrhs <= 4) return launch_apply_narrow<T, 4>(c, desc, A, Tbig, nrhs, transT, s);
   LocalBufs<T>& L = c->lb<T>();
   const int N = c->N;
   const int ntile = ceil_div(nrhs, kBC);
   const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
   for (int q = 0; q < c->nblock; ++q) {
     const int blk = transT ? q : c->nblock - 1 - q;
-    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(c->qrdesc.p, L.qrA.p, L.Tbig.p, blk * kBB, blk,
-                                                               c->nblock, N, ntile, L.F.p, c->f_off.p, c->f_ld.p,
-                                                               cnR, 0, transT);
+    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, ntile,
+                                                               L.F.p, c->f_off.p, c->f_ld.p, cnR, 0, transT);
     HIPCHK(hipGetLastError());
+  }
+}
+
+// Q^T (transT = 1) or Q (transT = 0) of every K_c^i applied to the local
+// vectors F.  Two-stage factors: Q = diag(Q1, I) Q2 in the full row order
+// once the interface rows are moved next to the first M rows: Q^T is Q1^T on
+// the first t_i rows, the interface rows moved up to row M, then Q2^T; Q is
+// the reverse (the rows M..t_i-1 of the first stage's vector are zero).
+template <typename T>
+void apply_q_local(ddelm_ctx c, int nrhs, int transT, hipStream_t s) {
+  LocalBufs<T>& L = c->lb<T>();
+  if (!c->two_stage) return apply_q_set<T>(c, c->qrdesc.p, L.qrA.p, L.Tbig.p, nrhs, transT, s);
+  const size_t sm = sizeof(double) * (size_t)std::max(c->geo.max_nG, 1);
+  if (transT) {
+    apply_q_set<T>(c, c->topdesc.p, L.topA.p, L.Tbig1.p, nrhs, 1, s);
+    k_move_rows<T><<<dim3(c->N, nrhs), kBlock, sm, s>>>(c->M, c->sizes_dev.p, c->offm_d.p, c->summ, L.F.p, 0);
+    HIPCHK(hipGetLastError());
+    apply_q_set<T>(c, c->qrdesc.p, L.qrA.p, L.Tbig.p, nrhs, 1, s);
+  } else {
+    apply_q_set<T>(c, c->qrdesc.p, L.qrA.p, L.Tbig.p, nrhs, 0, s);
+    k_move_rows<T><<<dim3(c->N, nrhs), kBlock, sm, s>>>(c->M, c->sizes_dev.p, c->offm_d.p, c->summ, L.F.p, 1);
+    HIPCHK(hipGetLastError());
+    apply_q_set<T>(c, c->topdesc.p, L.topA.p, L.Tbig1.p, nrhs, 0, s);
   }
 }
 

@@ -462,6 +462,27 @@ __global__ void __launch_bounds__(kBlock) k_evaluate(int nx, int ny, int M, int 
   }
 }
 
+// Two-stage QR: the interface rows of the local vectors F (n_G rows) move
+// between their place in the full row order (from row t_i = m - n_G) and the
+// reduced order of the second stage (from row M).  down = 0: up, after Q1^T;
+// down = 1: down, before Q1, with rows M..t_i-1 (the part of the first
+// stage's vector below its M leading rows) cleared.  Whole blocks are read
+// before any is written, so the ranges may overlap.
+template <typename T>
+__global__ void k_move_rows(int M, const int* __restrict__ sizes, const long long* __restrict__ offm, long long summ,
+                            T* __restrict__ F, int down) {
+  const int i = blockIdx.x, r = blockIdx.y;
+  const int m = sizes[5 * i + 3], ng = sizes[5 * i + 4], t = m - ng;
+  extern __shared__ double buf[];
+  T* Fi = F + (size_t)r * summ + offm[i];
+  const int src = down ? M : t, dst = down ? t : M;
+  for (int k = threadIdx.x; k < ng; k += kBlock) buf[k] = (double)Fi[src + k];
+  __syncthreads();
+  if (down)
+    for (int row = M + threadIdx.x; row < t; row += kBlock) Fi[row] = T(0);
+  for (int k = threadIdx.x; k < ng; k += kBlock) Fi[dst + k] = (T)buf[k];
+}
+
 // ---------------------------------------------------------------- evaluation on the matrix cores
 //
 // For many points the evaluation runs in tiles of 16 points of one subdomain:

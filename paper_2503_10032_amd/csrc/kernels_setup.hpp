@@ -125,6 +125,34 @@ struct QRDesc {
   int pad;
 };
 
+// Reduced matrices of the two-stage QR.  Matrix b (K_c^i for b < N, Kbar^i
+// for b >= N, i = b mod N) is the (M + n_G) x ncols matrix [R1 0; G E]: R1
+// the upper triangle of the first-stage factor (rows 0..M-1 of the K_c^i
+// features after their QR over the first t_i rows), G the interface rows of
+// the full features (rows t_i.. of K_c^i, or of Kbar^i in kbfull, same
+// layout), E the unit columns of the interface rows (K_c^i) or of the flux
+// rows (Kbar^i, from its row n_P of G on: uoff).
+template <typename T>
+__global__ void k_stage2_assemble(const QRDesc* __restrict__ d2, const QRDesc* __restrict__ d1, int N, int M,
+                                  const int* __restrict__ uoff, const T* __restrict__ top,
+                                  const T* __restrict__ kbfull, T* __restrict__ A) {
+  const int b = blockIdx.y, i = b % N;
+  const QRDesc d = d2[b], t = d1[i];
+  const T* full = b < N ? top : kbfull;
+  const long long n = (long long)d.ld * d.ncols;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
+    const int row = (int)(e % d.ld), col = (int)(e / d.ld);
+    T v;
+    if (col < M) {
+      if (row < M) v = row <= col ? top[t.off + (long long)col * t.ld + row] : T(0);
+      else v = full[t.off + (long long)col * t.ld + t.m + (row - M)];
+    } else {
+      v = row == M + uoff[b] + (col - M) ? T(1) : T(0);
+    }
+    A[d.off + e] = v;
+  }
+}
+
 // Condition estimate of a triangular factor from its diagonal: for matrix b,
 // out[b] = max_j |R_jj| / min_j |R_jj| over the nrefl diagonal entries of the
 // factored matrix (infinity when a diagonal entry is zero).  One workgroup
