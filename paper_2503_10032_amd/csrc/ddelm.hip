@@ -631,7 +631,7 @@ void convert(hipStream_t s, const TS* src, TD* dst, long long n) {
 // feature assembly into column-major blocks
 template <typename T>
 void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, const std::vector<long long>& off,
-                       const std::vector<int>& ld, int sub0, int nsub) {
+                       const std::vector<int>& ld, int sub0, int nsub, const int* first_row = nullptr) {
   if (max_rows == 0 || nsub == 0) return;
   FeatArgs a;
   a.lead = rs.lead; a.xint = c->x_int.p;
@@ -640,6 +640,7 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, c
   a.off = c->arena.put(off, c->stream); a.ld = c->arena.put(ld, c->stream); a.M = c->M; a.sub0 = sub0;
   a.rho_int = c->has_rho ? c->rho_int.p : nullptr;
   a.rho_iface = c->has_rho ? c->rho_iface.p : nullptr;
+  a.first_row = first_row;
   dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
   k_features<T><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
@@ -953,7 +954,9 @@ void launch_fused(ddelm_ctx c, int nrhs, double tol, const CgConfig& cfg, int ma
   f.lds_cu = xs + ys + part;
   // the distributed coarse rows stage whole coarse right-hand sides (2 nP
   // values each, at least one) in the same LDS, from its start
-  const int area = cfg.dist ? std::max(xs + ys + part + cu, 2 * c->nP) : xs + ys + part + cu;
+  // (and the corner columns of L, G and L^T for a slice, 2 x 4 x n_D values, from its start)
+  const int area = std::max(cfg.dist ? std::max(xs + ys + part + cu, 2 * c->nP) : xs + ys + part + cu,
+                            8 * std::max(g.max_nD, 1));
   f.lds_total = (area + 1) & ~1;     // the int tables after it stay 16-byte aligned
   f.dist = cfg.dist;
   f.X1t = c->X1t.p;
@@ -1286,7 +1289,14 @@ void factor_impl(ddelm_ctx c) {
     assemble_features<T>(c, c->rsK, g.max_m, two ? L.topA.p : L.qrA.p, o1, l1, 0, N);
     assemble_features<T>(c, c->rsA, g.max_nG, L.Am.p, oAm, ldA, 0, N);
     if (nn) {
-      assemble_features<T>(c, c->rsKb, g.max_m, two ? kbfull.p : L.qrA.p, o2, l1, 0, N);
+      // two-stage: only the interface rows of Kbar^i (its other rows are those of K_c^i)
+      const int* kb_first = nullptr;
+      if (two) {
+        std::vector<int> fr(N);
+        for (int i = 0; i < N; ++i) fr[i] = c->h_m[i] - c->h_nG[i];
+        kb_first = c->arena.put(fr, s);
+      }
+      assemble_features<T>(c, c->rsKb, g.max_m, two ? kbfull.p : L.qrA.p, o2, l1, 0, N, kb_first);
       std::vector<int> ldC(c->h_nD.begin(), c->h_nD.end());
       const std::vector<long long> oCD(c->h_offCD.begin(), c->h_offCD.end() - 1);
       L.CD.alloc(std::max(c->h_offCD[N], 1ll));

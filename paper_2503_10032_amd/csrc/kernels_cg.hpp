@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       const int ng = np + nd;
       int r0, r1;
       slice_rows(ng, f.S, q, r0, r1);
-      constexpr int kLA = 4;     // points per thread whose loads are issued together
+      constexpr int kLA = 5;     // points per thread whose loads are issued together
       for (int kb = th.k0; kb < nd; kb += kLA * kTPR) {
         double rv[kLA], pv[kLA], sv[kLA], wv[kLA][kMaxOwn];
         int gg[kLA];
@@ -931,7 +931,15 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       }
       int r0, r1;
       slice_rows(nd, f.S, q, r0, r1);
-      const T* L = a.Lm + a.offG[i];
+      {
+        // the slice's rows of the Pi columns of L, staged in LDS (xs is free here)
+        const T* L = a.Lm + a.offG[i];
+        for (int e = threadIdx.x; e < np * (r1 - r0); e += kBlock) {
+          const int b = e / (r1 - r0), tt = e % (r1 - r0);
+          xs[e] = (double)L[(long long)b * ng + np + r0 + tt];
+        }
+        __syncthreads();
+      }
       for (int kb = th.k0; kb < r1 - r0 && th.r < nrhs; kb += kLB * kTPR) {
         const int r = th.r;
         double lv[kLB];
@@ -946,7 +954,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
           if (tt >= r1 - r0) continue;
           const int row = r0 + tt;
           double acc = lv[u];
-          for (int b = 0; b < np; ++b) acc -= (double)L[(long long)b * ng + np + row] * cor[0][b][r];
+          for (int b = 0; b < np; ++b) acc -= xs[b * (r1 - r0) + tt] * cor[0][b][r];
           st_co(&a.lam_loc[(size_t)r * a.sumD + d0 + row], acc);
         }
       }
@@ -1077,9 +1085,21 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
       __syncthreads();
       int r0, r1;
       slice_rows(nd, f.S, q, r0, r1);
-      const T* G = a.Gm + a.offG[i];
-      const T* LT = a.LTm + a.offG[i];
       const int nrow = r1 - r0;
+      {
+        // the slice's rows of the Pi columns of G and L^T, staged in LDS
+        // (xs is free in this phase): gw[b][t] = G(np + r0 + t, b), lw likewise
+        const T* G = a.Gm + a.offG[i];
+        const T* LT = a.LTm + a.offG[i];
+        for (int e = threadIdx.x; e < np * nrow; e += kBlock) {
+          const int b = e / nrow, tt = e % nrow;
+          xs[e] = (double)G[(long long)b * ng + np + r0 + tt];
+          xs[np * nrow + e] = (double)LT[(long long)b * ng + np + r0 + tt];
+        }
+        __syncthreads();
+      }
+      const double* gw = xs;
+      const double* lw = xs + np * nrow;
       for (int kb = th.k0; kb < nrow && th.r < nrhs; kb += kLB * kTPR) {
         const int r = th.r;
         double sv[kLB], tv[kLB], rc[kLB];
@@ -1105,8 +1125,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
           const int row = r0 + tt;
           double acc = sv[u] + tv[u];
           for (int b = 0; b < np; ++b) {
-            acc -= (double)G[(long long)b * ng + np + row] * (cms[0][b][r] + cor[0][b][r]);
-            acc += (double)LT[(long long)b * ng + np + row] * (cms[1][b][r] + cor[1][b][r]);
+            acc -= gw[b * nrow + tt] * (cms[0][b][r] + cor[0][b][r]);
+            acc += lw[b * nrow + tt] * (cms[1][b][r] + cor[1][b][r]);
           }
           st_co(&a.w_loc[(size_t)r * a.sumD + d0 + row], acc);
           dacc += acc * rc[u];

@@ -34,6 +34,7 @@ struct FeatArgs {
   int sub0;              // first subdomain of this launch
   const double* rho_int;   // [N][lead][3] rho, d rho/dx, d rho/dy at xint, or nullptr (rho = 1)
   const double* rho_iface; // [#Pi + #Delta] rho at the interface points, or nullptr
+  const int* first_row;    // [N] rows below it are not assembled, or nullptr (all rows)
 };
 
 // One feature value of a stored-row term, t = tanh(w . xi + b) at the term's point.
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__
   const int r = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int nrows = a.lead + a.row0[i + 1] - a.row0[i];
-  if (r >= nrows || j >= a.M) return;
+  if (r >= nrows || j >= a.M || (a.first_row && r < a.first_row[i])) return;
   const double cx = a.geom[4 * i], cy = a.geom[4 * i + 1], hx = a.geom[4 * i + 2], hy = a.geom[4 * i + 3];
   const double w0 = a.W[((size_t)i * a.M + j) * 2], w1 = a.W[((size_t)i * a.M + j) * 2 + 1];
   const double bj = a.bias[(size_t)i * a.M + j];
