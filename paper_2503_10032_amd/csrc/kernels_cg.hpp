@@ -539,6 +539,40 @@ __device__ __forceinline__ void block_sum_grp(double v, double* dst, size_t stri
   }
 }
 
+// Two values per thread summed by right-hand side as in block_sum_grp, into
+// the shared arrays sa[r], sb[r] (visible to every thread on return).
+// `red` must hold 2 kBlock / min(kTPR, 64) values.  Fixed order.
+template <int NR>
+__device__ __forceinline__ void block_sum_grp2(double a, double b, double* sa, double* sb, int nrhs, double* red) {
+  constexpr int kTPR = RhsMajor<NR>::kTPR;
+  constexpr int kW = kTPR < 64 ? kTPR : 64;
+  constexpr int kE = kBlock / kW;
+#pragma unroll
+  for (int o = 1; o < kW; o <<= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane % kW == 0) {
+    red[threadIdx.x / kW] = a;
+    red[kE + threadIdx.x / kW] = b;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nrhs) {
+    constexpr int kPer = kE / NR;
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      ta += red[threadIdx.x * kPer + j];
+      tb += red[kE + threadIdx.x * kPer + j];
+    }
+    sa[threadIdx.x] = ta;
+    sb[threadIdx.x] = tb;
+  }
+  __syncthreads();
+}
+
 // gather_dl with the owner slots read from the LDS table of the unit
 template <int NR>
 __device__ __forceinline__ void gather_dl_tab(const int* tslot, int nd, const double* A, const double* B, double ca,
@@ -584,7 +618,7 @@ template <typename T, int NR>
 __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
   extern __shared__ double lds[];
   __shared__ double red[kWaves];
-  __shared__ double redv[kWaves * NR];
+  __shared__ double redv[kWaves * (NR > 2 ? NR : 2)];
   __shared__ double sc_rr[NR], sc_bb[NR], sc_done[NR], sc_it[NR], sc_beta[NR], sc_alpha[NR], sc_gprev[NR];
   __shared__ double sc_gt[NR], sc_dt[NR];   // the reduced (r, r) and (u, r) of the pass before
   __shared__ double cor[2][4][NR];          // per corner: (mu, e) or (nu, -D nu)
@@ -669,35 +703,30 @@ __global__ void __launch_bounds__(kBlock, 2) k_cg_fused(FusedArgs<T> f) {
   for (;; ++it) {
     if (it > 0) {
       // ---- reduce gamma_{it-1}, delta_{it-1}; convergence test; alpha, beta (identical in every workgroup)
-      // right-hand sides in groups of kRG, so that few sums are live at once
-      constexpr int kRG = NR < 4 ? NR : 4;
-      for (int g0 = 0; g0 < NR; g0 += kRG) {
-        double gs[kRG], ds[kRG], gt[kRG], dt[kRG];
+      // RHS-major: a thread sums the partials of its right-hand side th.r over
+      // the workgroups k = th.k0 + kTPR j, the loads of a batch issued together
+      {
+        constexpr int kRB = 8;
+        double gs = 0.0, ds = 0.0;
+        if (th.r < nrhs) {
+          const double* pg = &f.part[(size_t)((1 + ((it - 1) & 1)) * nrhs + th.r) * nb];
+          const double* pd = &f.part[(size_t)th.r * nb];
+          for (int kb = th.k0; kb < (int)nb; kb += kRB * kTPR) {
+            double vg[kRB], vd[kRB];
 #pragma unroll
-        for (int r = 0; r < kRG; ++r) gs[r] = ds[r] = 0.0;
-        for (int k = threadIdx.x; k < (int)nb; k += kBlock) {
-          double vg[kRG], vd[kRG];
+            for (int u = 0; u < kRB; ++u) {
+              const int k = kb + u * kTPR;
+              vg[u] = k < (int)nb ? ld_co(pg + k) : 0.0;
+              vd[u] = k < (int)nb ? ld_co(pd + k) : 0.0;
+            }
 #pragma unroll
-          for (int r = 0; r < kRG; ++r) {
-            const int rr = g0 + r;
-            vg[r] = rr < nrhs ? ld_co(&f.part[(size_t)((1 + ((it - 1) & 1)) * nrhs + rr) * nb + k]) : 0.0;
-            vd[r] = rr < nrhs ? ld_co(&f.part[(size_t)rr * nb + k]) : 0.0;
-          }
-#pragma unroll
-          for (int r = 0; r < kRG; ++r) {
-            gs[r] += vg[r];
-            ds[r] += vd[r];
-          }
-        }
-        block_sum_vec<double, kRG>(gs, gt, redv);
-        block_sum_vec<double, kRG>(ds, dt, redv);
-        if (threadIdx.x == 0) {
-#pragma unroll
-          for (int r = 0; r < kRG; ++r) {
-            sc_gt[g0 + r] = gt[r];
-            sc_dt[g0 + r] = dt[r];
+            for (int u = 0; u < kRB; ++u) {
+              gs += vg[u];
+              ds += vd[u];
+            }
           }
         }
+        block_sum_grp2<NR>(gs, ds, sc_gt, sc_dt, nrhs, redv);
       }
       if (threadIdx.x == 0) {
         for (int r = 0; r < nrhs; ++r) {
