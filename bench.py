@@ -48,8 +48,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "f32cg": 2}
 # below) and for the workload named; otherwise the bench reports null.
 CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
 CG_TRAFFIC = {
-    ("large", "fp64"): dict(fetch_kib=195639986.8125, write_kib=81298253.5, fetch_scale=0.5, write_scale=1.0,
-                            sha256="adb3a2bfc8e8fc7e5698f908b5ee5105f4eba206a55f01c352e2a4f8fea99db7"),
+    ("large", "fp64"): dict(fetch_kib=193906726.6875, write_kib=55986124.9375, fetch_scale=0.5, write_scale=1.0,
+                            sha256="3042a8d4dfad47ab03cd56cba2d88de01ab279c28b5c0e0af45bd56b73713d05"),
 }
 
 

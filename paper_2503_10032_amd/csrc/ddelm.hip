@@ -1102,7 +1102,7 @@ struct QRSet {
   const long long* coff = nullptr;
   const int* ldc = nullptr;
   const int* cn = nullptr;
-  int nmat = 0, max_m = 0, max_ncols = 0;
+  int nmat = 0, max_ncols = 0;
   T* A = nullptr;
   DBuf<T>* tau = nullptr;
   DBuf<T>* Tbuf = nullptr;
@@ -1145,12 +1145,16 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
       std::fill_n(cn_all.begin() + (size_t)(2 * blk + 1) * nmat, nmat, std::min(kb + bw + kBB, M));
     }
     const int* cn_dev = c->arena.put(cn_all, s);
+    // rows a panel touches: all from its first column on, or (zero band)
+    // its own 16 and those from zhi on
+    int panel_rows = 0;
+    for (const QRDesc& d : *q.h) panel_rows = std::max(panel_rows, d.zhi > 0 ? std::min(d.m, d.m - d.zhi + kNB) : d.m);
     for (int blk = 0; blk < c->nblock; ++blk) {
       const int kb = blk * kBB, bw = std::min(kBB, M - kb);
       const int* cnb = cn_dev + (size_t)2 * blk * nmat;
       for (int k = kb; k < kb + bw; k += kNB) {
         const int p = k / kNB;
-        launch_qr_panel16<T>(ceil_div(q.max_m, kPanelThreads), dim3(nmat), s, q.desc, q.A, q.tau->p, q.Tbuf->p, k, p,
+        launch_qr_panel16<T>(ceil_div(panel_rows, kPanelThreads), dim3(nmat), s, q.desc, q.A, q.tau->p, q.Tbuf->p, k, p,
                              c->npanel);
         const int c0 = k + std::min(kNB, M - k);
         if (c0 < kb + bw) {
@@ -1213,19 +1217,18 @@ void factor_impl(ddelm_ctx c) {
   c->h_qrdesc.assign(nmat, QRDesc());
   long long off = 0, toff = 0;
   c->max_ncols = 0;
-  int max_rows = 0;
   for (int b = 0; b < nmat; ++b) {
     const int i = b % N;
     QRDesc d;
     const int rows = two ? M + c->h_nG[i] : c->h_m[i];
     d.off = off; d.m = rows; d.ld = rows;
     d.ncols = M + (b < N ? c->h_nG[i] : c->h_nD[i]);
-    d.nrefl = M; d.tau = toff; d.pad = 0;
+    d.nrefl = M; d.tau = toff;
+    d.zhi = two ? M : 0;   // [R1; G]: R1 is upper triangular
     c->h_qrdesc[b] = d;
     off += (long long)d.ld * d.ncols;
     toff += M;
     c->max_ncols = std::max(c->max_ncols, d.ncols);
-    max_rows = std::max(max_rows, rows);
   }
   L.qrA.alloc(off);
   L.tau.alloc(toff);
@@ -1252,7 +1255,7 @@ void factor_impl(ddelm_ctx c) {
     for (int i = 0; i < N; ++i) {
       QRDesc d;
       d.off = o; d.m = c->h_m[i] - c->h_nG[i]; d.ld = c->h_m[i];
-      d.ncols = M; d.nrefl = M; d.tau = (long long)i * M; d.pad = 0;
+      d.ncols = M; d.nrefl = M; d.tau = (long long)i * M; d.zhi = 0;
       c->h_topdesc[i] = d;
       o += (long long)c->h_m[i] * M;
     }
@@ -1354,7 +1357,7 @@ void factor_impl(ddelm_ctx c) {
     convert<double, float>(s, q64.A, A32.p, (long long)nA);
     QRSet<float> q32;
     q32.desc = q64.desc; q32.h = q64.h; q32.coff = q64.coff; q32.ldc = q64.ldc; q32.cn = q64.cn;
-    q32.nmat = q64.nmat; q32.max_m = q64.max_m; q32.max_ncols = q64.max_ncols;
+    q32.nmat = q64.nmat; q32.max_ncols = q64.max_ncols;
     q32.A = A32.p; q32.tau = &tau32; q32.Tbuf = &Tbuf32; q32.Tbig = &Tbig32;
     qr_all<float>(c, q32);
     convert<float, double>(s, A32.p, q64.A, (long long)nA);
@@ -1365,7 +1368,7 @@ void factor_impl(ddelm_ctx c) {
   if (two) {
     QRSet<T> q1;
     q1.desc = c->topdesc.p; q1.h = &c->h_topdesc; q1.coff = c->top_coff.p; q1.ldc = c->top_ldc.p; q1.cn = c->top_cn.p;
-    q1.nmat = N; q1.max_m = g.max_m; q1.max_ncols = M;
+    q1.nmat = N; q1.max_ncols = M;
     q1.A = L.topA.p; q1.tau = &L.tau1; q1.Tbuf = &L.Tbuf1; q1.Tbig = &L.Tbig1;
     run_qr(q1);
     // the reduced matrices [R1 0; G E] of K_c^i and Kbar^i
@@ -1382,7 +1385,7 @@ void factor_impl(ddelm_ctx c) {
   {
     QRSet<T> q2;
     q2.desc = c->qrdesc.p; q2.h = &c->h_qrdesc; q2.coff = c->qr_coff.p; q2.ldc = c->qr_ldc.p; q2.cn = c->qr_cn.p;
-    q2.nmat = nmat; q2.max_m = max_rows; q2.max_ncols = c->max_ncols;
+    q2.nmat = nmat; q2.max_ncols = c->max_ncols;
     q2.A = L.qrA.p; q2.tau = &L.tau; q2.Tbuf = &L.Tbuf; q2.Tbig = &L.Tbig;
     run_qr(q2);
   }

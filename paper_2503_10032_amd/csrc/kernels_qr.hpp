@@ -51,6 +51,16 @@ __device__ __forceinline__ T v_elem(const T* Am, int ld, int m, int k, int row, 
   return Am[(long long)(k + j) * ld + row];
 }
 
+// Row skipping for matrices with a zero band (QRDesc::zhi): the reflectors
+// of columns [k, k + w) are zero in rows [k + w, zhi), and applying them
+// leaves those rows unchanged, so row loops that start at k jump from the
+// band's first row to zhi.  Rows at or past zhi are left alone.
+__device__ __forceinline__ int skip_band(int r, int kw, int zhi) { return (r >= kw && r < zhi) ? zhi : r; }
+// Row of panel-local index l (l = 0, 1, ...) for the panel of columns
+// [k, k + kNB): the panel's own rows first, then the rows from zhi on.
+template <int NB>
+__device__ __forceinline__ int band_row(int k, int l, int zhi) { return (zhi > k + NB && l >= NB) ? zhi + (l - NB) : k + l; }
+
 // ---------------------------------------------------------------- panel
 // One workgroup of kPanelThreads threads per matrix; rows k + tid + q*kPanelThreads.
 constexpr int kPanelThreads = 512;
@@ -107,7 +117,7 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
   for (int c = 0; c < kNB; ++c) part[c] = 0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kPanelThreads;
+    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
     const T x = a[q][JJ];
     if (r > j && r < d.m) {
 #pragma unroll
@@ -132,7 +142,7 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
   for (int c = 0; c < kNB; ++c) w[c] = rowj[c] + scale * w[c];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kPanelThreads;
+    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
     if (r >= j && r < d.m) {
       const T vj = (r == j) ? T(1) : a[q][JJ] * scale;
       a[q][JJ] = (r == j) ? beta : vj;
@@ -179,7 +189,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __re
   T a[RPT][kNB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kPanelThreads;
+    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
 #pragma unroll
     for (int c = 0; c < kNB; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
   }
@@ -188,7 +198,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __re
   if (threadIdx.x < ncol) tau[d.tau + k + threadIdx.x] = Ts[threadIdx.x][threadIdx.x];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = k + threadIdx.x + q * kPanelThreads;
+    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
 #pragma unroll
     for (int c = 0; c < kNB; ++c)
       if (r < d.m && c < ncol) Am[(long long)(k + c) * d.ld + r] = a[q][c];
@@ -246,7 +256,8 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
     }
   };
   load_chunk(k);
-  for (int r0 = k; r0 < d.m; r0 += 64) {
+  for (int r0 = k; r0 < d.m;) {
+    const int rn = skip_band(r0 + 64, k + kNB, d.zhi);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -258,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       Cs[e % 64][e / 64] = cc[u];
     }
     __syncthreads();
-    if (r0 + 64 < d.m) load_chunk(r0 + 64);
+    if (rn < d.m) load_chunk(rn);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int rr = wv * 16 + ks * 4 + (lane >> 4);
@@ -267,6 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       acc1 = Mfma<T>::mma(av, Cs[rr][16 + (lane & 15)], acc1);
     }
     __syncthreads();
+    r0 = rn;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -307,9 +319,11 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) bn_[ks] = v_elem(Am, d.ld, d.m, k, row, ks * 4 + (lane >> 4));
   };
+  // 64-row groups of the four waves, the band skipped between groups
+  auto next_rb = [&](int r) { return skip_band(r - wv * 16 + kWaves * 16, k + kNB, d.zhi) + wv * 16; };
   int rb = k + wv * 16;
   if (rb < d.m) load_rows(rb);
-  for (; rb < d.m; rb += kWaves * 16) {
+  for (; rb < d.m; rb = next_rb(rb)) {
     const int row = rb + (lane & 15);
     v4 acc[2];
     T bv[4];
@@ -319,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       for (int v = 0; v < 4; ++v) acc[cg][v] = cn_[4 * cg + v];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) bv[ks] = bn_[ks];
-    if (rb + kWaves * 16 < d.m) load_rows(rb + kWaves * 16);
+    if (next_rb(rb) < d.m) load_rows(next_rb(rb));
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
@@ -389,18 +403,19 @@ __global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__
     const int e = threadIdx.x + u * kBlock;
     vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, kb + e % 64, e / 64) : 0.0;
   }
-  for (int r0 = kb; r0 < d.m; r0 += 64) {
+  for (int r0 = kb; r0 < d.m;) {
+    const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = threadIdx.x + u * kBlock;
       Vc[e % 64][e / 64] = vv[u];
     }
     __syncthreads();
-    if (r0 + 64 < d.m) {       // next chunk's loads in flight during this chunk's products
+    if (rn < d.m) {       // next chunk's loads in flight during this chunk's products
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = threadIdx.x + u * kBlock;
-        vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, r0 + 64 + e % 64, e / 64) : 0.0;
+        vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, rn + e % 64, e / 64) : 0.0;
       }
     }
 #pragma unroll 4
@@ -411,6 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__
       for (int t = 0; t < 4; ++t) acc[t] = Mfma<double>::mma(av, Vc[rr][16 * t + (lane & 15)], acc[t]);
     }
     __syncthreads();
+    r0 = rn;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -480,7 +496,8 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
     vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
     cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
   }
-  for (int r0 = kb; r0 < d.m; r0 += 64) {
+  for (int r0 = kb; r0 < d.m;) {
+    const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = threadIdx.x + u * kBlock;
@@ -488,11 +505,11 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       Cs[e % 64][e / 64] = cc[u];
     }
     __syncthreads();
-    if (r0 + 64 < d.m) {       // next chunk's loads in flight during this chunk's products
+    if (rn < d.m) {       // next chunk's loads in flight during this chunk's products
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = threadIdx.x + u * kBlock;
-        const int row = r0 + 64 + e % 64, c = e / 64;
+        const int row = rn + e % 64, c = e / 64;
         vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
         cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
       }
@@ -505,6 +522,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mma(av, Cs[rr][16 * t + (lane & 15)], acc[t]);
     }
     __syncthreads();
+    r0 = rn;
   }
   // W into Cs, T into Vs
 #pragma unroll
@@ -555,9 +573,10 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       bn_[ks] = jj < bw ? v_elem(Am, d.ld, d.m, kb, row, jj) : T(0);
     }
   };
+  auto next_rb = [&](int r) { return skip_band(r - wv * 16 + kWaves * 16, kb + kBB, d.zhi) + wv * 16; };
   int rb = kb + wv * 16;
   if (rb < d.m) load_rows(rb);
-  for (; rb < d.m; rb += kWaves * 16) {
+  for (; rb < d.m; rb = next_rb(rb)) {
     const int row = rb + (lane & 15);
     v4 cacc[4];
     T bv[16];
@@ -567,7 +586,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       for (int v = 0; v < 4; ++v) cacc[t][v] = cn_[4 * t + v];
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) bv[ks] = bn_[ks];
-    if (rb + kWaves * 16 < d.m) load_rows(rb + kWaves * 16);
+    if (next_rb(rb) < d.m) load_rows(next_rb(rb));
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int jj = ks * 4 + (lane >> 4);
@@ -691,17 +710,20 @@ __global__ void __launch_bounds__(an_threads(NR)) k_qr_apply_narrow(const QRDesc
     const int bw = min(kBB, d.nrefl - kb);
     const T* Tin = Tbig + ((long long)blockIdx.x * nblock + blk) * kBB * kBB;
     for (int e = threadIdx.x; e < kBB * kBB; e += kAN) Ts[e / kBB][e % kBB] = Tin[e];
+    // rows by their index l along [kb, m) with the zero band skipped
+    const int nl = d.zhi > kb + kBB ? kBB + m - d.zhi : m - kb;
     // ---- W = V^T C
     T acc[16][NR];
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj)
 #pragma unroll
       for (int c = 0; c < NR; ++c) acc[jj][c] = T(0);
-    for (int r0 = kb + 128 * wh; r0 < m; r0 += 128 * kRG) {
+    for (int l0 = 128 * wh; l0 < nl; l0 += 128 * kRG) {
       T vv[2][16], cv[2][NR];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int r = r0 + u * 64 + lane;
+        const int l = l0 + u * 64 + lane;
+        const int r = l < nl ? band_row<kBB>(kb, l, d.zhi) : m;
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
           const int j = 16 * wg + jj;
@@ -748,8 +770,9 @@ __global__ void __launch_bounds__(an_threads(NR)) k_qr_apply_narrow(const QRDesc
     }
     __syncthreads();
     // ---- C += V W, two rows per thread with their loads issued together
-    for (int r = kb + threadIdx.x; r < m; r += 2 * kAN) {
-      const int r2 = r + kAN;
+    for (int l = threadIdx.x; l < nl; l += 2 * kAN) {
+      const int r = band_row<kBB>(kb, l, d.zhi);
+      const int r2 = l + kAN < nl ? band_row<kBB>(kb, l + kAN, d.zhi) : m;
       T a[2][NR];
 #pragma unroll
       for (int c = 0; c < NR; ++c) {

@@ -123,7 +123,8 @@ struct QRDesc {
   int ncols;       // columns stored (factored columns first)
   int nrefl;       // reflectors (= factored columns)
   long long tau;   // offset into tau
-  int pad;
+  int zhi;         // rows (j, zhi) of column j are zero and stay zero (an upper
+                   // triangle on top of dense rows); 0 when there is no such band
 };
 
 // Reduced matrices of the two-stage QR.  Matrix b (K_c^i for b < N, Kbar^i
