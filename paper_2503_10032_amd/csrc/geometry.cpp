@@ -15,7 +15,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <climits>
+#include <cstdint>
 #include <set>
+#include <thread>
 #include <tuple>
 
 namespace ddelm {
@@ -101,23 +104,30 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
   subs.assign(N, SubInfo());
   rowsK = RowSet(); rowsA = RowSet(); rowsKb = RowSet(); rowsAb = RowSet();
   rowsK.lead = rowsKb.lead = n_int;   // interior rows come straight from x_int
-  {
-    const size_t side_rows = (size_t)N * (4 * (size_t)p + 4 * s_extra.size() + 8);
-    for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) {
-      r->ptr.reserve(side_rows + 1);
-      r->row0.reserve(N + 1);
-      r->terms.reserve(2 * side_rows);
-    }
-    rowsA.terms.reserve(side_rows + (size_t)N * 8 * p);
-  }
-  for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) r->ptr.push_back(0);
 
-  std::vector<Term> ft, ct;   // terms of one corner flux row / one continuity row
-  ft.reserve(8 * (size_t)p);
-  ct.reserve(3);
-  for (int iy = 0; iy < ny; ++iy) {
-    for (int ix = 0; ix < nx; ++ix) {
-      const int i = iy * nx + ix;
+  // Rows of subdomains [i0, i1) appended to rs[0..3] (K, A, Kbar, Abar).  A
+  // subdomain's rows depend only on its own position, so ranges of
+  // subdomains are built independently and concatenated in order.
+  auto build_range = [&](int i0, int i1, RowSet* rs) {
+    RowSet& rK = rs[0];
+    RowSet& rA = rs[1];
+    RowSet& rKb = rs[2];
+    RowSet& rAb = rs[3];
+    {
+      const size_t side_rows = (size_t)(i1 - i0) * (4 * (size_t)p + 4 * s_extra.size() + 8);
+      for (int k = 0; k < 4; ++k) {
+        rs[k].ptr.reserve(side_rows + 1);
+        rs[k].row0.reserve(i1 - i0 + 1);
+        rs[k].terms.reserve(2 * side_rows);
+      }
+      rA.terms.reserve(side_rows + (size_t)(i1 - i0) * 8 * p);
+    }
+    for (int k = 0; k < 4; ++k) rs[k].ptr.push_back(0);
+    std::vector<Term> ft, ct;   // terms of one corner flux row / one continuity row
+    ft.reserve(8 * (size_t)p);
+    ct.reserve(3);
+    for (int i = i0; i < i1; ++i) {
+      const int ix = i % nx, iy = i / nx;
       SubInfo& sb = subs[i];
       sb.ix = ix; sb.iy = iy;
       sb.cx = lo[0] + (ix + 0.5) * h[0];
@@ -189,16 +199,16 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
         }
       };
       // ---- rows
-      for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) r->begin_sub();
+      for (int k = 0; k < 4; ++k) rs[k].begin_sub();
       for (int k = 0; k < sb.n_B; ++k) {
         Term t{sb.xB[2 * k], sb.xB[2 * k + 1], 0, 0, 1.0, OP_VALUE, 0};
-        rowsK.add_row({t});
-        rowsKb.add_row({t});
+        rK.add_row({t});
+        rKb.add_row({t});
       }
       for (auto& g : pis) {
         Term t{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0};
-        rowsK.add_row({t});
-        rowsKb.add_row({t});
+        rK.add_row({t});
+        rKb.add_row({t});
         // flux row at a corner
         ft.clear();
         if (coarse == 2 || coarse == 4) {      // mean-flux corner rows (A_m)
@@ -221,7 +231,7 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
           vertex_normal(g.vjx, g.vjy, n);
           ft.push_back(Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, g.g});
         }
-        rowsA.add_row(ft);
+        rA.add_row(ft);
       }
       for (auto& g : dls) {
         double n[2];
@@ -235,14 +245,71 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
           if (is_pi(d.v0x, d.v0y)) ct.push_back(Term{vx(d.v0x), vy(d.v0y), 0, 0, -(1.0 - sk), OP_VALUE, 0});
           if (is_pi(d.v1x, d.v1y)) ct.push_back(Term{vx(d.v1x), vy(d.v1y), 0, 0, -sk, OP_VALUE, 0});
         }
-        rowsK.add_row(ct);
-        rowsA.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
-        rowsKb.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
-        rowsAb.add_row({Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0}});
+        rK.add_row(ct);
+        rA.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
+        rKb.add_row({Term{g.x, g.y, n[0], n[1], 1.0, OP_FLUX, n_pi + g.g}});
+        rAb.add_row({Term{g.x, g.y, 0, 0, 1.0, OP_VALUE, 0}});
       }
     }
+  };
+  RowSet* fin[4] = {&rowsK, &rowsA, &rowsKb, &rowsAb};
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nthr = (int)std::min<long long>(std::min(8u, hw), std::max(1, N / 64));
+  if (nthr <= 1) {
+    RowSet part[4];
+    build_range(0, N, part);
+    for (int k = 0; k < 4; ++k) {
+      fin[k]->row0 = std::move(part[k].row0);
+      fin[k]->ptr = std::move(part[k].ptr);
+      fin[k]->terms = std::move(part[k].terms);
+    }
+  } else {
+    std::vector<RowSet> part((size_t)4 * nthr);
+    std::vector<int> first(nthr + 1);
+    for (int t = 0; t <= nthr; ++t) first[t] = (int)((long long)N * t / nthr);
+    std::vector<char> failed(nthr, 0);
+    {
+      std::vector<std::thread> th;
+      for (int t = 0; t < nthr; ++t)
+        th.emplace_back([&, t]() {
+          try {
+            build_range(first[t], first[t + 1], &part[(size_t)4 * t]);
+          } catch (...) {
+            failed[t] = 1;
+          }
+        });
+      for (auto& x : th) x.join();
+    }
+    for (int t = 0; t < nthr; ++t)
+      if (failed[t]) return "out of host memory building the row sets";
+    // concatenate: ranges in order, row indices and term offsets shifted
+    std::vector<long long> roff((size_t)4 * (nthr + 1), 0), toff((size_t)4 * (nthr + 1), 0);
+    for (int k = 0; k < 4; ++k)
+      for (int t = 0; t < nthr; ++t) {
+        const RowSet& r = part[(size_t)4 * t + k];
+        roff[(size_t)4 * (t + 1) + k] = roff[(size_t)4 * t + k] + (long long)r.ptr.size() - 1;
+        toff[(size_t)4 * (t + 1) + k] = toff[(size_t)4 * t + k] + (long long)r.terms.size();
+      }
+    for (int k = 0; k < 4; ++k) {
+      if (toff[(size_t)4 * nthr + k] > INT32_MAX) return "row sets too large";
+      fin[k]->ptr.assign((size_t)roff[(size_t)4 * nthr + k] + 1, 0);
+      fin[k]->terms.resize((size_t)toff[(size_t)4 * nthr + k]);
+      fin[k]->row0.assign(N, 0);
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthr; ++t)
+      th.emplace_back([&, t]() {
+        for (int k = 0; k < 4; ++k) {
+          const RowSet& r = part[(size_t)4 * t + k];
+          const int ro = (int)roff[(size_t)4 * t + k], to = (int)toff[(size_t)4 * t + k];
+          std::copy(r.terms.begin(), r.terms.end(), fin[k]->terms.begin() + to);
+          for (size_t j = 1; j < r.ptr.size(); ++j) fin[k]->ptr[ro + j] = r.ptr[j] + to;
+          for (size_t q = 0; q < r.row0.size(); ++q) fin[k]->row0[first[t] + q] = r.row0[q] + ro;
+        }
+      });
+    for (auto& x : th) x.join();
   }
-  for (RowSet* r : {&rowsK, &rowsA, &rowsKb, &rowsAb}) r->row0.push_back((int)r->ptr.size() - 1);
+  for (RowSet* r : fin) r->row0.push_back((int)r->ptr.size() - 1);
 
   // ---- slot offsets, owner lists, global coordinates
   pi_off.assign(N + 1, 0);
