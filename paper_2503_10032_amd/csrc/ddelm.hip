@@ -2380,13 +2380,26 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
                                             x0);
       acc(o0);
       st.start_rel_res = o0.start_rel;
-      const size_t shm = (size_t)c->M * sizeof(double);
+      // right-hand sides per residual workgroup: the largest power of two up
+      // to 16 (and up to nrhs) whose coefficient block fits in 56 KiB of LDS
+      int P = 1;
+      while (P < 16 && P < nrhs && (size_t)c->M * 2 * P * sizeof(double) <= (size_t)56 << 10) P *= 2;
+      const size_t shm = (size_t)c->M * P * sizeof(double);
       double prev_worst = 0.0, worst = 0.0;
       for (int step = 0; step < c->opt.refine_maxit; ++step) {
-        k_residual<<<dim3(N, nrhs), kBlock, shm, s>>>(
-            c->M, c->nP, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,
-            c->K64.p, c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP,
-            c->sumD, c->l64.F.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p);
+        const dim3 grid(N, ceil_div(nrhs, P));
+#define RES_ARGS                                                                                                  \
+  c->M, c->nP, c->nD, nrhs, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,      \
+      c->K64.p, c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP, c->sumD, \
+      c->l64.F.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p
+        switch (P) {
+          case 1: k_residual<1><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
+          case 2: k_residual<2><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
+          case 4: k_residual<4><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
+          case 8: k_residual<8><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
+          default: k_residual<16><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
+        }
+#undef RES_ARGS
         HIPCHK(hipGetLastError());
         if (c->nP + c->nD > 0) {
           k_flux_residual<<<dim3(ceil_div(c->nP + c->nD, kBlock), nrhs), kBlock, 0, s>>>(

@@ -147,45 +147,84 @@ __global__ void k_recover(int M, int nP, int nD, const int* __restrict__ pi_off,
 // Residual of the coupled system [K B; A 0][c; mu] = [f; 0] in float64:
 //   R = f - K c - B mu   (B mu is -mu on the interface rows),
 //   flux slots  aP/aD = (A_m c) at the local Pi / Delta rows.
-// K64 (m x M) and A64 (n_G x M) are the float64 feature matrices.
-__global__ void k_residual(int M, int nP, int nD, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                           const int* __restrict__ dl_off, const int* __restrict__ pi_l2g,
-                           const int* __restrict__ dl_l2g, const long long* __restrict__ offK,
-                           const double* __restrict__ K64, const long long* __restrict__ offAm,
-                           const double* __restrict__ A64, const long long* __restrict__ offm, long long summ,
-                           const double* __restrict__ F64, const double* __restrict__ coef,
-                           const double* __restrict__ mu_pi, const double* __restrict__ mu_dl, int N, int sumP,
-                           int sumD, double* __restrict__ R64, double* __restrict__ fGP, double* __restrict__ fGD,
-                           double* __restrict__ aP, double* __restrict__ aD) {
-  const int i = blockIdx.x, r = blockIdx.y;
+// K64 (m x M) and A64 (n_G x M) are the float64 feature matrices.  One
+// workgroup per (subdomain, group of P right-hand sides): rows along the
+// threads, the group's P coefficient vectors in LDS (cs[k][j]), so every
+// element of K and A read from memory serves P products.  Dynamic LDS:
+// M * P doubles.
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_residual(
+    int M, int nP, int nD, int nrhs, const int* __restrict__ sizes, const int* __restrict__ pi_off,
+    const int* __restrict__ dl_off, const int* __restrict__ pi_l2g, const int* __restrict__ dl_l2g,
+    const long long* __restrict__ offK, const double* __restrict__ K64, const long long* __restrict__ offAm,
+    const double* __restrict__ A64, const long long* __restrict__ offm, long long summ,
+    const double* __restrict__ F64, const double* __restrict__ coef, const double* __restrict__ mu_pi,
+    const double* __restrict__ mu_dl, int N, int sumP, int sumD, double* __restrict__ R64,
+    double* __restrict__ fGP, double* __restrict__ fGD, double* __restrict__ aP, double* __restrict__ aD) {
+  const int i = blockIdx.x, r0 = blockIdx.y * P;
+  const int nr = min(P, nrhs - r0);
   const int nI = sizes[5 * i + 1], nB = sizes[5 * i + 2], m = sizes[5 * i + 3], ng = sizes[5 * i + 4];
   const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
   extern __shared__ double cs[];
-  for (int k = threadIdx.x; k < M; k += kBlock) cs[k] = coef[((size_t)r * N + i) * M + k];
+  for (int e = threadIdx.x; e < M * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    cs[e] = j < nr ? coef[((size_t)(r0 + j) * N + i) * M + k] : 0.0;
+  }
   __syncthreads();
+  constexpr int kU = 8;   // matrix elements loaded together per thread
   const double* K = K64 + offK[i];
-  const size_t base = (size_t)r * summ + offm[i];
+  const long long base = offm[i];
   for (int row = threadIdx.x; row < m; row += kBlock) {
-    double acc = F64[base + row];
-    for (int k = 0; k < M; ++k) acc -= K[(long long)k * m + row] * cs[k];
-    const int g = row - nI - nB;
-    if (g >= 0) {
-      if (g < np) {
-        acc += mu_pi[(size_t)r * nP + pi_l2g[p0 + g]];
-        fGP[(size_t)r * sumP + p0 + g] = acc;
-      } else {
-        acc += mu_dl[(size_t)r * nD + dl_l2g[d0 + g - np]];
-        fGD[(size_t)r * sumD + d0 + g - np] = acc;
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = j < nr ? F64[(size_t)(r0 + j) * summ + base + row] : 0.0;
+    for (int k0 = 0; k0 < M; k0 += kU) {
+      double kv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) kv[u] = k0 + u < M ? K[(long long)(k0 + u) * m + row] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (k0 + u < M) {
+#pragma unroll
+          for (int j = 0; j < P; ++j) acc[j] -= kv[u] * cs[(k0 + u) * P + j];
+        }
       }
     }
-    R64[base + row] = acc;
+    const int g = row - nI - nB;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      double v = acc[j];
+      if (g >= 0) {
+        if (g < np) {
+          v += mu_pi[(size_t)r * nP + pi_l2g[p0 + g]];
+          fGP[(size_t)r * sumP + p0 + g] = v;
+        } else {
+          v += mu_dl[(size_t)r * nD + dl_l2g[d0 + g - np]];
+          fGD[(size_t)r * sumD + d0 + g - np] = v;
+        }
+      }
+      R64[(size_t)r * summ + base + row] = v;
+    }
   }
   const double* A = A64 + offAm[i];
   for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += A[(long long)k * ng + t] * cs[k];
-    if (t < np) aP[(size_t)r * sumP + p0 + t] = acc;
-    else aD[(size_t)r * sumD + d0 + t - np] = acc;
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double av = A[(long long)k * ng + t];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += av * cs[k * P + j];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      if (t < np) aP[(size_t)r * sumP + p0 + t] = acc[j];
+      else aD[(size_t)r * sumD + d0 + t - np] = acc[j];
+    }
   }
 }
 
