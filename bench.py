@@ -50,6 +50,8 @@ CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
 CG_TRAFFIC = {
     ("large", "fp64"): dict(fetch_kib=193906726.6875, write_kib=55986124.9375, fetch_scale=0.5, write_scale=1.0,
                             sha256="3042a8d4dfad47ab03cd56cba2d88de01ab279c28b5c0e0af45bd56b73713d05"),
+    ("medium", "fp64"): dict(fetch_kib=1448168.3, write_kib=49408.6, fetch_scale=0.5, write_scale=1.0,
+                             sha256="3042a8d4dfad47ab03cd56cba2d88de01ab279c28b5c0e0af45bd56b73713d05"),
 }
 
 

@@ -254,7 +254,8 @@ std::string Geometry::build(int nx_, int ny_, const double* lo_, const double* h
   };
   RowSet* fin[4] = {&rowsK, &rowsA, &rowsKb, &rowsAb};
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nthr = (int)std::min<long long>(std::min(8u, hw), std::max(1, N / 64));
+  const int nthr = threads > 0 ? std::min(threads, N)
+                               : (int)std::min<long long>(std::min(8u, hw), std::max(1, N / 64));
   if (nthr <= 1) {
     RowSet part[4];
     build_range(0, N, part);

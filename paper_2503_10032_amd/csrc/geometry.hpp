@@ -60,6 +60,7 @@ struct RowSet {
 };
 
 struct Geometry {
+  int threads = 0;     // host threads for the row sets (0: up to 8, by problem size)
   int nx = 0, ny = 0, N = 0, p = 0, coarse = 2;
   double lo[2], hi[2], h[2];
   int n_pi = 0, n_dl = 0, n_edges = 0;
