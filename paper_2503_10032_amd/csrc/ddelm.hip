@@ -565,10 +565,18 @@ ddelm_status run_guarded(ddelm_ctx c, F&& fn) {
 // --------------------------------------------------------------- launch helpers
 
 template <typename T>
-void launch_qr_panel16(int rpt, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
+void launch_qr_panel16(int rows, dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
                        int npanel) {
-  switch (rpt) {
-#define CASE(R) case R: launch_qr_panel16_rpt<T, R>(grid, s, d, A, tau, Tb, k, panel, npanel); break;
+  // up to 256 rows: one row per thread of a 256-thread workgroup (fewer waves
+  // in each column's reduction, more matrices per compute unit); else
+  // ceil(rows / 512) rows per thread of 512 threads
+  if (rows <= 256) {
+    launch_qr_panel16_rpt<T, 1, 256>(grid, s, d, A, tau, Tb, k, panel, npanel);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  switch (ceil_div(rows, kPanelThreads)) {
+#define CASE(R) case R: launch_qr_panel16_rpt<T, R, kPanelThreads>(grid, s, d, A, tau, Tb, k, panel, npanel); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
     default: throw StatusError{DDELM_E_SHAPE, "local row count too large (max 3072)"};
@@ -1154,7 +1162,7 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
       const int* cnb = cn_dev + (size_t)2 * blk * nmat;
       for (int k = kb; k < kb + bw; k += kNB) {
         const int p = k / kNB;
-        launch_qr_panel16<T>(ceil_div(panel_rows, kPanelThreads), dim3(nmat), s, q.desc, q.A, q.tau->p, q.Tbuf->p, k, p,
+        launch_qr_panel16<T>(panel_rows, dim3(nmat), s, q.desc, q.A, q.tau->p, q.Tbuf->p, k, p,
                              c->npanel);
         const int c0 = k + std::min(kNB, M - k);
         if (c0 < kb + bw) {

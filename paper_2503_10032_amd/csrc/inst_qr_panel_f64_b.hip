@@ -1,4 +1,4 @@
 #include "inst_qr_panel.inc"
-DDELM_INST_PANEL(double, 4)
-DDELM_INST_PANEL(double, 5)
-DDELM_INST_PANEL(double, 6)
+DDELM_INST_PANEL(double, 4, 512)
+DDELM_INST_PANEL(double, 5, 512)
+DDELM_INST_PANEL(double, 6, 512)

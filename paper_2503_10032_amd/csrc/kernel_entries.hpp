@@ -10,8 +10,8 @@ namespace ddelm {
 
 struct QRDesc;
 
-// k_qr_panel16<T, RPT> on `grid` workgroups of kPanelThreads threads.
-template <typename T, int RPT>
+// k_qr_panel16<T, RPT, NT> on `grid` workgroups of NT threads.
+template <typename T, int RPT, int NT>
 void launch_qr_panel16_rpt(dim3 grid, hipStream_t s, const QRDesc* d, T* A, T* tau, T* Tb, int k, int panel,
                            int npanel);
 

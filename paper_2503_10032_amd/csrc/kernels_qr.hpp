@@ -62,9 +62,9 @@ template <int NB>
 __device__ __forceinline__ int band_row(int k, int l, int zhi) { return (zhi > k + NB && l >= NB) ? zhi + (l - NB) : k + l; }
 
 // ---------------------------------------------------------------- panel
-// One workgroup of kPanelThreads threads per matrix; rows k + tid + q*kPanelThreads.
+// One workgroup of NT threads per matrix (kPanelThreads, or 256 when the
+// panel has at most 256 rows); rows k + tid + q*NT.
 constexpr int kPanelThreads = 512;
-constexpr int kPanelWaves = kPanelThreads / 64;
 
 // Column JJ of a panel (compile-time, so each column only touches the
 // columns it needs and picks its own column without selects).  One reduction
@@ -75,10 +75,10 @@ constexpr int kPanelWaves = kPanelThreads / 64;
 // so the squared norm of x (slot JJ) and the 15 sums share one reduction.
 // Sum over the panel's workgroup of kNB values per thread with a single
 // barrier: wave sums through DPP, one LDS slot per wave, then every wave adds
-// the kPanelWaves partial sums itself (lanes 0..kNB-1) and broadcasts them
-// by readlane.  `red` holds kPanelWaves * kNB values; callers alternate two
+// the NW partial sums itself (lanes 0..kNB-1) and broadcasts them
+// by readlane.  `red` holds NW * kNB values (NW waves); callers alternate two
 // buffers, so a wave that runs ahead cannot overwrite sums still being read.
-template <typename T>
+template <typename T, int NW>
 __device__ __forceinline__ void panel_sum(const T* v, T* out, T* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   T w[kNB];
@@ -92,7 +92,7 @@ __device__ __forceinline__ void panel_sum(const T* v, T* out, T* red) {
   T s = 0;
   if (lane < kNB) {
 #pragma unroll
-    for (int k = 0; k < kPanelWaves; ++k) s += red[k * kNB + lane];
+    for (int k = 0; k < NW; ++k) s += red[k * kNB + lane];
   }
 #pragma unroll
   for (int c = 0; c < kNB; ++c) {
@@ -106,18 +106,18 @@ __device__ __forceinline__ void panel_sum(const T* v, T* out, T* red) {
   }
 }
 
-template <typename T, int RPT, int JJ>
+template <typename T, int RPT, int JJ, int NT>
 __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT][kNB], T* red2, T* rowj2,
                                              T (&Ts)[kNB][kNB]) {
   const int j = k + JJ;
-  T* red = red2 + (JJ & 1) * kPanelWaves * kNB;     // alternating buffers, see panel_sum
+  T* red = red2 + (JJ & 1) * (NT / 64) * kNB;     // alternating buffers, see panel_sum
   T* rowj = rowj2 + (JJ & 1) * kNB;
   T part[kNB];
 #pragma unroll
   for (int c = 0; c < kNB; ++c) part[c] = 0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
+    const int r = band_row<kNB>(k, threadIdx.x + q * NT, d.zhi);
     const T x = a[q][JJ];
     if (r > j && r < d.m) {
 #pragma unroll
@@ -129,7 +129,7 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
     }
   }
   T w[kNB];
-  panel_sum<T>(part, w, red);
+  panel_sum<T, NT / 64>(part, w, red);
   const T ss = w[JJ];
   const T alpha = rowj[JJ];
   T beta = alpha, tj = 0, scale = 0;
@@ -142,7 +142,7 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
   for (int c = 0; c < kNB; ++c) w[c] = rowj[c] + scale * w[c];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
+    const int r = band_row<kNB>(k, threadIdx.x + q * NT, d.zhi);
     if (r >= j && r < d.m) {
       const T vj = (r == j) ? T(1) : a[q][JJ] * scale;
       a[q][JJ] = (r == j) ? beta : vj;
@@ -163,48 +163,48 @@ __device__ __forceinline__ void panel_column(const QRDesc& d, int k, T (&a)[RPT]
   if (threadIdx.x == 0) Ts[JJ][JJ] = tj;
 }
 
-template <typename T, int RPT, int JJ>
+template <typename T, int RPT, int JJ, int NT>
 __device__ __forceinline__ void panel_columns(const QRDesc& d, int k, int ncol, T (&a)[RPT][kNB], T* red, T* rowj,
                                               T (&Ts)[kNB][kNB]) {
   if constexpr (JJ < kNB) {
     if (JJ < ncol) {
-      panel_column<T, RPT, JJ>(d, k, a, red, rowj, Ts);
-      panel_columns<T, RPT, JJ + 1>(d, k, ncol, a, red, rowj, Ts);
+      panel_column<T, RPT, JJ, NT>(d, k, a, red, rowj, Ts);
+      panel_columns<T, RPT, JJ + 1, NT>(d, k, ncol, a, red, rowj, Ts);
     }
   }
 }
 
-template <typename T, int RPT>
-__global__ void __launch_bounds__(kPanelThreads) k_qr_panel16(const QRDesc* __restrict__ desc, T* __restrict__ A,
+template <typename T, int RPT, int NT>
+__global__ void __launch_bounds__(NT) k_qr_panel16(const QRDesc* __restrict__ desc, T* __restrict__ A,
                                                               T* __restrict__ tau, T* __restrict__ Tbuf, int k,
                                                               int panel, int npanel) {
   const QRDesc d = desc[blockIdx.x];
   if (k >= d.nrefl) return;
-  __shared__ T red[2 * kPanelWaves * kNB];
+  __shared__ T red[2 * (NT / 64) * kNB];
   __shared__ T rowj[2 * kNB];
   __shared__ T Ts[kNB][kNB];
   T* Am = A + d.off;
   const int ncol = min(kNB, d.nrefl - k);
-  for (int e = threadIdx.x; e < kNB * kNB; e += kPanelThreads) Ts[e / kNB][e % kNB] = T(0);
+  for (int e = threadIdx.x; e < kNB * kNB; e += NT) Ts[e / kNB][e % kNB] = T(0);
   T a[RPT][kNB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
+    const int r = band_row<kNB>(k, threadIdx.x + q * NT, d.zhi);
 #pragma unroll
     for (int c = 0; c < kNB; ++c) a[q][c] = (r < d.m && c < ncol) ? Am[(long long)(k + c) * d.ld + r] : T(0);
   }
-  panel_columns<T, RPT, 0>(d, k, ncol, a, red, rowj, Ts);
+  panel_columns<T, RPT, 0, NT>(d, k, ncol, a, red, rowj, Ts);
   __syncthreads();
   if (threadIdx.x < ncol) tau[d.tau + k + threadIdx.x] = Ts[threadIdx.x][threadIdx.x];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int r = band_row<kNB>(k, threadIdx.x + q * kPanelThreads, d.zhi);
+    const int r = band_row<kNB>(k, threadIdx.x + q * NT, d.zhi);
 #pragma unroll
     for (int c = 0; c < kNB; ++c)
       if (r < d.m && c < ncol) Am[(long long)(k + c) * d.ld + r] = a[q][c];
   }
   T* Tout = Tbuf + ((long long)blockIdx.x * npanel + panel) * kNB * kNB;
-  for (int e = threadIdx.x; e < kNB * kNB; e += kPanelThreads) Tout[e] = Ts[e / kNB][e % kNB];
+  for (int e = threadIdx.x; e < kNB * kNB; e += NT) Tout[e] = Ts[e / kNB][e % kNB];
 }
 
 // ---------------------------------------------------------------- block reflector application
