@@ -74,20 +74,55 @@ constexpr int kPanelThreads = 512;
 //   v_c . v_j = v_c[j] + s sum_{r>j} x_r v_c[r]        (c < JJ, builds T)
 // so the squared norm of x (slot JJ) and the 15 sums share one reduction.
 // Sum over the panel's workgroup of kNB values per thread with a single
-// barrier: wave sums through DPP, one LDS slot per wave, then every wave adds
-// the NW partial sums itself (lanes 0..kNB-1) and broadcasts them
-// by readlane.  `red` holds NW * kNB values (NW waves); callers alternate two
-// buffers, so a wave that runs ahead cannot overwrite sums still being read.
+// barrier.  Within a wave, a reduce-scatter over each row of 16 lanes: four
+// butterfly steps through DPP moves (row mirror, half-row mirror, two quad
+// permutations; partners differ in lane bit 3, 2, 1, 0), in each of which
+// the lane whose bit is clear keeps the lower half of its values and adds
+// its partner's copy of them, so lane i of a row ends with the row's sum of
+// value i (15 moves and adds per lane instead of 16 full wave reductions);
+// then the four rows are added by two lane shuffles.  Lanes 0..kNB-1 write
+// the wave's sums to one LDS slot per wave; every wave then adds the NW
+// partial sums itself (lanes 0..kNB-1) and broadcasts them by readlane.
+// `red` holds NW * kNB values (NW waves); callers alternate two buffers, so
+// a wave that runs ahead cannot overwrite sums still being read.
 template <typename T, int NW>
 __device__ __forceinline__ void panel_sum(const T* v, T* out, T* red) {
+  static_assert(kNB == 16, "one value per lane of a 16-lane row");
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  T w[kNB];
+  T a8[8], a4[4], a2[2];
+  {
+    const bool h = lane & 8;     // partner 15 - i
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) w[c] = wave_sum_dpp(v[c]);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) red[wid * kNB + c] = w[c];
+    for (int j = 0; j < 8; ++j) {
+      const T snd = h ? v[j] : v[j + 8];
+      a8[j] = (h ? v[j + 8] : v[j]) + dpp_move<0x140, 0xf>(snd);   // row_mirror
+    }
   }
+  {
+    const bool h = lane & 4;     // partner 7 - i within the half row
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T snd = h ? a8[j] : a8[j + 4];
+      a4[j] = (h ? a8[j + 4] : a8[j]) + dpp_move<0x141, 0xf>(snd);   // row_half_mirror
+    }
+  }
+  {
+    const bool h = lane & 2;     // partner i ^ 2
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const T snd = h ? a4[j] : a4[j + 2];
+      a2[j] = (h ? a4[j + 2] : a4[j]) + dpp_move<0x4E, 0xf>(snd);   // quad_perm [2,3,0,1]
+    }
+  }
+  T w;
+  {
+    const bool h = lane & 1;     // partner i ^ 1
+    const T snd = h ? a2[0] : a2[1];
+    w = (h ? a2[1] : a2[0]) + dpp_move<0xB1, 0xf>(snd);             // quad_perm [1,0,3,2]
+  }
+  w += __shfl_xor(w, 16, 64);
+  w += __shfl_xor(w, 32, 64);
+  if (lane < kNB) red[wid * kNB + lane] = w;
   __syncthreads();
   T s = 0;
   if (lane < kNB) {
