@@ -569,25 +569,28 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   const T* Tin = Tbig + ((long long)b * nblock + blk) * kBB * kBB;
   for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Vs[e / kBB][e % kBB] = Tin[e];
   __syncthreads();
-  // ---- W <- -T^T W (Q^T) or -T W (Q)
-  T wn[kBB * kBC / kBlock];
+  // ---- W <- -T^T W (Q^T) or -T W (Q) on the matrix cores: wave wv forms
+  //      rows 16 wv .. 16 wv + 15 (4 tiles of 16 columns); the zero triangle
+  //      of T is multiplied too (64 products per wave, as one row chunk of
+  //      V^T C)
+  {
+    v4 tacc[4];
 #pragma unroll
-  for (int u = 0; u < kBB * kBC / kBlock; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    const int i = e / kBC, c = e % kBC;
-    T s = T(0);
-    if (transT) {
-      for (int ip = 0; ip <= i; ++ip) s += Vs[ip][i] * Cs[ip][c];
-    } else {
-      for (int ip = i; ip < kBB; ++ip) s += Vs[i][ip] * Cs[ip][c];
+    for (int t = 0; t < 4; ++t) tacc[t] = v4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const T av = transT ? Vs[kk][16 * wv + (lane & 15)] : Vs[16 * wv + (lane & 15)][kk];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) tacc[t] = Mfma<T>::mma(av, Cs[kk][16 * t + (lane & 15)], tacc[t]);
     }
-    wn[u] = -s;
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kBB * kBC / kBlock; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    Cs[e / kBC][e % kBC] = wn[u];
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * wv + Mfma<T>::drow(lane, v);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Cs[i][16 * t + (lane & 15)] = -tacc[t][v];
+    }
   }
   __syncthreads();
   // ---- C <- C + V W for 16-row blocks (rows along the lanes)
