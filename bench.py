@@ -119,6 +119,15 @@ def cpu_baseline(w, iters):
     W, b = I.hidden_params(s3.N, s3.M, 2, s3.a, s3.seed)
     xi = I.interior_points(s3)
 
+    def per_call(fn, min_s, min_n=3):
+        """Median time of one call, repeated for at least min_s seconds."""
+        ts, t_all = [], time.perf_counter()
+        while len(ts) < min_n or time.perf_counter() - t_all < min_s:
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
     def measure():
         t0 = time.perf_counter()
         geo = O.Geometry2D(3, 3, I.edge_params(s3.p), I.extra_boundary_params(s3), xi)
@@ -126,14 +135,10 @@ def cpu_baseline(w, iters):
         t1 = time.perf_counter()
         e = np.zeros(s.nP)
         e[0] = 1.0
-        t2 = time.perf_counter()
-        s.S_Pi_apply(e)
-        t3 = time.perf_counter()
+        t_col = per_call(lambda: s.S_Pi_apply(e), 1.0)
         v = np.random.default_rng(0).standard_normal(s.nD)
-        s.S_theta(v)
-        t4 = time.perf_counter()
-        t_col = t3 - t2
-        return t1 - t0 - s.nP * t_col, t_col, t4 - t3, s.nP
+        t_op = per_call(lambda: s.S_theta(v), 3.0)
+        return t1 - t0 - s.nP * t_col, t_col, t_op, s.nP
 
     t_set, t_col, t_op, np3 = measure()
     N, nP = w.N, (w.nx - 1) * (w.ny - 1)
@@ -150,9 +155,10 @@ def cpu_baseline(w, iters):
         "value": est, "unit": "s", "cores": int(blas_threads()), "kind": "oracle",
         "value_1thread": one,
         "sample": (f"oracle on a 3x3 partition with the {w.name} workload's local shapes: setup without the "
-                   f"coarse columns {t_set:.2f}s, one S_Pi column sweep {t_col:.3f}s, one S_theta application "
-                   f"{t_op:.3f}s; scaled as N*t_setup/9 + n_Pi*N*t_col/9 + nrhs*I*N*t_op/9 with N={N}, "
-                   f"n_Pi={nP}, nrhs={w.nrhs}, I={iters}"),
+                   f"coarse columns {t_set:.2f}s, one S_Pi column sweep {t_col:.4f}s and one S_theta application "
+                   f"{t_op:.4f}s (medians of calls repeated for 1 s and 3 s); scaled as N*t_setup/9 + "
+                   f"n_Pi*N*t_col/9 + nrhs*I*N*t_op/9 with N={N}, n_Pi={nP}, nrhs={w.nrhs}, I={iters}; "
+                   f"measured with all BLAS threads, then again with one"),
     }
 
 
