@@ -1705,12 +1705,17 @@ void apply_q_set(ddelm_ctx c, const QRDesc* desc, const T* A, const T* Tbig, int
   if (nrhs <= 4) return launch_apply_narrow<T, 4>(c, desc, A, Tbig, nrhs, transT, s);
   LocalBufs<T>& L = c->lb<T>();
   const int N = c->N;
-  const int ntile = ceil_div(nrhs, kBC);
   const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
   for (int q = 0; q < c->nblock; ++q) {
     const int blk = transT ? q : c->nblock - 1 - q;
-    k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, ntile,
-                                                               L.F.p, c->f_off.p, c->f_ld.p, cnR, 0, transT);
+    if (nrhs <= 16) {   // one 16-column tile per matrix
+      k_qr_wy64<T, 16><<<ceil_div(N, 8) * 8, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, 1, L.F.p,
+                                                             c->f_off.p, c->f_ld.p, cnR, 0, transT);
+    } else {
+      const int ntile = ceil_div(nrhs, kBC);
+      k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, ntile,
+                                                                 L.F.p, c->f_off.p, c->f_ld.p, cnR, 0, transT);
+    }
     HIPCHK(hipGetLastError());
   }
 }

@@ -493,15 +493,20 @@ __global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__
 // Apply the block reflector of block blk (columns kb .. kb+bw-1) of every
 // matrix to columns [c0, cn[b]) of C + coff[b] (leading dimension ldc[b]):
 // transT = 1 applies Q^T = I - V T^T V^T, transT = 0 applies Q = I - V T V^T.
-// 1-D grid over (matrix, 64-column tile), arranged so that all tiles of one
+// 1-D grid over (matrix, BC-column tile), arranged so that all tiles of one
 // matrix land on the same XCD (workgroup id mod 8) and share its L2 for V.
-template <typename T>
+// BC = 64 for the factorisation's trailing updates; BC = 16 applies Q or Q^T
+// to up to 16 right-hand sides without the products of 48 empty columns.
+template <typename T, int BC = kBC>
 __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                     const T* __restrict__ Tbig, int kb, int blk, int nblock,
                                                     int nmat, int ntile, T* __restrict__ C,
                                                     const long long* __restrict__ coff, const int* __restrict__ ldc,
                                                     const int* __restrict__ cn, int c0, int transT) {
   typedef typename Mfma<T>::v4 v4;
+  static_assert(BC == 16 || BC == 64, "column tiles of 16 or 64");
+  constexpr int NT = BC / 16;           // 16-column MFMA tiles
+  constexpr int CPT = 64 * BC / kBlock;   // elements of a 64-row C chunk per thread
   const int id = blockIdx.x;
   const int b = (id % 8) + 8 * ((id / 8) / ntile);
   const int tile = (id / 8) % ntile;
@@ -509,26 +514,31 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   const QRDesc d = desc[b];
   if (kb >= d.nrefl) return;
   const int bw = min(kBB, d.nrefl - kb);
-  const int cbeg = c0 + tile * kBC;
+  const int cbeg = c0 + tile * BC;
   const int ctot = cn[b];
   if (cbeg >= ctot) return;
-  const int ncol = min(kBC, ctot - cbeg);
+  const int ncol = min(BC, ctot - cbeg);
   const int L = ldc[b];
   const T* Am = A + d.off;
   T* Cm = C + coff[b];
   __shared__ T Vs[64][kBB + 1];      // V chunk, later T
-  __shared__ T Cs[64][kBC + 1];      // C chunk, later W
+  __shared__ T Cs[64][BC + 1];       // C chunk, later W
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // ---- W = V^T C: wave wv forms rows 16 wv .. 16 wv + 15 of W (4 tiles of 16 columns)
-  v4 acc[4];
+  // ---- W = V^T C: wave wv forms rows 16 wv .. 16 wv + 15 of W (NT tiles of 16 columns)
+  v4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = v4{0, 0, 0, 0};
-  T vv[16], cc[16];
+  for (int t = 0; t < NT; ++t) acc[t] = v4{0, 0, 0, 0};
+  T vv[16], cc[CPT];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = threadIdx.x + u * kBlock;
     const int row = kb + e % 64, c = e / 64;
     vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    const int row = kb + e % 64, c = e / 64;
     cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
   }
   for (int r0 = kb; r0 < d.m;) {
@@ -537,6 +547,10 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
     for (int u = 0; u < 16; ++u) {
       const int e = threadIdx.x + u * kBlock;
       Vs[e % 64][e / 64] = vv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + u * kBlock;
       Cs[e % 64][e / 64] = cc[u];
     }
     __syncthreads();
@@ -546,6 +560,11 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
         const int e = threadIdx.x + u * kBlock;
         const int row = rn + e % 64, c = e / 64;
         vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int e = threadIdx.x + u * kBlock;
+        const int row = rn + e % 64, c = e / 64;
         cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
       }
     }
@@ -554,7 +573,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       const int rr = ks * 4 + (lane >> 4);
       const T av = Vs[rr][16 * wv + (lane & 15)];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mma(av, Cs[rr][16 * t + (lane & 15)], acc[t]);
+      for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mma(av, Cs[rr][16 * t + (lane & 15)], acc[t]);
     }
     __syncthreads();
     r0 = rn;
@@ -564,42 +583,41 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   for (int v = 0; v < 4; ++v) {
     const int i = 16 * wv + Mfma<T>::drow(lane, v);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Cs[i][16 * t + (lane & 15)] = acc[t][v];
+    for (int t = 0; t < NT; ++t) Cs[i][16 * t + (lane & 15)] = acc[t][v];
   }
   const T* Tin = Tbig + ((long long)b * nblock + blk) * kBB * kBB;
   for (int e = threadIdx.x; e < kBB * kBB; e += kBlock) Vs[e / kBB][e % kBB] = Tin[e];
   __syncthreads();
   // ---- W <- -T^T W (Q^T) or -T W (Q) on the matrix cores: wave wv forms
-  //      rows 16 wv .. 16 wv + 15 (4 tiles of 16 columns); the zero triangle
-  //      of T is multiplied too (64 products per wave, as one row chunk of
-  //      V^T C)
+  //      rows 16 wv .. 16 wv + 15 (NT tiles of 16 columns); the zero
+  //      triangle of T is multiplied too (as one row chunk of V^T C)
   {
-    v4 tacc[4];
+    v4 tacc[NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) tacc[t] = v4{0, 0, 0, 0};
+    for (int t = 0; t < NT; ++t) tacc[t] = v4{0, 0, 0, 0};
 #pragma unroll 4
     for (int ks = 0; ks < 16; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
       const T av = transT ? Vs[kk][16 * wv + (lane & 15)] : Vs[16 * wv + (lane & 15)][kk];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) tacc[t] = Mfma<T>::mma(av, Cs[kk][16 * t + (lane & 15)], tacc[t]);
+      for (int t = 0; t < NT; ++t) tacc[t] = Mfma<T>::mma(av, Cs[kk][16 * t + (lane & 15)], tacc[t]);
     }
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = 16 * wv + Mfma<T>::drow(lane, v);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) Cs[i][16 * t + (lane & 15)] = -tacc[t][v];
+      for (int t = 0; t < NT; ++t) Cs[i][16 * t + (lane & 15)] = -tacc[t][v];
     }
   }
   __syncthreads();
   // ---- C <- C + V W for 16-row blocks (rows along the lanes)
   // loads of the next 16-row block are issued before the products of this one
-  T cn_[16], bn_[16];
+  T cn_[4 * NT], bn_[16];
   auto load_rows = [&](int rb) {
     const int row = rb + (lane & 15);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * t + Mfma<T>::drow(lane, v);
@@ -616,10 +634,10 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   if (rb < d.m) load_rows(rb);
   for (; rb < d.m; rb = next_rb(rb)) {
     const int row = rb + (lane & 15);
-    v4 cacc[4];
+    v4 cacc[NT];
     T bv[16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) cacc[t][v] = cn_[4 * t + v];
 #pragma unroll
@@ -629,10 +647,10 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
     for (int ks = 0; ks < 16; ++ks) {
       const int jj = ks * 4 + (lane >> 4);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) cacc[t] = Mfma<T>::mma(Cs[jj][16 * t + (lane & 15)], bv[ks], cacc[t]);
+      for (int t = 0; t < NT; ++t) cacc[t] = Mfma<T>::mma(Cs[jj][16 * t + (lane & 15)], bv[ks], cacc[t]);
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * t + Mfma<T>::drow(lane, v);
