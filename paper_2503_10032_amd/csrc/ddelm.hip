@@ -1696,6 +1696,26 @@ void launch_apply_narrow(ddelm_ctx c, const QRDesc* desc, const T* A, const T* T
   HIPCHK(hipGetLastError());
 }
 
+// Right-hand sides per workgroup for the kernels that stage a block of them
+// in LDS (per_rhs doubles each, the matrix read once per block): the largest
+// power of two up to 16 (and up to nrhs) whose block fits in 56 KiB.
+inline int rhs_group(int nrhs, size_t per_rhs) {
+  int P = 1;
+  while (P < 16 && P < nrhs && per_rhs * 2 * P * sizeof(double) <= ((size_t)56 << 10)) P *= 2;
+  return P;
+}
+// f(std::integral_constant<int, P>()) for P in {1, 2, 4, 8, 16}
+template <typename Fn>
+void with_rhs_group(int P, Fn&& f) {
+  switch (P) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    default: f(std::integral_constant<int, 16>()); break;
+  }
+}
+
 // Q^T (transT = 1) or Q (transT = 0) of one set of N matrices applied to the
 // local vectors F (rows 0..d.m-1 of every subdomain's block).
 template <typename T>
@@ -1755,10 +1775,13 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   c->mark(5);
   // ---- Q^T f (block reflectors), projections, K^+ f, fluxes
   apply_q_local<T>(c, nrhs, 1, s);
-  k_rhs_proj<T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p,
-                                                                   c->offQG_d.p, L.QG.p, c->offm_d.p, c->summ, L.F.p,
-                                                                   c->sumP, c->sumD, fGP, fGD, c->rho_loc.p,
-                                                                   c->s_loc.p);
+  const int PM = rhs_group(nrhs, M);   // right-hand sides per workgroup with M values each in LDS
+  with_rhs_group(PM, [&](auto kp) {
+    constexpr int P = decltype(kp)::value;
+    k_rhs_proj<T, P><<<dim3(N, ceil_div(nrhs, P)), kBlock, (size_t)M * P * sizeof(double), s>>>(
+        M, nrhs, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offQG_d.p, L.QG.p, c->offm_d.p, c->summ, L.F.p, c->sumP,
+        c->sumD, fGP, fGD, c->rho_loc.p, c->s_loc.p);
+  });
   HIPCHK(hipGetLastError());
   {
     const size_t smt = (size_t)M * kTRSMC * sizeof(T);
@@ -1767,9 +1790,12 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
                                                                    cnM, 0);
     HIPCHK(hipGetLastError());
 
-    k_rhs_flux<T, T><<<dim3(N, nrhs), kBlock, M * sizeof(double), s>>>(
-          M, c->nD, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
+    with_rhs_group(PM, [&](auto kp) {
+      constexpr int P = decltype(kp)::value;
+      k_rhs_flux<T, T, P><<<dim3(N, ceil_div(nrhs, P)), kBlock, (size_t)M * P * sizeof(double), s>>>(
+          M, c->nD, nrhs, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->dl_l2g.p, c->dl_own_ptr.p, c->dl_own_slot.p,
           c->offAm_d.p, L.Am.p, c->offm_d.p, c->summ, L.F.p, c->sumP, c->sumD, hD, c->psi_loc.p, c->l_loc.p);
+    });
     HIPCHK(hipGetLastError());
   }
   // ---- b of eq. nn-mixed
@@ -1804,10 +1830,16 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
     k_mu_pi<<<ceil_div(c->nP * nrhs, kBlock), kBlock, 0, s>>>(c->nP, nrhs, c->pif.p, c->c1.p, c->pif.p);
     HIPCHK(hipGetLastError());
   }
-  k_recover<T><<<dim3(N, nrhs), kBlock, (size_t)std::max(c->geo.max_nG, 1) * sizeof(double), s>>>(
-      M, c->nP, c->nD, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->qrdesc.p, L.qrA.p, c->offm_d.p, c->summ,
-      L.F.p, c->pif.p, c->cg_x.p, N, coef, accumulate);
-  HIPCHK(hipGetLastError());
+  {
+    const int mg = std::max(c->geo.max_nG, 1);
+    with_rhs_group(rhs_group(nrhs, mg), [&](auto kp) {
+      constexpr int P = decltype(kp)::value;
+      k_recover<T, P><<<dim3(N, ceil_div(nrhs, P)), kBlock, (size_t)mg * P * sizeof(double), s>>>(
+          M, c->nP, c->nD, nrhs, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->qrdesc.p, L.qrA.p, c->offm_d.p,
+          c->summ, L.F.p, c->pif.p, c->cg_x.p, N, coef, accumulate);
+    });
+    HIPCHK(hipGetLastError());
+  }
   if (mu_pi_out && c->nP > 0)
     HIPCHK(hipMemcpyAsync(mu_pi_out, c->pif.p, (size_t)nrhs * c->nP * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (mu_dl_out && c->nD > 0)
@@ -2393,26 +2425,17 @@ ddelm_status solve_any(ddelm_ctx c, int nrhs, const double* f_I, const double* g
                                             x0);
       acc(o0);
       st.start_rel_res = o0.start_rel;
-      // right-hand sides per residual workgroup: the largest power of two up
-      // to 16 (and up to nrhs) whose coefficient block fits in 56 KiB of LDS
-      int P = 1;
-      while (P < 16 && P < nrhs && (size_t)c->M * 2 * P * sizeof(double) <= (size_t)56 << 10) P *= 2;
+      const int P = rhs_group(nrhs, c->M);   // right-hand sides per residual workgroup
       const size_t shm = (size_t)c->M * P * sizeof(double);
       double prev_worst = 0.0, worst = 0.0;
       for (int step = 0; step < c->opt.refine_maxit; ++step) {
-        const dim3 grid(N, ceil_div(nrhs, P));
-#define RES_ARGS                                                                                                  \
-  c->M, c->nP, c->nD, nrhs, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p, c->offK_d.p,      \
-      c->K64.p, c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N, c->sumP, c->sumD, \
-      c->l64.F.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p
-        switch (P) {
-          case 1: k_residual<1><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
-          case 2: k_residual<2><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
-          case 4: k_residual<4><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
-          case 8: k_residual<8><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
-          default: k_residual<16><<<grid, kBlock, shm, s>>>(RES_ARGS); break;
-        }
-#undef RES_ARGS
+        with_rhs_group(P, [&](auto kp) {
+          constexpr int PP = decltype(kp)::value;
+          k_residual<PP><<<dim3(N, ceil_div(nrhs, PP)), kBlock, shm, s>>>(
+              c->M, c->nP, c->nD, nrhs, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->pi_l2g.p, c->dl_l2g.p,
+              c->offK_d.p, c->K64.p, c->offAm_d.p, c->l64.Am.p, c->offm_d.p, c->summ, c->F64.p, coef, muP.p, muD.p, N,
+              c->sumP, c->sumD, c->l64.F.p, c->fGP.p, c->fGD.p, c->aP.p, c->aD.p);
+        });
         HIPCHK(hipGetLastError());
         if (c->nP + c->nD > 0) {
           k_flux_residual<<<dim3(ceil_div(c->nP + c->nD, kBlock), nrhs), kBlock, 0, s>>>(

@@ -54,93 +54,149 @@ __global__ void k_rhs_split(const int* __restrict__ sizes, const int* __restrict
 
 // p_G = Q_G (Q^T f)[:M];  rho_loc = p_P - f_P (Pi slots), s_loc = p_D - f_D
 // (Delta slots), where f_P, f_D are the interface rows of f before Q^T was
-// applied (fGP, fGD; null when they are zero)
-template <typename T>
-__global__ void k_rhs_proj(int M, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                           const int* __restrict__ dl_off, const long long* __restrict__ offQG,
-                           const T* __restrict__ QG, const long long* __restrict__ offm, long long summ,
-                           const T* __restrict__ F, int sumP, int sumD, const double* __restrict__ fGP,
-                           const double* __restrict__ fGD, double* __restrict__ rho_loc, double* __restrict__ s_loc) {
-  const int i = blockIdx.x, r = blockIdx.y;
+// applied (fGP, fGD; null when they are zero).  One workgroup per
+// (subdomain, group of P right-hand sides), Q_G read once per group.
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_rhs_proj(int M, int nrhs, const int* __restrict__ sizes,
+                                                     const int* __restrict__ pi_off, const int* __restrict__ dl_off,
+                                                     const long long* __restrict__ offQG, const T* __restrict__ QG,
+                                                     const long long* __restrict__ offm, long long summ,
+                                                     const T* __restrict__ F, int sumP, int sumD,
+                                                     const double* __restrict__ fGP, const double* __restrict__ fGD,
+                                                     double* __restrict__ rho_loc, double* __restrict__ s_loc) {
+  const int i = blockIdx.x, r0 = blockIdx.y * P, nr = min(P, nrhs - r0);
   const int ng = sizes[5 * i + 4];
   const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
-  extern __shared__ double al[];
-  const T* Fi = F + (size_t)r * summ + offm[i];
-  for (int k = threadIdx.x; k < M; k += kBlock) al[k] = (double)Fi[k];
+  extern __shared__ double al[];   // [M][P]
+  for (int e = threadIdx.x; e < M * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    al[e] = j < nr ? (double)F[(size_t)(r0 + j) * summ + offm[i] + k] : 0.0;
+  }
   __syncthreads();
+  constexpr int kU = 8;   // elements of Q loaded together per thread
   const T* Q = QG + offQG[i];
   for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += (double)Q[(long long)t * M + k] * al[k];
-    if (t < np) {
-      const size_t e = (size_t)r * sumP + p0 + t;
-      rho_loc[e] = acc - (fGP ? fGP[e] : 0.0);
-    } else {
-      const size_t e = (size_t)r * sumD + d0 + t - np;
-      s_loc[e] = acc - (fGD ? fGD[e] : 0.0);
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    for (int k0 = 0; k0 < M; k0 += kU) {
+      double q[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) q[u] = k0 + u < M ? (double)Q[(long long)t * M + k0 + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k0 + u < M) {
+#pragma unroll
+          for (int j = 0; j < P; ++j) acc[j] += q[u] * al[(k0 + u) * P + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      if (t < np) {
+        const size_t e = (size_t)r * sumP + p0 + t;
+        rho_loc[e] = acc[j] - (fGP ? fGP[e] : 0.0);
+      } else {
+        const size_t e = (size_t)r * sumD + d0 + t - np;
+        s_loc[e] = acc[j] - (fGD ? fGD[e] : 0.0);
+      }
     }
   }
 }
 
 // ad = A_m c_f0;  psi_loc = -ad_P, l_loc = -ad_D (+ h_D at the first owner of
-// each Delta point, so that the owner sum gives h_D - A_D K^+ f)
-template <typename T, typename TA>
-__global__ void k_rhs_flux(int M, int nD, const int* __restrict__ sizes, const int* __restrict__ pi_off,
-                           const int* __restrict__ dl_off, const int* __restrict__ dl_l2g,
-                           const int* __restrict__ dl_own_ptr, const int* __restrict__ dl_own_slot,
-                           const long long* __restrict__ offAm, const TA* __restrict__ Am,
-                           const long long* __restrict__ offm, long long summ, const T* __restrict__ F, int sumP,
-                           int sumD, const double* __restrict__ hD, double* __restrict__ psi_loc,
-                           double* __restrict__ l_loc) {
-  const int i = blockIdx.x, r = blockIdx.y;
+// each Delta point, so that the owner sum gives h_D - A_D K^+ f).  One
+// workgroup per (subdomain, group of P right-hand sides), A_m read once per
+// group.
+template <typename T, typename TA, int P>
+__global__ void __launch_bounds__(kBlock) k_rhs_flux(int M, int nD, int nrhs, const int* __restrict__ sizes,
+                                                     const int* __restrict__ pi_off, const int* __restrict__ dl_off,
+                                                     const int* __restrict__ dl_l2g, const int* __restrict__ dl_own_ptr,
+                                                     const int* __restrict__ dl_own_slot,
+                                                     const long long* __restrict__ offAm, const TA* __restrict__ Am,
+                                                     const long long* __restrict__ offm, long long summ,
+                                                     const T* __restrict__ F, int sumP, int sumD,
+                                                     const double* __restrict__ hD, double* __restrict__ psi_loc,
+                                                     double* __restrict__ l_loc) {
+  const int i = blockIdx.x, r0 = blockIdx.y * P, nr = min(P, nrhs - r0);
   const int ng = sizes[5 * i + 4];
   const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i];
-  extern __shared__ double cf[];
-  const T* Fi = F + (size_t)r * summ + offm[i];
-  for (int k = threadIdx.x; k < M; k += kBlock) cf[k] = (double)Fi[k];
+  extern __shared__ double cf[];   // [M][P]
+  for (int e = threadIdx.x; e < M * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    cf[e] = j < nr ? (double)F[(size_t)(r0 + j) * summ + offm[i] + k] : 0.0;
+  }
   __syncthreads();
   const TA* A = Am + offAm[i];
   for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int k = 0; k < M; ++k) acc += (double)A[(long long)k * ng + t] * cf[k];
-    if (t < np) {
-      psi_loc[(size_t)r * sumP + p0 + t] = -acc;
-    } else {
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double av = (double)A[(long long)k * ng + t];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += av * cf[k * P + j];
+    }
+    int own = 1, g = 0;
+    if (t >= np && hD) {
       const int slot = d0 + t - np;
-      double v = -acc;
-      if (hD) {
-        const int g = dl_l2g[slot];
-        if (dl_own_slot[dl_own_ptr[g]] == slot) v += hD[(size_t)r * nD + g];
+      g = dl_l2g[slot];
+      own = dl_own_slot[dl_own_ptr[g]] == slot;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      if (t < np) {
+        psi_loc[(size_t)r * sumP + p0 + t] = -acc[j];
+      } else {
+        double v = -acc[j];
+        if (hD && own) v += hD[(size_t)r * nD + g];
+        l_loc[(size_t)r * sumD + d0 + t - np] = v;
       }
-      l_loc[(size_t)r * sumD + slot] = v;
     }
   }
 }
 
 // c^i = c_f0 + E [mu_P(Pi^i); mu_D(Delta^i)], E = R^{-1} Q_G^T kept in the K_c
 // matrix (rows 0..M-1 of columns M.., leading dimension m).  accumulate = 1
-// adds the result to coef instead of overwriting it.
-template <typename T>
-__global__ void k_recover(int M, int nP, int nD, const int* __restrict__ pi_off, const int* __restrict__ dl_off,
-                          const int* __restrict__ pi_l2g, const int* __restrict__ dl_l2g,
-                          const QRDesc* __restrict__ desc, const T* __restrict__ qrA,
-                          const long long* __restrict__ offm, long long summ, const T* __restrict__ F,
-                          const double* __restrict__ mu_pi, const double* __restrict__ mu_dl, int N,
-                          double* __restrict__ coef, int accumulate) {
-  const int i = blockIdx.x, r = blockIdx.y;
+// adds the result to coef instead of overwriting it.  One workgroup per
+// (subdomain, group of P right-hand sides), E read once per group.
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_recover(int M, int nP, int nD, int nrhs, const int* __restrict__ pi_off,
+                                                    const int* __restrict__ dl_off, const int* __restrict__ pi_l2g,
+                                                    const int* __restrict__ dl_l2g, const QRDesc* __restrict__ desc,
+                                                    const T* __restrict__ qrA, const long long* __restrict__ offm,
+                                                    long long summ, const T* __restrict__ F,
+                                                    const double* __restrict__ mu_pi, const double* __restrict__ mu_dl,
+                                                    int N, double* __restrict__ coef, int accumulate) {
+  const int i = blockIdx.x, r0 = blockIdx.y * P, nr = min(P, nrhs - r0);
   const int p0 = pi_off[i], np = pi_off[i + 1] - p0, d0 = dl_off[i], nd = dl_off[i + 1] - d0;
-  extern __shared__ double mus[];
-  for (int a = threadIdx.x; a < np + nd; a += kBlock)
-    mus[a] = a < np ? mu_pi[(size_t)r * nP + pi_l2g[p0 + a]] : mu_dl[(size_t)r * nD + dl_l2g[d0 + a - np]];
+  extern __shared__ double mus[];   // [np + nd][P]
+  for (int e = threadIdx.x; e < (np + nd) * P; e += kBlock) {
+    const int a = e / P, j = e % P, r = r0 + j;
+    mus[e] = j >= nr ? 0.0
+                     : (a < np ? mu_pi[(size_t)r * nP + pi_l2g[p0 + a]] : mu_dl[(size_t)r * nD + dl_l2g[d0 + a - np]]);
+  }
   __syncthreads();
   const QRDesc d = desc[i];
   const T* E = qrA + d.off + (long long)M * d.ld;
-  const T* Fi = F + (size_t)r * summ + offm[i];
   for (int k = threadIdx.x; k < M; k += kBlock) {
-    double acc = (double)Fi[k];
-    for (int a = 0; a < np + nd; ++a) acc += (double)E[(long long)a * d.ld + k] * mus[a];
-    const size_t e = ((size_t)r * N + i) * M + k;
-    coef[e] = accumulate ? coef[e] + acc : acc;
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = j < nr ? (double)F[(size_t)(r0 + j) * summ + offm[i] + k] : 0.0;
+    for (int a = 0; a < np + nd; ++a) {
+      const double ev = (double)E[(long long)a * d.ld + k];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += ev * mus[a * P + j];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const size_t e = ((size_t)(r0 + j) * N + i) * M + k;
+      coef[e] = accumulate ? coef[e] + acc[j] : acc[j];
+    }
   }
 }
 
