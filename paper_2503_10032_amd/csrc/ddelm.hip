@@ -682,6 +682,60 @@ size_t local_smem(ddelm_ctx c) {
   return sizeof(double) * (size_t)std::max({c->geo.max_nG, 2 * c->nP, 1});
 }
 
+// Right-hand sides per workgroup for the kernels that stage a block of them
+// in LDS (per_rhs doubles each, the matrix read once per block): the largest
+// power of two up to 16 (and up to nrhs) whose block fits in 56 KiB.
+inline int rhs_group(int nrhs, size_t per_rhs) {
+  int P = 1;
+  while (P < 16 && P < nrhs && per_rhs * 2 * P * sizeof(double) <= ((size_t)56 << 10)) P *= 2;
+  return P;
+}
+// f(std::integral_constant<int, P>()) for P in {1, 2, 4, 8, 16}
+template <typename Fn>
+void with_rhs_group(int P, Fn&& f) {
+  switch (P) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    default: f(std::integral_constant<int, 16>()); break;
+  }
+}
+
+
+// The per-subdomain local stages (kernels_solve.hpp) on groups of P
+// right-hand sides: v -> G, L rows; -N lambda; -N^T (P lambda); eta -> L^T
+// rows.  Each stages its gathered vectors as [point][P] in LDS.
+template <typename T>
+void launch_local_v(ddelm_ctx c, const OpArgs<T>& a, const double* v, int nrhs, hipStream_t s) {
+  const size_t per = (size_t)std::max(c->geo.max_nG, 1);
+  with_rhs_group(rhs_group(nrhs, per), [&](auto kp) {
+    constexpr int P = decltype(kp)::value;
+    k_ph_local_v<T, P><<<dim3(c->N, ceil_div(nrhs, P)), kBlock, per * P * sizeof(double), s>>>(a, v, nrhs);
+  });
+  HIPCHK(hipGetLastError());
+}
+template <typename T>
+void launch_local_N(ddelm_ctx c, const OpArgs<T>& a, int transposed, int nrhs, hipStream_t s) {
+  const size_t per = (size_t)std::max(c->geo.max_nD, 1);
+  with_rhs_group(rhs_group(nrhs, per), [&](auto kp) {
+    constexpr int P = decltype(kp)::value;
+    const dim3 g(c->N, ceil_div(nrhs, P));
+    if (transposed) k_ph_P2<T, P><<<g, kBlock, per * P * sizeof(double), s>>>(a, nrhs);
+    else k_ph_P1<T, P><<<g, kBlock, per * P * sizeof(double), s>>>(a, nrhs);
+  });
+  HIPCHK(hipGetLastError());
+}
+template <typename T>
+void launch_local_eta(ddelm_ctx c, const OpArgs<T>& a, int nrhs, hipStream_t s) {
+  const size_t per = (size_t)std::max(c->geo.max_nD, 1);
+  with_rhs_group(rhs_group(nrhs, per), [&](auto kp) {
+    constexpr int P = decltype(kp)::value;
+    k_ph_eta<T, P><<<dim3(c->N, ceil_div(nrhs, P)), kBlock, per * P * sizeof(double), s>>>(a, nrhs);
+  });
+  HIPCHK(hipGetLastError());
+}
+
 // --------------------------------------------------------------- solve workspaces
 
 // The solve workspace for nrhs right-hand sides: every buffer with its
@@ -867,12 +921,10 @@ void run_phases_after_stage1(ddelm_ctx c, OpArgs<T>& a, int nrhs, const double* 
   k_ph_lam<T><<<gl, kBlock, 0, s>>>(a);
   HIPCHK(hipGetLastError());
   if (a.theta != 0.0) {
-    k_ph_P1<T><<<gl, kBlock, sm, s>>>(a);
-    k_ph_P2<T><<<gl, kBlock, sm, s>>>(a);
-    HIPCHK(hipGetLastError());
+    launch_local_N<T>(c, a, 0, nrhs, s);
+    launch_local_N<T>(c, a, 1, nrhs, s);
   }
-  k_ph_eta<T><<<gl, kBlock, sm, s>>>(a);
-  HIPCHK(hipGetLastError());
+  launch_local_eta<T>(c, a, nrhs, s);
   if (c->nP > 0) {
     k_ph_coarse2<T><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
     HIPCHK(hipGetLastError());
@@ -907,7 +959,7 @@ void cg_multilaunch(ddelm_ctx c, int nrhs, double tol) {
   while (it < c->opt.maxit) {
     const int nstep = std::min(check_every, c->opt.maxit - it);
     for (int k = 0; k < nstep; ++k) {
-      k_ph_local_v<T><<<dim3(c->N, nrhs), kBlock, sm, s>>>(a, st.p);
+      launch_local_v<T>(c, a, st.p, nrhs, s);
       run_phases_after_stage1<T>(c, a, nrhs, nullptr);
       k_cg_wdot<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, st);
       k_cg_alpha<<<nrhs, kBlock, 0, s>>>(st);
@@ -1607,8 +1659,7 @@ void run_cg(ddelm_ctx c, int nrhs, double tol, CoreOut& res) {
 void apply_s_theta64(ddelm_ctx c, int nrhs, const double* v, double* out) {
   hipStream_t s = c->stream;
   OpArgs<double> a = op_args<double>(c, nrhs);
-  k_ph_local_v<double><<<dim3(c->N, nrhs), kBlock, local_smem(c), s>>>(a, v);
-  HIPCHK(hipGetLastError());
+  launch_local_v<double>(c, a, v, nrhs, s);
   run_phases_after_stage1<double>(c, a, nrhs, nullptr);
   k_ph_sum_w<double><<<dim3(ceil_div(c->nD, kBlock), nrhs), kBlock, 0, s>>>(a, out);
   HIPCHK(hipGetLastError());
@@ -1694,26 +1745,6 @@ void launch_apply_narrow(ddelm_ctx c, const QRDesc* desc, const T* A, const T* T
   k_qr_apply_narrow<T, NR><<<c->N, an_threads(NR), smem, s>>>(desc, A, Tbig, c->nblock, L.F.p, c->f_off.p,
                                                               c->f_ld.p, nrhs, transT);
   HIPCHK(hipGetLastError());
-}
-
-// Right-hand sides per workgroup for the kernels that stage a block of them
-// in LDS (per_rhs doubles each, the matrix read once per block): the largest
-// power of two up to 16 (and up to nrhs) whose block fits in 56 KiB.
-inline int rhs_group(int nrhs, size_t per_rhs) {
-  int P = 1;
-  while (P < 16 && P < nrhs && per_rhs * 2 * P * sizeof(double) <= ((size_t)56 << 10)) P *= 2;
-  return P;
-}
-// f(std::integral_constant<int, P>()) for P in {1, 2, 4, 8, 16}
-template <typename Fn>
-void with_rhs_group(int P, Fn&& f) {
-  switch (P) {
-    case 1: f(std::integral_constant<int, 1>()); break;
-    case 2: f(std::integral_constant<int, 2>()); break;
-    case 4: f(std::integral_constant<int, 4>()); break;
-    case 8: f(std::integral_constant<int, 8>()); break;
-    default: f(std::integral_constant<int, 16>()); break;
-  }
 }
 
 // Q^T (transT = 1) or Q (transT = 0) of one set of N matrices applied to the
@@ -1821,7 +1852,7 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   if (c->nP > 0) {
     if (c->nD > 0) {
       const size_t sm = local_smem(c);
-      k_ph_local_v<T><<<dim3(N, nrhs), kBlock, sm, s>>>(a, c->cg_x.p);
+      launch_local_v<T>(c, a, c->cg_x.p, nrhs, s);
       k_ph_coarse1<T><<<dim3(ceil_div(2 * c->nP, kBlock), nrhs), kBlock, sm, s>>>(a);
       HIPCHK(hipGetLastError());
     } else {
@@ -1969,8 +2000,8 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
   if (nD > 0) {
     k_adj_A2<T><<<gl, kBlock, 0, s>>>(a, c->adj_etaD.p, c->adj_nu.p);
     if (a.theta != 0.0) {
-      k_ph_P1<T><<<gl, kBlock, sm, s>>>(a);
-      k_ph_P2<T><<<gl, kBlock, sm, s>>>(a);
+      launch_local_N<T>(c, a, 0, nrhs, s);
+      launch_local_N<T>(c, a, 1, nrhs, s);
     }
     k_adj_A3<T><<<gl, kBlock, sm, s>>>(a, c->adj_lbar.p, c->adj_mloc.p);
     k_adj_hD<T><<<gD, kBlock, 0, s>>>(a, hbD);

@@ -59,31 +59,50 @@ struct OpArgs {
 };
 
 // LDS needed by the local phases: 2 * max n_G doubles + reductions.
+// The local stages below take the right-hand sides r0 .. r0 + nr - 1 (nr <=
+// P) of one subdomain i together: the gathered vectors sit in LDS as
+// [point][P], so every element of a local operator read from memory serves
+// all of them.
+
 // ---------------------------------------------------------------- stage 1
 // s = G_DD v_i, l = L_DD v_i (Delta slots), rho = G_PD v_i, psi = L_PD v_i (Pi slots).
-template <typename T>
-__device__ void ph_local_v(const OpArgs<T>& a, const double* __restrict__ v, int i, int r, double* sm) {
+template <typename T, int P>
+__device__ void ph_local_v(const OpArgs<T>& a, const double* __restrict__ v, int i, int r0, int nr, double* sm) {
   const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
   const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
   const int ng = np + nd;
   double* vs = sm;
-  for (int k = threadIdx.x; k < nd; k += kBlock) vs[k] = v[(size_t)r * a.nD + a.dl_l2g[d0 + k]];
+  for (int e = threadIdx.x; e < nd * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    vs[e] = j < nr ? v[(size_t)(r0 + j) * a.nD + a.dl_l2g[d0 + k]] : 0.0;
+  }
   __syncthreads();
   const T* G = a.Gm + a.offG[i];
   const T* L = a.Lm + a.offG[i];
   for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double sg = 0.0, sl = 0.0;
+    double sg[P], sl[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) sg[j] = sl[j] = 0.0;
     for (int b = 0; b < nd; ++b) {
       const long long e = (long long)(np + b) * ng + t;
-      sg += (double)G[e] * vs[b];
-      sl += (double)L[e] * vs[b];
+      const double g = (double)G[e], l = (double)L[e];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        sg[j] += g * vs[b * P + j];
+        sl[j] += l * vs[b * P + j];
+      }
     }
-    if (t < np) {
-      a.rho_loc[(size_t)r * a.sumP + p0 + t] = sg;
-      a.psi_loc[(size_t)r * a.sumP + p0 + t] = sl;
-    } else {
-      a.s_loc[(size_t)r * a.sumD + d0 + t - np] = sg;
-      a.l_loc[(size_t)r * a.sumD + d0 + t - np] = sl;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      if (t < np) {
+        a.rho_loc[(size_t)r * a.sumP + p0 + t] = sg[j];
+        a.psi_loc[(size_t)r * a.sumP + p0 + t] = sl[j];
+      } else {
+        a.s_loc[(size_t)r * a.sumD + d0 + t - np] = sg[j];
+        a.l_loc[(size_t)r * a.sumD + d0 + t - np] = sl[j];
+      }
     }
   }
   __syncthreads();
@@ -143,36 +162,34 @@ __device__ __forceinline__ double dl_sum(const int* __restrict__ own_ptr, const 
   return s;
 }
 
-// ---------------------------------------------------------------- stage 4: y = -N_i lambda_i
-template <typename T>
-__device__ void ph_local_P1(const OpArgs<T>& a, int i, int r, double* sm) {
+// ---------------------------------------------------------------- stages 4 and 5
+// out = -B_i (sum over owners of src at the Delta points of i):
+//   y = -N_i lambda_i (B = N, src = lam_loc) and z = -N_i^T (P lambda)_i (B = N^T, src = y_loc)
+template <typename T, int P>
+__device__ void ph_local_N(const OpArgs<T>& a, const T* __restrict__ B, const double* __restrict__ src,
+                           double* __restrict__ out, int i, int r0, int nr, double* sm) {
   const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
   double* ls = sm;
-  const double* lam = a.lam_loc + (size_t)r * a.sumD;
-  for (int k = threadIdx.x; k < nd; k += kBlock) ls[k] = dl_sum(a.dl_own_ptr, a.dl_own_slot, lam, a.dl_l2g[d0 + k]);
-  __syncthreads();
-  const T* Nm = a.Nm + a.offN[i];
-  for (int t = threadIdx.x; t < nd; t += kBlock) {
-    double acc = 0.0;
-    for (int b = 0; b < nd; ++b) acc += (double)Nm[(long long)b * nd + t] * ls[b];
-    a.y_loc[(size_t)r * a.sumD + d0 + t] = -acc;
+  for (int e = threadIdx.x; e < nd * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    ls[e] = j < nr ? dl_sum(a.dl_own_ptr, a.dl_own_slot, src + (size_t)(r0 + j) * a.sumD, a.dl_l2g[d0 + k]) : 0.0;
   }
   __syncthreads();
-}
-
-// ---------------------------------------------------------------- stage 5: z = -N_i^T (P lambda)_i
-template <typename T>
-__device__ void ph_local_P2(const OpArgs<T>& a, int i, int r, double* sm) {
-  const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
-  double* qs = sm;
-  const double* y = a.y_loc + (size_t)r * a.sumD;
-  for (int k = threadIdx.x; k < nd; k += kBlock) qs[k] = dl_sum(a.dl_own_ptr, a.dl_own_slot, y, a.dl_l2g[d0 + k]);
-  __syncthreads();
-  const T* NT = a.NTm + a.offN[i];
+  const T* Bi = B + a.offN[i];
   for (int t = threadIdx.x; t < nd; t += kBlock) {
-    double acc = 0.0;
-    for (int b = 0; b < nd; ++b) acc += (double)NT[(long long)b * nd + t] * qs[b];
-    a.z_loc[(size_t)r * a.sumD + d0 + t] = -acc;
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    for (int b = 0; b < nd; ++b) {
+      const double m = (double)Bi[(long long)b * nd + t];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += m * ls[b * P + j];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      out[(size_t)(r0 + j) * a.sumD + d0 + t] = -acc[j];
+    }
   }
   __syncthreads();
 }
@@ -181,31 +198,45 @@ __device__ void ph_local_P2(const OpArgs<T>& a, int i, int r, double* sm) {
 // eta = theta P^T P lambda + (1-theta) lambda at the Delta points of i;
 // nu_loc = L_DP^T eta (Pi slots), t = L_DD^T eta (Delta slots).
 // With theta == 0 the Neumann-Neumann stages are skipped and eta = lambda.
-template <typename T>
-__device__ void ph_local_eta(const OpArgs<T>& a, int i, int r, double* sm) {
+template <typename T, int P>
+__device__ void ph_local_eta(const OpArgs<T>& a, int i, int r0, int nr, double* sm) {
   const int p0 = a.pi_off[i], np = a.pi_off[i + 1] - p0;
   const int d0 = a.dl_off[i], nd = a.dl_off[i + 1] - d0;
   const int ng = np + nd;
   double* es = sm;
-  const double* lam = a.lam_loc + (size_t)r * a.sumD;
-  const double* z = a.z_loc + (size_t)r * a.sumD;
-  for (int k = threadIdx.x; k < nd; k += kBlock) {
-    const int g = a.dl_l2g[d0 + k];
-    const double l = dl_sum(a.dl_own_ptr, a.dl_own_slot, lam, g);
-    if (a.theta != 0.0) {
-      const double pp = dl_sum(a.dl_own_ptr, a.dl_own_slot, z, g);
-      es[k] = a.theta * pp + (1.0 - a.theta) * l;
-    } else {
-      es[k] = l;
+  for (int e = threadIdx.x; e < nd * P; e += kBlock) {
+    const int k = e / P, j = e % P;
+    double val = 0.0;
+    if (j < nr) {
+      const int g = a.dl_l2g[d0 + k];
+      const double l = dl_sum(a.dl_own_ptr, a.dl_own_slot, a.lam_loc + (size_t)(r0 + j) * a.sumD, g);
+      if (a.theta != 0.0) {
+        const double pp = dl_sum(a.dl_own_ptr, a.dl_own_slot, a.z_loc + (size_t)(r0 + j) * a.sumD, g);
+        val = a.theta * pp + (1.0 - a.theta) * l;
+      } else {
+        val = l;
+      }
     }
+    es[e] = val;
   }
   __syncthreads();
   const T* LT = a.LTm + a.offG[i];
   for (int t = threadIdx.x; t < ng; t += kBlock) {
-    double acc = 0.0;
-    for (int b = 0; b < nd; ++b) acc += (double)LT[(long long)(np + b) * ng + t] * es[b];
-    if (t < np) a.nu_loc[(size_t)r * a.sumP + p0 + t] = acc;
-    else a.t_loc[(size_t)r * a.sumD + d0 + t - np] = acc;
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
+    for (int b = 0; b < nd; ++b) {
+      const double m = (double)LT[(long long)(np + b) * ng + t];
+#pragma unroll
+      for (int j = 0; j < P; ++j) acc[j] += m * es[b * P + j];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (j >= nr) break;
+      const int r = r0 + j;
+      if (t < np) a.nu_loc[(size_t)r * a.sumP + p0 + t] = acc[j];
+      else a.t_loc[(size_t)r * a.sumD + d0 + t - np] = acc[j];
+    }
   }
   __syncthreads();
 }
@@ -233,10 +264,12 @@ __device__ void ph_local_w(const OpArgs<T>& a, int i, int r) {
 }
 
 // ---------------------------------------------------------------- phase kernels (one launch each)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ph_local_v(OpArgs<T> a, const double* __restrict__ v) {
+// Launched on (N, ceil(nrhs / P)) workgroups with P * (max n_G or 2 nP) doubles of LDS.
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_ph_local_v(OpArgs<T> a, const double* __restrict__ v, int nrhs) {
   extern __shared__ double sm[];
-  ph_local_v(a, v, blockIdx.x, blockIdx.y, sm);
+  const int r0 = blockIdx.y * P;
+  ph_local_v<T, P>(a, v, blockIdx.x, r0, min(P, nrhs - r0), sm);
 }
 
 template <typename T>
@@ -249,22 +282,25 @@ __global__ void __launch_bounds__(kBlock) k_ph_coarse1(OpArgs<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_ph_lam(OpArgs<T> a) { ph_local_lam(a, blockIdx.x, blockIdx.y); }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ph_P1(OpArgs<T> a) {
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_ph_P1(OpArgs<T> a, int nrhs) {
   extern __shared__ double sm[];
-  ph_local_P1(a, blockIdx.x, blockIdx.y, sm);
+  const int r0 = blockIdx.y * P;
+  ph_local_N<T, P>(a, a.Nm, a.lam_loc, a.y_loc, blockIdx.x, r0, min(P, nrhs - r0), sm);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ph_P2(OpArgs<T> a) {
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_ph_P2(OpArgs<T> a, int nrhs) {
   extern __shared__ double sm[];
-  ph_local_P2(a, blockIdx.x, blockIdx.y, sm);
+  const int r0 = blockIdx.y * P;
+  ph_local_N<T, P>(a, a.NTm, a.y_loc, a.z_loc, blockIdx.x, r0, min(P, nrhs - r0), sm);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ph_eta(OpArgs<T> a) {
+template <typename T, int P>
+__global__ void __launch_bounds__(kBlock) k_ph_eta(OpArgs<T> a, int nrhs) {
   extern __shared__ double sm[];
-  ph_local_eta(a, blockIdx.x, blockIdx.y, sm);
+  const int r0 = blockIdx.y * P;
+  ph_local_eta<T, P>(a, blockIdx.x, r0, min(P, nrhs - r0), sm);
 }
 
 template <typename T>
