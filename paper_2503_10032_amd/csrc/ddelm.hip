@@ -1585,7 +1585,8 @@ void factor_impl(ddelm_ctx c) {
       HIPCHK(hipStreamSynchronize(s));
     }
     const size_t smi = (size_t)n * 4 * sizeof(double);
-    if (smi > 160 * 1024) c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
+    if (smi + sizeof(double) * kIB * (kIB + 1) > 160 * 1024)
+      c->fail(DDELM_E_SHAPE, "coarse problem too large for the inverse kernel");
     if (smi > 65536) HIPCHK(hipFuncSetAttribute((const void*)k_chol_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smi));
     k_chol_inverse<<<ceil_div(n, 4), kBlock, smi, s>>>(c->Sfac.p, n, c->Sinv.p);
     HIPCHK(hipGetLastError());

@@ -493,34 +493,75 @@ __global__ void __launch_bounds__(kBlock) k_chol_panel(double* __restrict__ S, i
 }
 
 // Columns of S^{-1} from the Cholesky factor (lower, column-major):
-// solve L y = e_k then L^T x = y; 4 columns per workgroup, in LDS.
+// solve L y = e_k then L^T x = y; 4 columns per workgroup, in LDS.  Both
+// substitutions go by blocks of kIB rows: the block's triangle is staged in
+// LDS and solved by four threads (one column each, the block's unknowns in
+// registers), then every thread updates one (row, column) of the rest with
+// the block's kIB solved values: three barriers per block instead of two
+// per row.
+constexpr int kIB = 32;
 __global__ void __launch_bounds__(kBlock) k_chol_inverse(const double* __restrict__ Lf, int n,
                                                          double* __restrict__ Sinv) {
   extern __shared__ unsigned char smem_raw[];
   double* x = reinterpret_cast<double*>(smem_raw);   // [n][4]
+  __shared__ double Lb[kIB][kIB + 1];                // Lb[i][j] = L(kb + i, kb + j)
   const int c0 = blockIdx.x * 4;
   for (int e = threadIdx.x; e < n * 4; e += kBlock) {
     const int r = e / 4, c = e % 4;
     x[e] = (r == c0 + c) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {      // forward: L y = e
-    if (threadIdx.x < 4) x[k * 4 + threadIdx.x] /= Lf[(long long)k * n + k];
-    __syncthreads();
-    for (int e = (k + 1) * 4 + threadIdx.x; e < n * 4; e += kBlock) {
-      const int r = e / 4, c = e % 4;
-      x[e] -= Lf[(long long)k * n + r] * x[k * 4 + c];
+  const int nblk = (n + kIB - 1) / kIB;
+  for (int pass = 0; pass < 2; ++pass) {          // 0: L y = e, 1: L^T x = y
+    for (int q = 0; q < nblk; ++q) {
+      const int bk = pass == 0 ? q : nblk - 1 - q;
+      const int kb = bk * kIB, nb = min(kIB, n - kb);
+      for (int e = threadIdx.x; e < kIB * kIB; e += kBlock) {
+        const int i = e % kIB, j = e / kIB;
+        Lb[i][j] = (i < nb && j < nb) ? Lf[(long long)(kb + j) * n + kb + i] : 0.0;
+      }
+      __syncthreads();
+      if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        double xr[kIB];
+#pragma unroll
+        for (int k = 0; k < kIB; ++k) xr[k] = k < nb ? x[(kb + k) * 4 + c] : 0.0;
+        if (pass == 0) {
+#pragma unroll
+          for (int k = 0; k < kIB; ++k) {
+            if (k < nb) {
+              xr[k] /= Lb[k][k];
+#pragma unroll
+              for (int r = k + 1; r < kIB; ++r) xr[r] -= Lb[r][k] * xr[k];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = kIB - 1; k >= 0; --k) {
+            if (k < nb) {
+              xr[k] /= Lb[k][k];
+#pragma unroll
+              for (int r = 0; r < k; ++r) xr[r] -= Lb[k][r] * xr[k];
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kIB; ++k)
+          if (k < nb) x[(kb + k) * 4 + c] = xr[k];
+      }
+      __syncthreads();
+      // rows below the block (forward) or above it (backward)
+      const int u0 = pass == 0 ? kb + nb : 0, u1 = pass == 0 ? n : kb;
+      for (int e = u0 * 4 + threadIdx.x; e < u1 * 4; e += kBlock) {
+        const int r = e / 4, c = e % 4;
+        double acc = x[e];
+        for (int k = 0; k < nb; ++k) {
+          const double l = pass == 0 ? Lf[(long long)(kb + k) * n + r] : Lf[(long long)r * n + kb + k];
+          acc -= l * x[(kb + k) * 4 + c];
+        }
+        x[e] = acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {   // backward: L^T x = y
-    if (threadIdx.x < 4) x[k * 4 + threadIdx.x] /= Lf[(long long)k * n + k];
-    __syncthreads();
-    for (int e = threadIdx.x; e < k * 4; e += kBlock) {
-      const int r = e / 4, c = e % 4;
-      x[e] -= Lf[(long long)r * n + k] * x[k * 4 + c];
-    }
-    __syncthreads();
   }
   for (int e = threadIdx.x; e < n * 4; e += kBlock) {
     const int r = e / 4, c = e % 4;
