@@ -48,10 +48,10 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "f32cg": 2}
 # below) and for the workload named; otherwise the bench reports null.
 CG_SOURCES = ("kernels_cg.hpp", "kernels_solve.hpp", "kernels_common.hpp")
 CG_TRAFFIC = {
-    ("large", "fp64"): dict(fetch_kib=193906726.6875, write_kib=55986124.9375, fetch_scale=0.5, write_scale=1.0,
-                            sha256="3042a8d4dfad47ab03cd56cba2d88de01ab279c28b5c0e0af45bd56b73713d05"),
-    ("medium", "fp64"): dict(fetch_kib=1448168.3, write_kib=49408.6, fetch_scale=0.5, write_scale=1.0,
-                             sha256="3042a8d4dfad47ab03cd56cba2d88de01ab279c28b5c0e0af45bd56b73713d05"),
+    ("large", "fp64"): dict(fetch_kib=193915486.4, write_kib=56009999.5, fetch_scale=0.5, write_scale=1.0,
+                            sha256="5ec49a76e5efeaaec9be3560ce59b2087caf083144dfcbd0d7cbe7fd572511bf"),
+    ("medium", "fp64"): dict(fetch_kib=1448269.2, write_kib=53905.8, fetch_scale=0.5, write_scale=1.0,
+                             sha256="5ec49a76e5efeaaec9be3560ce59b2087caf083144dfcbd0d7cbe7fd572511bf"),
 }
 
 
