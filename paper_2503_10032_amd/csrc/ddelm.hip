@@ -1192,6 +1192,19 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
     // same columns before it; the two updates of one block touch disjoint
     // columns and read only that block's reflectors and T factor.
     const int nmat8 = ceil_div(nmat, 8) * 8;
+    // block-reflector updates address a matrix by 32-bit byte offsets when
+    // every matrix of the set is under 2^31 bytes
+    bool off32 = true;
+    for (const QRDesc& d : *q.h) off32 = off32 && (long long)d.ld * d.ncols * (long long)sizeof(T) < (1LL << 31);
+    auto update = [&](int kb, int blk, int ntile, hipStream_t st, const int* cend, int cfirst) {
+      if (off32)
+        k_qr_wy64<T, kBC, true><<<nmat8 * ntile, kBlock, 0, st>>>(q.desc, q.A, q.Tbig->p, kb, blk,
+                                                                  c->nblock, nmat, ntile, q.A, q.coff, q.ldc, cend,
+                                                                  cfirst, 1);
+      else
+        k_qr_wy64<T><<<nmat8 * ntile, kBlock, 0, st>>>(q.desc, q.A, q.Tbig->p, kb, blk, c->nblock, nmat, ntile,
+                                                       q.A, q.coff, q.ldc, cend, cfirst, 1);
+    };
     hipStream_t s2 = c->side_stream();
     HIPCHK(hipEventRecord(c->sev(0), s));
     HIPCHK(hipStreamWaitEvent(s2, c->sev(0), 0));
@@ -1233,8 +1246,7 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
         if (blk > 0) HIPCHK(hipStreamWaitEvent(s, evR(blk - 1), 0));
         const int* cnn = cn_dev + (size_t)(2 * blk + 1) * nmat;   // = c1
         const int ntn = ceil_div(c1 - c0, kBC);
-        k_qr_wy64<T><<<nmat8 * ntn, kBlock, 0, s>>>(q.desc, q.A, q.Tbig->p, kb, blk, c->nblock, nmat, ntn, q.A,
-                                                    q.coff, q.ldc, cnn, c0, 1);
+        update(kb, blk, ntn, s, cnn, c0);
         HIPCHK(hipGetLastError());
       }
       // far update: every column after the next block (and the appended unit
@@ -1242,8 +1254,7 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
       const int ntf = ceil_div(q.max_ncols - c1, kBC);
       HIPCHK(hipStreamWaitEvent(s2, evT(blk), 0));
       if (ntf > 0) {
-        k_qr_wy64<T><<<nmat8 * ntf, kBlock, 0, s2>>>(q.desc, q.A, q.Tbig->p, kb, blk, c->nblock, nmat, ntf, q.A,
-                                                     q.coff, q.ldc, q.cn, c1, 1);
+        update(kb, blk, ntf, s2, q.cn, c1);
         HIPCHK(hipGetLastError());
       }
       HIPCHK(hipEventRecord(evR(blk), s2));
@@ -1758,16 +1769,24 @@ void apply_q_set(ddelm_ctx c, const QRDesc* desc, const T* A, const T* Tbig, int
   LocalBufs<T>& L = c->lb<T>();
   const int N = c->N;
   const int* cnR = c->arena.put(std::vector<int>(N, nrhs), s);
+  // 32-bit byte offsets when a subdomain's block of F (nrhs columns of
+  // leading dimension summ) and every QR matrix are under 2^31 bytes
+  bool off32 = (long long)c->summ * nrhs * (long long)sizeof(T) < (1LL << 31);
+  for (const QRDesc& d : c->h_qrdesc) off32 = off32 && (long long)d.ld * d.ncols * (long long)sizeof(T) < (1LL << 31);
+  for (const QRDesc& d : c->h_topdesc) off32 = off32 && (long long)d.ld * d.ncols * (long long)sizeof(T) < (1LL << 31);
   for (int q = 0; q < c->nblock; ++q) {
     const int blk = transT ? q : c->nblock - 1 - q;
-    if (nrhs <= 16) {   // one 16-column tile per matrix
-      k_qr_wy64<T, 16><<<ceil_div(N, 8) * 8, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, 1, L.F.p,
-                                                             c->f_off.p, c->f_ld.p, cnR, 0, transT);
-    } else {
-      const int ntile = ceil_div(nrhs, kBC);
-      k_qr_wy64<T><<<ceil_div(N, 8) * 8 * ntile, kBlock, 0, s>>>(desc, A, Tbig, blk * kBB, blk, c->nblock, N, ntile,
-                                                                 L.F.p, c->f_off.p, c->f_ld.p, cnR, 0, transT);
-    }
+    const int ntile = nrhs <= 16 ? 1 : ceil_div(nrhs, kBC);
+    const dim3 grid(ceil_div(N, 8) * 8 * ntile);
+    auto args = std::make_tuple(desc, A, Tbig, blk * kBB, blk, c->nblock, N, ntile, L.F.p, (const long long*)c->f_off.p,
+                                (const int*)c->f_ld.p, cnR, 0, transT);
+    auto launch = [&](auto kern) {
+      std::apply([&](auto... a) { kern<<<grid, kBlock, 0, s>>>(a...); }, args);
+    };
+    if (nrhs <= 16)   // one 16-column tile per matrix
+      off32 ? launch(k_qr_wy64<T, 16, true>) : launch(k_qr_wy64<T, 16>);
+    else
+      off32 ? launch(k_qr_wy64<T, kBC, true>) : launch(k_qr_wy64<T>);
     HIPCHK(hipGetLastError());
   }
 }

@@ -497,8 +497,12 @@ __global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__
 // matrix land on the same XCD (workgroup id mod 8) and share its L2 for V.
 // BC = 64 for the factorisation's trailing updates; BC = 16 applies Q or Q^T
 // to up to 16 right-hand sides without the products of 48 empty columns.
-template <typename T, int BC = kBC>
-__global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ desc, const T* __restrict__ A,
+// Off32: every element of a matrix and of its C block lies within 2^31 bytes
+// of the block's start (checked by the caller), so addresses are a uniform
+// base plus a 32-bit byte offset (fewer registers than 64-bit addresses per
+// column).
+template <typename T, int BC = kBC, bool Off32 = false>
+__global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                     const T* __restrict__ Tbig, int kb, int blk, int nblock,
                                                     int nmat, int ntile, T* __restrict__ C,
                                                     const long long* __restrict__ coff, const int* __restrict__ ldc,
@@ -521,6 +525,28 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   const int L = ldc[b];
   const T* Am = A + d.off;
   T* Cm = C + coff[b];
+  // element (row, col) of the matrix (column-major, leading dimension ld)
+  // and of the C block (leading dimension L)
+  auto aref = [&](int col, int row) -> const T& {
+    if constexpr (Off32)
+      return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(Am) +
+                                         (unsigned)((col * d.ld + row) * (int)sizeof(T)));
+    else
+      return Am[(long long)col * d.ld + row];
+  };
+  auto cref = [&](int col, int row) -> T& {
+    if constexpr (Off32)
+      return *reinterpret_cast<T*>(reinterpret_cast<char*>(Cm) + (unsigned)((col * L + row) * (int)sizeof(T)));
+    else
+      return Cm[(long long)col * L + row];
+  };
+  // V(row, j) of the block: 0 above the diagonal, 1 on it, stored below it
+  auto vref = [&](int row, int j) -> T {
+    const int rr = row - kb;
+    if (row >= d.m || rr < j) return T(0);
+    if (rr == j) return T(1);
+    return aref(kb + j, row);
+  };
   __shared__ T Vs[64][kBB + 1];      // V chunk, later T
   __shared__ T Cs[64][BC + 1];       // C chunk, later W
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -533,13 +559,13 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
   for (int u = 0; u < 16; ++u) {
     const int e = threadIdx.x + u * kBlock;
     const int row = kb + e % 64, c = e / 64;
-    vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+    vv[u] = c < bw ? vref(row, c) : T(0);
   }
 #pragma unroll
   for (int u = 0; u < CPT; ++u) {
     const int e = threadIdx.x + u * kBlock;
     const int row = kb + e % 64, c = e / 64;
-    cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+    cc[u] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
   }
   for (int r0 = kb; r0 < d.m;) {
     const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
@@ -559,13 +585,13 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
       for (int u = 0; u < 16; ++u) {
         const int e = threadIdx.x + u * kBlock;
         const int row = rn + e % 64, c = e / 64;
-        vv[u] = c < bw ? v_elem(Am, d.ld, d.m, kb, row, c) : T(0);
+        vv[u] = c < bw ? vref(row, c) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
         const int e = threadIdx.x + u * kBlock;
         const int row = rn + e % 64, c = e / 64;
-        cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+        cc[u] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
       }
     }
 #pragma unroll 4
@@ -621,18 +647,21 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * t + Mfma<T>::drow(lane, v);
-        cn_[4 * t + v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+        cn_[4 * t + v] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
       }
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int jj = ks * 4 + (lane >> 4);
-      bn_[ks] = jj < bw ? v_elem(Am, d.ld, d.m, kb, row, jj) : T(0);
+      bn_[ks] = jj < bw ? vref(row, jj) : T(0);
     }
   };
   auto next_rb = [&](int r) { return skip_band(r - wv * 16 + kWaves * 16, kb + kBB, d.zhi) + wv * 16; };
   int rb = kb + wv * 16;
   if (rb < d.m) load_rows(rb);
   for (; rb < d.m; rb = next_rb(rb)) {
+    // W is read from LDS in every row block rather than held in registers
+    // across the loop (64 doubles per lane), which keeps two waves per SIMD
+    asm volatile("" ::: "memory");
     const int row = rb + (lane & 15);
     v4 cacc[NT];
     T bv[16];
@@ -654,7 +683,7 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy64(const QRDesc* __restrict__ d
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * t + Mfma<T>::drow(lane, v);
-        if (row < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + row] = cacc[t][v];
+        if (row < d.m && c < ncol) cref(cbeg + c, row) = cacc[t][v];
       }
   }
 }
