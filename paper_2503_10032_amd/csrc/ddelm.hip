@@ -1231,8 +1231,13 @@ void qr_all(ddelm_ctx c, const QRSet<T>& q) {
                              c->npanel);
         const int c0 = k + std::min(kNB, M - k);
         if (c0 < kb + bw) {
-          k_qr_wy<T><<<dim3(nmat, ceil_div(kb + bw - c0, kUC)), kBlock, 0, s>>>(
-              q.desc, q.A, q.Tbuf->p, k, p, c->npanel, q.A, q.coff, q.ldc, cnb, c0, 1);
+          const dim3 grid(nmat, ceil_div(kb + bw - c0, kUC));
+          if (off32)
+            k_qr_wy<T, true><<<grid, kBlock, 0, s>>>(q.desc, q.A, q.Tbuf->p, k, p, c->npanel, q.A, q.coff, q.ldc,
+                                                     cnb, c0, 1);
+          else
+            k_qr_wy<T><<<grid, kBlock, 0, s>>>(q.desc, q.A, q.Tbuf->p, k, p, c->npanel, q.A, q.coff, q.ldc, cnb, c0,
+                                               1);
           HIPCHK(hipGetLastError());
         }
       }

@@ -56,6 +56,15 @@ __device__ __forceinline__ T v_elem(const T* Am, int ld, int m, int k, int row, 
 // leaves those rows unchanged, so row loops that start at k jump from the
 // band's first row to zhi.  Rows at or past zhi are left alone.
 __device__ __forceinline__ int skip_band(int r, int kw, int zhi) { return (r >= kw && r < zhi) ? zhi : r; }
+
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full __syncthreads waits for them as well).
+// For loops whose threads exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 // Row of panel-local index l (l = 0, 1, ...) for the panel of columns
 // [k, k + kNB): the panel's own rows first, then the rows from zhi on.
 template <int NB>
@@ -249,7 +258,8 @@ __global__ void __launch_bounds__(NT) k_qr_panel16(const QRDesc* __restrict__ de
 // transT = 1 applies Q^T (I - V T^T V^T); transT = 0 applies Q (I - V T V^T).
 constexpr int kUC = 32;   // columns per workgroup
 
-template <typename T>
+// Off32: as for k_qr_wy64 below (32-bit byte offsets from the matrix start).
+template <typename T, bool Off32 = false>
 __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                   const T* __restrict__ Tbuf, int k, int panel, int npanel,
                                                   T* __restrict__ C, const long long* __restrict__ coff,
@@ -265,6 +275,20 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
   const int L = ldc[blockIdx.x];
   const T* Am = A + d.off;
   T* Cm = C + coff[blockIdx.x];
+  // element (row, col) of the matrix (leading dimension ld) and of C (L)
+  auto aref = [&](int col, int row) -> const T& {
+    if constexpr (Off32)
+      return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(Am) +
+                                         (unsigned)((col * d.ld + row) * (int)sizeof(T)));
+    else
+      return Am[(long long)col * d.ld + row];
+  };
+  auto cref = [&](int col, int row) -> T& {
+    if constexpr (Off32)
+      return *reinterpret_cast<T*>(reinterpret_cast<char*>(Cm) + (unsigned)((col * L + row) * (int)sizeof(T)));
+    else
+      return Cm[(long long)col * L + row];
+  };
   __shared__ T Vs[64][kNB + 1];
   __shared__ T Cs[64][kUC + 1];
   __shared__ T Wp[kWaves][kNB][kUC + 1];
@@ -272,39 +296,44 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const T* Tin = Tbuf + ((long long)blockIdx.x * npanel + panel) * kNB * kNB;
   for (int e = threadIdx.x; e < kNB * kNB; e += kBlock) Ts[e / kNB][e % kNB] = Tin[e];
-  // ---- W = V^T C over rows k..m-1, 64-row chunks staged in LDS; the next
-  //      chunk's loads (4 V and 8 C elements per thread) are in flight during
-  //      this chunk's products
+  // ---- W = V^T C over rows k..m-1, 64-row chunks staged in LDS; the loads
+  //      of the next two chunks (4 V and 8 C elements per thread each, in
+  //      two register sets used in turn) are in flight during this chunk's
+  //      products, and the barriers order the LDS accesses only
   v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  T vv[4], cc[8];
-  auto load_chunk = [&](int r0) {
+  // every load reads an element inside the matrix (indices clamped) and the
+  // value (0 or 1 above and on the diagonal, 0 past the last row or column)
+  // is selected when the chunk is stored to LDS: straight-line loads whose
+  // waits count only the chunk being stored
+  auto load_chunk = [&](int r0, T (&vv)[4], T (&cc)[8]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = threadIdx.x + u * kBlock;
-      vv[u] = v_elem(Am, d.ld, d.m, k, r0 + e % 64, e / 64);
+      vv[u] = aref(k + e / 64, min(r0 + e % 64, d.m - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      cc[u] = cref(cbeg + min(e / 64, ncol - 1), min(r0 + e % 64, d.m - 1));
+    }
+  };
+  // chunk at r0 held in (vv, cc): to LDS, its products; then (vv, cc) takes
+  // the chunk at rl
+  auto chunk = [&](int r0, T (&vv)[4], T (&cc)[8], int rl) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = threadIdx.x + u * kBlock;
+      const int row = r0 + e % 64, j = e / 64, rr = row - k;
+      Vs[e % 64][j] = (row >= d.m || rr < j) ? T(0) : (rr == j ? T(1) : vv[u]);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = threadIdx.x + u * kBlock;
       const int c = e / 64, row = r0 + e % 64;
-      cc[u] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+      Cs[e % 64][c] = (row < d.m && c < ncol) ? cc[u] : T(0);
     }
-  };
-  load_chunk(k);
-  for (int r0 = k; r0 < d.m;) {
-    const int rn = skip_band(r0 + 64, k + kNB, d.zhi);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      Vs[e % 64][e / 64] = vv[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      Cs[e % 64][e / 64] = cc[u];
-    }
-    __syncthreads();
-    if (rn < d.m) load_chunk(rn);
+    lds_barrier();
+    load_chunk(min(rl, d.m), vv, cc);   // past the end: unused, no branch
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int rr = wv * 16 + ks * 4 + (lane >> 4);
@@ -312,8 +341,23 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
       acc0 = Mfma<T>::mma(av, Cs[rr][lane & 15], acc0);
       acc1 = Mfma<T>::mma(av, Cs[rr][16 + (lane & 15)], acc1);
     }
-    __syncthreads();
-    r0 = rn;
+    lds_barrier();
+  };
+  auto next_chunk = [&](int r) { return r < d.m ? skip_band(r + 64, k + kNB, d.zhi) : d.m; };
+  {
+    T va[4], ca[8], vb[4], cb[8];
+    int r0 = k, r1 = next_chunk(k);
+    load_chunk(r0, va, ca);
+    load_chunk(r1, vb, cb);
+    while (r0 < d.m) {
+      const int r2 = next_chunk(r1);
+      chunk(r0, va, ca, r2);
+      if (r1 >= d.m) break;
+      const int r3 = next_chunk(r2);
+      chunk(r1, vb, cb, r3);
+      r0 = r2;
+      r1 = r3;
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -339,36 +383,38 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
     Wp[1][i][c] = -s;
   }
   __syncthreads();
-  // ---- C^T <- C^T + Wn^T V^T for 16-row blocks (rows along the lanes); the
-  //      next block's loads are issued before this block's products
-  T cn_[8], bn_[4];
-  auto load_rows = [&](int rb) {
-    const int row = rb + (lane & 15);
+  // ---- C^T <- C^T + Wn^T V^T for 16-row blocks (rows along the lanes); two
+  //      register sets used in turn keep the loads of the next two blocks in
+  //      flight during this block's products (clamped indices, values
+  //      selected at use, as above)
+  auto load_rows = [&](int rb, T (&cn)[8], T (&bn)[4]) {
+    const int row = min(rb + (lane & 15), d.m - 1);
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int c = cg * 16 + Mfma<T>::drow(lane, v);
-        cn_[4 * cg + v] = (row < d.m && c < ncol) ? Cm[(long long)(cbeg + c) * L + row] : T(0);
+        const int c = min(cg * 16 + Mfma<T>::drow(lane, v), ncol - 1);
+        cn[4 * cg + v] = cref(cbeg + c, row);
       }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) bn_[ks] = v_elem(Am, d.ld, d.m, k, row, ks * 4 + (lane >> 4));
+    for (int ks = 0; ks < 4; ++ks) bn[ks] = aref(k + ks * 4 + (lane >> 4), row);
   };
-  // 64-row groups of the four waves, the band skipped between groups
-  auto next_rb = [&](int r) { return skip_band(r - wv * 16 + kWaves * 16, k + kNB, d.zhi) + wv * 16; };
-  int rb = k + wv * 16;
-  if (rb < d.m) load_rows(rb);
-  for (; rb < d.m; rb = next_rb(rb)) {
-    const int row = rb + (lane & 15);
+  // block at rb held in (cn, bn): its products and stores; then (cn, bn)
+  // takes the block at rl
+  auto block = [&](int rb, T (&cn)[8], T (&bn)[4], int rl) {
+    const int row = rb + (lane & 15), rr = row - k;
     v4 acc[2];
     T bv[4];
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[cg][v] = cn_[4 * cg + v];
+      for (int v = 0; v < 4; ++v) acc[cg][v] = cn[4 * cg + v];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) bv[ks] = bn_[ks];
-    if (next_rb(rb) < d.m) load_rows(next_rb(rb));
+    for (int ks = 0; ks < 4; ++ks) {
+      const int j = ks * 4 + (lane >> 4);
+      bv[ks] = (row >= d.m || rr < j) ? T(0) : (rr == j ? T(1) : bn[ks]);
+    }
+    load_rows(min(rl, d.m), cn, bn);
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
@@ -381,8 +427,27 @@ __global__ void __launch_bounds__(kBlock) k_qr_wy(const QRDesc* __restrict__ des
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = cg * 16 + Mfma<T>::drow(lane, v);
-        if (row < d.m && c < ncol) Cm[(long long)(cbeg + c) * L + row] = acc[cg][v];
+        if (row < d.m && c < ncol) cref(cbeg + c, row) = acc[cg][v];
       }
+  };
+  // 64-row groups of the four waves, the band skipped between groups
+  auto next_rb = [&](int r) {
+    return r < d.m ? skip_band(r - wv * 16 + kWaves * 16, k + kNB, d.zhi) + wv * 16 : d.m;
+  };
+  {
+    T ca[8], va[4], cb[8], vb[4];
+    int r0 = k + wv * 16, r1 = next_rb(r0);
+    load_rows(min(r0, d.m), ca, va);
+    load_rows(min(r1, d.m), cb, vb);
+    while (r0 < d.m) {
+      const int r2 = next_rb(r1);
+      block(r0, ca, va, r2);
+      if (r1 >= d.m) break;
+      const int r3 = next_rb(r2);
+      block(r1, cb, vb, r3);
+      r0 = r2;
+      r1 = r3;
+    }
   }
 }
 
@@ -540,13 +605,6 @@ __global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc*
     else
       return Cm[(long long)col * L + row];
   };
-  // V(row, j) of the block: 0 above the diagonal, 1 on it, stored below it
-  auto vref = [&](int row, int j) -> T {
-    const int rr = row - kb;
-    if (row >= d.m || rr < j) return T(0);
-    if (rr == j) return T(1);
-    return aref(kb + j, row);
-  };
   __shared__ T Vs[64][kBB + 1];      // V chunk, later T
   __shared__ T Cs[64][BC + 1];       // C chunk, later W
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -554,46 +612,43 @@ __global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc*
   v4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4{0, 0, 0, 0};
+  // Loads read elements inside the matrix (indices clamped) with no
+  // branches; the values (0 or 1 above and on the diagonal of V, 0 past the
+  // last row or column) are selected when a chunk is stored to LDS.  The
+  // barriers of this loop order LDS accesses only, so the next chunk's loads
+  // stay in flight across them.
   T vv[16], cc[CPT];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    const int row = kb + e % 64, c = e / 64;
-    vv[u] = c < bw ? vref(row, c) : T(0);
-  }
-#pragma unroll
-  for (int u = 0; u < CPT; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    const int row = kb + e % 64, c = e / 64;
-    cc[u] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
-  }
-  for (int r0 = kb; r0 < d.m;) {
-    const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
+  auto load_chunk = [&](int r0) {
+    const int row = min(r0 + (int)threadIdx.x % 64, d.m - 1);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      Vs[e % 64][e / 64] = vv[u];
+      const int c = (threadIdx.x + u * kBlock) / 64;
+      vv[u] = aref(kb + min(c, bw - 1), row);
     }
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      Cs[e % 64][e / 64] = cc[u];
+      const int c = (threadIdx.x + u * kBlock) / 64;
+      cc[u] = cref(cbeg + min(c, ncol - 1), row);
     }
-    __syncthreads();
-    if (rn < d.m) {       // next chunk's loads in flight during this chunk's products
+  };
+  load_chunk(kb);
+  for (int r0 = kb; r0 < d.m;) {
+    const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
+    {
+      const int row = r0 + threadIdx.x % 64, rr = row - kb;
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const int e = threadIdx.x + u * kBlock;
-        const int row = rn + e % 64, c = e / 64;
-        vv[u] = c < bw ? vref(row, c) : T(0);
+        const int e = threadIdx.x + u * kBlock, c = e / 64;
+        Vs[e % 64][c] = (c >= bw || row >= d.m || rr < c) ? T(0) : (rr == c ? T(1) : vv[u]);
       }
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
-        const int e = threadIdx.x + u * kBlock;
-        const int row = rn + e % 64, c = e / 64;
-        cc[u] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
+        const int e = threadIdx.x + u * kBlock, c = e / 64;
+        Cs[e % 64][c] = (row < d.m && c < ncol) ? cc[u] : T(0);
       }
     }
+    lds_barrier();
+    load_chunk(min(rn, d.m));   // next chunk in flight during the products (past the end: unused)
 #pragma unroll 4
     for (int ks = 0; ks < 16; ++ks) {
       const int rr = ks * 4 + (lane >> 4);
@@ -601,7 +656,7 @@ __global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc*
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::mma(av, Cs[rr][16 * t + (lane & 15)], acc[t]);
     }
-    __syncthreads();
+    lds_barrier();
     r0 = rn;
   }
   // W into Cs, T into Vs
@@ -640,19 +695,20 @@ __global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc*
   // ---- C <- C + V W for 16-row blocks (rows along the lanes)
   // loads of the next 16-row block are issued before the products of this one
   T cn_[4 * NT], bn_[16];
+  // (clamped indices, values selected at use, as above)
   auto load_rows = [&](int rb) {
-    const int row = rb + (lane & 15);
+    const int row = min(rb + (lane & 15), d.m - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int c = 16 * t + Mfma<T>::drow(lane, v);
-        cn_[4 * t + v] = (row < d.m && c < ncol) ? cref(cbeg + c, row) : T(0);
+        cn_[4 * t + v] = cref(cbeg + min(c, ncol - 1), row);
       }
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int jj = ks * 4 + (lane >> 4);
-      bn_[ks] = jj < bw ? vref(row, jj) : T(0);
+      bn_[ks] = aref(kb + min(jj, bw - 1), row);
     }
   };
   auto next_rb = [&](int r) { return skip_band(r - wv * 16 + kWaves * 16, kb + kBB, d.zhi) + wv * 16; };
@@ -669,9 +725,15 @@ __global__ void __launch_bounds__(kBlock, Off32 ? 2 : 1) k_qr_wy64(const QRDesc*
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) cacc[t][v] = cn_[4 * t + v];
+    {
+      const int rr = row - kb;
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) bv[ks] = bn_[ks];
-    if (next_rb(rb) < d.m) load_rows(next_rb(rb));
+      for (int ks = 0; ks < 16; ++ks) {
+        const int jj = ks * 4 + (lane >> 4);
+        bv[ks] = (jj >= bw || row >= d.m || rr < jj) ? T(0) : (rr == jj ? T(1) : bn_[ks]);
+      }
+    }
+    load_rows(min(next_rb(rb), d.m));
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int jj = ks * 4 + (lane >> 4);
