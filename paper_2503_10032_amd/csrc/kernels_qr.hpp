@@ -490,48 +490,57 @@ __global__ void __launch_bounds__(kBlock) k_qr_tmerge(const QRDesc* __restrict__
     const int p = kb / kNB + pp;
     Ts[pp * kNB + i][pp * kNB + j] = (double)Tbuf[((long long)blockIdx.x * npanel + p) * kNB * kNB + i * kNB + j];
   }
-  // G = V^T V over the rows of the block's reflectors on f64 MFMA: wave wv
-  // forms rows 16 wv .. 16 wv + 15 of G (4 tiles of 16 columns)
+  // G = V^T V over the rows of the block's reflectors on f64 MFMA.  The
+  // merge reads only the blocks G(p, q), p < q, of 16 x 16 (panels p and q):
+  // six tiles, two for waves 0 and 1 and one for waves 2 and 3.  Loads read
+  // clamped in-matrix addresses with no branches and the reflector values
+  // are selected when a chunk is stored to LDS; the loop's barriers order
+  // LDS accesses only, so the next chunk's loads stay in flight.
   typedef Mfma<double>::v4 v4d;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v4d acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = v4d{0, 0, 0, 0};
-  double vv[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, kb + e % 64, e / 64) : 0.0;
-  }
-  for (int r0 = kb; r0 < d.m;) {
-    const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      Vc[e % 64][e / 64] = vv[u];
-    }
-    __syncthreads();
-    if (rn < d.m) {       // next chunk's loads in flight during this chunk's products
+  const int tp0 = wv < 2 ? 0 : wv - 1, tq0 = wv == 0 ? 1 : 3;   // (0,1) (0,3) (1,3) (2,3)
+  const int tp1 = wv, tq1 = 2;                                  // (0,2) (1,2) for waves 0, 1
+  const bool two_tiles = wv < 2;
+  v4d acc0 = v4d{0, 0, 0, 0}, acc1 = v4d{0, 0, 0, 0};
+  if (npb > 1) {
+    T vv[16];
+    auto load_chunk = [&](int r0) {
+      const int row = min(r0 + (int)threadIdx.x % 64, d.m - 1);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const int e = threadIdx.x + u * kBlock;
-        vv[u] = e / 64 < bw ? (double)v_elem(Am, d.ld, d.m, kb, rn + e % 64, e / 64) : 0.0;
+        const int c = (threadIdx.x + u * kBlock) / 64;
+        vv[u] = Am[(long long)(kb + min(c, bw - 1)) * d.ld + row];
       }
-    }
+    };
+    load_chunk(kb);
+    for (int r0 = kb; r0 < d.m;) {
+      const int rn = skip_band(r0 + 64, kb + kBB, d.zhi);
+      {
+        const int row = r0 + threadIdx.x % 64, rr = row - kb;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = threadIdx.x + u * kBlock, c = e / 64;
+          Vc[e % 64][c] = (c >= bw || row >= d.m || rr < c) ? 0.0 : (rr == c ? 1.0 : (double)vv[u]);
+        }
+      }
+      lds_barrier();
+      load_chunk(min(rn, d.m));   // next chunk in flight during the products (past the end: unused)
 #pragma unroll 4
-    for (int ks = 0; ks < 16; ++ks) {
-      const int rr = ks * 4 + (lane >> 4);
-      const double av = Vc[rr][16 * wv + (lane & 15)];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = Mfma<double>::mma(av, Vc[rr][16 * t + (lane & 15)], acc[t]);
+      for (int ks = 0; ks < 16; ++ks) {
+        const int rr = ks * 4 + (lane >> 4);
+        acc0 = Mfma<double>::mma(Vc[rr][16 * tp0 + (lane & 15)], Vc[rr][16 * tq0 + (lane & 15)], acc0);
+        if (two_tiles)
+          acc1 = Mfma<double>::mma(Vc[rr][16 * tp1 + (lane & 15)], Vc[rr][16 * tq1 + (lane & 15)], acc1);
+      }
+      lds_barrier();
+      r0 = rn;
     }
-    __syncthreads();
-    r0 = rn;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Gs[16 * tp0 + Mfma<double>::drow(lane, v)][16 * tq0 + (lane & 15)] = acc0[v];
+      if (two_tiles) Gs[16 * tp1 + Mfma<double>::drow(lane, v)][16 * tq1 + (lane & 15)] = acc1[v];
+    }
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) Gs[16 * wv + Mfma<double>::drow(lane, v)][16 * t + (lane & 15)] = acc[t][v];
   __syncthreads();
   // merge: T(0:n0, n0:n0+16) = -T(0:n0, 0:n0) G(0:n0, n0:n0+16) T(n0:n0+16, n0:n0+16)
   for (int q = 1; q < npb; ++q) {
