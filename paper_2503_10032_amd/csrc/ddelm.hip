@@ -1503,8 +1503,9 @@ void factor_impl(ddelm_ctx c) {
       if (smt > 65536)
         HIPCHK(hipFuncSetAttribute((const void*)k_trsm<T, kTRSMC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)smt));
-      k_trsm<T, kTRSMC><<<dim3(nmat, ceil_div(maxx, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.qrA.p, dxo,
-                                                                               dld, dxn, 0);
+      const int nt = ceil_div(maxx, kTRSMC);
+      k_trsm<T, kTRSMC><<<ceil_div(nmat, 8) * 8 * nt, kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.qrA.p, dxo, dld, dxn,
+                                                                       0, nmat, nt);
       HIPCHK(hipGetLastError());
     }
   }
@@ -1842,8 +1843,9 @@ CoreOut solve_core(ddelm_ctx c, int nrhs, const double* fGP, const double* fGD, 
   {
     const size_t smt = (size_t)M * kTRSMC * sizeof(T);
     const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
-    k_trsm<T, kTRSMC><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p,
-                                                                   cnM, 0);
+    const int nt = ceil_div(nrhs, kTRSMC);
+    k_trsm<T, kTRSMC><<<ceil_div(N, 8) * 8 * nt, kBlock, smt, s>>>(c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p,
+                                                                   c->f_ld.p, cnM, 0, N, nt);
     HIPCHK(hipGetLastError());
 
     with_rhs_group(PM, [&](auto kp) {
@@ -2047,8 +2049,9 @@ CoreOut adjoint_core(ddelm_ctx c, int nrhs, const double* cbar, const double* mu
                                           c->cg_x.p, c->sumD, c->offm_d.p, c->summ, L.F.p, c->adj_pbar.p, sumG);
   HIPCHK(hipGetLastError());
   const int* cnM = c->arena.put(std::vector<int>(N, nrhs), s);
-  k_trsm<T, kTRSMC><<<dim3(N, ceil_div(nrhs, kTRSMC)), kBlock, (size_t)M * kTRSMC * sizeof(T), s>>>(
-      c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p, cnM, 1);
+  const int nt = ceil_div(nrhs, kTRSMC);
+  k_trsm<T, kTRSMC><<<ceil_div(N, 8) * 8 * nt, kBlock, (size_t)M * kTRSMC * sizeof(T), s>>>(
+      c->qrdesc.p, L.qrA.p, L.F.p, c->f_off.p, c->f_ld.p, cnM, 1, N, nt);
   k_adj_alpha<T><<<gl, kBlock, smG, s>>>(M, c->sizes_dev.p, c->pi_off.p, c->dl_off.p, c->offQG_d.p, L.QG.p,
                                          c->adj_pbar.p, sumG, c->offm_d.p, c->summ, L.F.p);
   HIPCHK(hipGetLastError());

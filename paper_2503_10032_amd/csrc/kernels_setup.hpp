@@ -211,18 +211,25 @@ template <typename T, int kTRSMC>
 __global__ void __launch_bounds__(kBlock, 4) k_trsm(const QRDesc* __restrict__ desc, const T* __restrict__ A,
                                                  T* __restrict__ X, const long long* __restrict__ xoff,
                                                  const int* __restrict__ ldx, const int* __restrict__ xn,
-                                                 int trans) {
+                                                 int trans, int nmat, int ntile) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);          // [kTRSMC][n]: a column per RHS, rows along the lanes
-  const QRDesc d = desc[blockIdx.x];
+  // 1-D grid over (matrix, column tile), arranged so that all tiles of one
+  // matrix land on the same XCD (workgroup id mod 8) close together in
+  // time: R is read from memory once and then from that XCD's L2
+  const int id = blockIdx.x;
+  const int b = (id % 8) + 8 * ((id / 8) / ntile);
+  const int tile = (id / 8) % ntile;
+  if (b >= nmat) return;
+  const QRDesc d = desc[b];
   const int n = d.nrefl;
-  const int cbeg = blockIdx.y * kTRSMC;
-  const int ctot = xn[blockIdx.x];
+  const int cbeg = tile * kTRSMC;
+  const int ctot = xn[b];
   if (cbeg >= ctot) return;
   const int nc = min(kTRSMC, ctot - cbeg);
   const T* R = A + d.off;
-  T* Xm = X + xoff[blockIdx.x];
-  const int L = ldx[blockIdx.x];
+  T* Xm = X + xoff[b];
+  const int L = ldx[b];
   {
     constexpr int kU = 8;      // loads issued together per thread
     for (int e0 = threadIdx.x; e0 < n * kTRSMC; e0 += kU * kBlock) {
