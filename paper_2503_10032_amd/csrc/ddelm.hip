@@ -649,7 +649,7 @@ void assemble_features(ddelm_ctx c, const RowSetDev& rs, int max_rows, T* out, c
   a.rho_int = c->has_rho ? c->rho_int.p : nullptr;
   a.rho_iface = c->has_rho ? c->rho_iface.p : nullptr;
   a.first_row = first_row;
-  dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, 4), nsub);
+  dim3 grid(ceil_div(max_rows, 64), ceil_div(c->M, kWaves * kFeatCols), nsub);
   k_features<T><<<grid, kBlock, 0, c->stream>>>(a, out);
   HIPCHK(hipGetLastError());
   const int l0 = rs.h_long_first[sub0], l1 = rs.h_long_first[sub0 + nsub];

@@ -52,39 +52,61 @@ __device__ __forceinline__ double term_value(const FeatArgs& a, const Term& tm, 
 // lanes of a wave instead of looping over them in one thread.
 constexpr int kLongTerms = 8;
 
+constexpr int kFeatCols = 8;   // neurons per wave in k_features
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a, T* __restrict__ out) {
+  // A wave takes 64 consecutive rows and kFeatCols consecutive neurons: the
+  // row's data (point, coefficient, term range) is read once for all of its
+  // neurons and each neuron's weights are wave-uniform; every element is
+  // computed with the same operations as one element per thread would be.
   const int i = a.sub0 + blockIdx.z;
   const int r = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j0 = (blockIdx.y * kWaves + wv) * kFeatCols;
   const int nrows = a.lead + a.row0[i + 1] - a.row0[i];
-  if (r >= nrows || j >= a.M || (a.first_row && r < a.first_row[i])) return;
+  if (r >= nrows || j0 >= a.M || (a.first_row && r < a.first_row[i])) return;
+  const int j1 = min(j0 + kFeatCols, a.M);
   const double cx = a.geom[4 * i], cy = a.geom[4 * i + 1], hx = a.geom[4 * i + 2], hy = a.geom[4 * i + 3];
-  const double w0 = a.W[((size_t)i * a.M + j) * 2], w1 = a.W[((size_t)i * a.M + j) * 2 + 1];
-  const double bj = a.bias[(size_t)i * a.M + j];
-  const double gx = w0 / hx, gy = w1 / hy;
-  const double lap = gx * gx + gy * gy;
-  double acc = 0.0;
+  T* o = out + a.off[i] + (long long)j0 * a.ld[i] + r;
+  const long long ldo = a.ld[i];
+  const double* Wi = a.W + (size_t)i * a.M * 2;
+  const double* bi = a.bias + (size_t)i * a.M;
   if (r < a.lead) {            // interior row: -Laplace(phi) at the interior point
     const double px = a.xint[((size_t)i * a.lead + r) * 2], py = a.xint[((size_t)i * a.lead + r) * 2 + 1];
-    const double t = tanh_fast(w0 * ((px - cx) / hx) + w1 * ((py - cy) / hy) + bj);
-    const double dt = 1.0 - t * t;
-    double v = 2.0 * t * dt * lap;
+    const double xs = (px - cx) / hx, ys = (py - cy) / hy;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
     if (a.rho_int) {
       const double* q = a.rho_int + ((size_t)i * a.lead + r) * 3;
-      v = q[0] * v - dt * (q[1] * gx + q[2] * gy);
+      q0 = q[0]; q1 = q[1]; q2 = q[2];
     }
-    out[a.off[i] + (long long)j * a.ld[i] + r] = (T)v;
+    for (int j = j0; j < j1; ++j, o += ldo) {
+      const double w0 = Wi[2 * j], w1 = Wi[2 * j + 1], bj = bi[j];
+      const double gx = w0 / hx, gy = w1 / hy;
+      const double lap = gx * gx + gy * gy;
+      const double t = tanh_fast(w0 * xs + w1 * ys + bj);
+      const double dt = 1.0 - t * t;
+      double v = 2.0 * t * dt * lap;
+      if (a.rho_int) v = q0 * v - dt * (q1 * gx + q2 * gy);
+      *o = (T)v;
+    }
     return;
   }
   const int row = a.row0[i] + r - a.lead;
-  if (a.ptr[row + 1] - a.ptr[row] > kLongTerms) return;
-  for (int q = a.ptr[row]; q < a.ptr[row + 1]; ++q) {
-    const Term tm = a.terms[q];
-    const double t = tanh_fast(w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj);
-    acc += tm.wgt * term_value(a, tm, t, gx, gy, lap);
+  const int q0 = a.ptr[row], q1 = a.ptr[row + 1];
+  if (q1 - q0 > kLongTerms) return;
+  for (int j = j0; j < j1; ++j, o += ldo) {
+    const double w0 = Wi[2 * j], w1 = Wi[2 * j + 1], bj = bi[j];
+    const double gx = w0 / hx, gy = w1 / hy;
+    const double lap = gx * gx + gy * gy;
+    double acc = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const Term tm = a.terms[q];
+      const double t = tanh_fast(w0 * ((tm.x - cx) / hx) + w1 * ((tm.y - cy) / hy) + bj);
+      acc += tm.wgt * term_value(a, tm, t, gx, gy, lap);
+    }
+    *o = (T)acc;
   }
-  out[a.off[i] + (long long)j * a.ld[i] + r] = (T)acc;
 }
 
 // Rows with many terms: list[k] = (subdomain, local row) for k < nlong (all
