@@ -1451,9 +1451,9 @@ void factor_impl(ddelm_ctx c) {
     std::vector<int> uoff(nmat);
     for (int b = 0; b < nmat; ++b) uoff[b] = b < N ? 0 : c->h_nP[b % N];
     const int* duoff = c->arena.put(uoff, s);
-    long long most = 0;
-    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, (long long)d.ld * d.ncols);
-    k_stage2_assemble<T><<<dim3((unsigned)std::min(ceil_div(most, kBlock), 512), nmat), kBlock, 0, s>>>(
+    int most = 0;   // columns of the widest matrix
+    for (const QRDesc& d : c->h_qrdesc) most = std::max(most, d.ncols);
+    k_stage2_assemble<T><<<dim3((unsigned)std::min(most, 64), nmat), kBlock, 0, s>>>(
         c->qrdesc.p, c->topdesc.p, N, M, duoff, L.topA.p, kbfull.p, L.qrA.p);
     HIPCHK(hipGetLastError());
     kbfull.free();

@@ -163,17 +163,19 @@ __global__ void k_stage2_assemble(const QRDesc* __restrict__ d2, const QRDesc* _
   const int b = blockIdx.y, i = b % N;
   const QRDesc d = d2[b], t = d1[i];
   const T* full = b < N ? top : kbfull;
-  const long long n = (long long)d.ld * d.ncols;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
-    const int row = (int)(e % d.ld), col = (int)(e / d.ld);
-    T v;
-    if (col < M) {
-      if (row < M) v = row <= col ? top[t.off + (long long)col * t.ld + row] : T(0);
-      else v = full[t.off + (long long)col * t.ld + t.m + (row - M)];
-    } else {
-      v = row == M + uoff[b] + (col - M) ? T(1) : T(0);
+  // columns over the workgroups, rows over the threads (no index division)
+  for (int col = blockIdx.x; col < d.ncols; col += gridDim.x) {
+    T* dst = A + d.off + (long long)col * d.ld;
+    for (int row = threadIdx.x; row < d.ld; row += kBlock) {
+      T v;
+      if (col < M) {
+        if (row < M) v = row <= col ? top[t.off + (long long)col * t.ld + row] : T(0);
+        else v = full[t.off + (long long)col * t.ld + t.m + (row - M)];
+      } else {
+        v = row == M + uoff[b] + (col - M) ? T(1) : T(0);
+      }
+      dst[row] = v;
     }
-    A[d.off + e] = v;
   }
 }
 
