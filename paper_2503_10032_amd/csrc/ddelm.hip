@@ -615,10 +615,14 @@ template <typename TS, typename TD>
 void copy_batch(ddelm_ctx c, const std::vector<CopyDesc>& h, const TS* S, TD* D) {
   if (h.empty()) return;
   long long mx = 0;
-  for (auto& cd : h) mx = std::max(mx, (long long)cd.rows * cd.cols);
+  int mc = 0;
+  for (auto& cd : h) {
+    mx = std::max(mx, (long long)cd.rows * cd.cols);
+    mc = std::max(mc, cd.cols);
+  }
   if (mx == 0) return;
   const CopyDesc* d = c->arena.put(h, c->stream);
-  dim3 grid(std::min(ceil_div(mx, kBlock), 1024), (unsigned)h.size());
+  dim3 grid(std::min(mc, 1024), (unsigned)h.size());   // a column per workgroup and step
   k_copy2d<TS, TD><<<grid, kBlock, 0, c->stream>>>(d, S, D);
   HIPCHK(hipGetLastError());
 }

@@ -371,13 +371,13 @@ template <typename TS, typename TD>
 __global__ void __launch_bounds__(kBlock) k_copy2d(const CopyDesc* __restrict__ desc, const TS* __restrict__ S,
                                                    TD* __restrict__ D) {
   const CopyDesc c = desc[blockIdx.y];
-  const long long n = (long long)c.rows * c.cols;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += (long long)gridDim.x * kBlock) {
-    const int r = (int)(e % c.rows), col = (int)(e / c.rows);
-    const TS v = S[c.src + (long long)col * c.lds + r];
-    if (c.trans) D[c.dst + (long long)r * c.ldd + col] = (TD)v;
-    else D[c.dst + (long long)col * c.ldd + r] = (TD)v;
-  }
+  // columns over the workgroups, rows over the threads (no index division)
+  for (int col = blockIdx.x; col < c.cols; col += gridDim.x)
+    for (int r = threadIdx.x; r < c.rows; r += kBlock) {
+      const TS v = S[c.src + (long long)col * c.lds + r];
+      if (c.trans) D[c.dst + (long long)r * c.ldd + col] = (TD)v;
+      else D[c.dst + (long long)col * c.ldd + r] = (TD)v;
+    }
 }
 
 #ifndef DDELM_KERNEL_SUBSET   // plain kernels: defined once, in the unit that launches them
