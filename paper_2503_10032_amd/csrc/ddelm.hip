@@ -592,8 +592,9 @@ void gemm_batch(ddelm_ctx c, const std::vector<GemmDesc>& h, const T* A, const T
   for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
   if (mm == 0 || nn == 0) return;
   const GemmDesc* d = c->arena.put(h, c->stream);
-  dim3 grid(ceil_div(mm, kGT), ceil_div(nn, kGT), (unsigned)h.size());
-  k_gemm_mfma<T, T, T><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  const int nx = ceil_div(mm, kGT), ny = ceil_div(nn, kGT), nmat = (int)h.size();
+  k_gemm_mfma<T, T, T><<<(nmat >= 8 ? ceil_div(nmat, 8) * 8 : nmat) * nx * ny, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta, nx, ny,
+                                                                           nmat);
   HIPCHK(hipGetLastError());
 }
 
@@ -606,8 +607,9 @@ void gemm_batch_mixed(ddelm_ctx c, const std::vector<GemmDesc>& h, const TA* A, 
   for (auto& g : h) { mm = std::max(mm, g.m); nn = std::max(nn, g.n); }
   if (mm == 0 || nn == 0) return;
   const GemmDesc* d = c->arena.put(h, c->stream);
-  dim3 grid(ceil_div(mm, kGT), ceil_div(nn, kGT), (unsigned)h.size());
-  k_gemm_mfma<TA, TB, TC><<<grid, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta);
+  const int nx = ceil_div(mm, kGT), ny = ceil_div(nn, kGT), nmat = (int)h.size();
+  k_gemm_mfma<TA, TB, TC><<<(nmat >= 8 ? ceil_div(nmat, 8) * 8 : nmat) * nx * ny, kBlock, 0, c->stream>>>(d, A, B, C, transA, alpha, beta, nx, ny,
+                                                                           nmat);
   HIPCHK(hipGetLastError());
 }
 

@@ -771,10 +771,20 @@ constexpr int kGT = 32;
 template <typename TA, typename TB, typename TC>
 __global__ void __launch_bounds__(kBlock) k_gemm_mfma(const GemmDesc* __restrict__ desc, const TA* __restrict__ A,
                                                       const TB* __restrict__ B, TC* __restrict__ C, int transA,
-                                                      double alpha, double beta) {
+                                                      double alpha, double beta, int nx, int ny, int nmat) {
   typedef Mfma<double>::v4 v4;
-  const GemmDesc g = desc[blockIdx.z];
-  const int row0 = blockIdx.x * kGT, col0 = blockIdx.y * kGT;
+  // 1-D grid over (matrix, tile).  With 8 or more products, all tiles of
+  // one product land on the same XCD (workgroup id mod 8) close together in
+  // time and share its L2 for their row and column strips; fewer products
+  // spread their tiles over all XCDs.
+  const int ntl = nx * ny;
+  const int id = blockIdx.x;
+  const bool grouped = nmat >= 8;
+  const int b = grouped ? (id % 8) + 8 * ((id / 8) / ntl) : id / ntl;
+  const int t = grouped ? (id / 8) % ntl : id % ntl;
+  if (b >= nmat) return;
+  const GemmDesc g = desc[b];
+  const int row0 = (t % nx) * kGT, col0 = (t / nx) * kGT;
   if (row0 >= g.m || col0 >= g.n) return;
   __shared__ double As[kGT][kGT + 1];   // As[k][row]
   __shared__ double Bs[kGT][kGT + 1];   // Bs[col][k]
